@@ -1,0 +1,475 @@
+"""Pins of the CPU oracle against facts fixed outside the oracle itself:
+integer arithmetic, closed forms, exact rational arithmetic, IEEE error
+bounds, library conversions and invariants.  Every test here runs on the CPU.
+"""
+import math
+import struct
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import workloads
+
+U64 = 2.0 ** -53
+
+
+def gamma(k, u=U64):
+    return k * u / (1 - k * u)
+
+
+# ---------------------------------------------------------------- GEMV ----
+
+@pytest.mark.parametrize("op", [0, 1])
+@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("m,n", [(1, 1), (3, 5), (17, 64), (65, 33), (128, 257)])
+def test_gemv_integer_exact(orc, op, layout, m, n):
+    """Section 3.1 GEMV definition: on integers in [-8, 8] every partial sum
+    is an exact binary64 integer, so the oracle must equal int64 arithmetic."""
+    A, x, c0 = workloads.gemv_inputs(m, n, seed=102 + m + n, dist="int8", op_t=bool(op))
+    Ai = A.astype(np.int64)
+    ref = c0.astype(np.int64) + (Ai @ x.astype(np.int64) if op == 0 else Ai.T @ x.astype(np.int64))
+    got = orc.gemv(A, x, c0, op=op, layout=layout)
+    assert np.array_equal(got, ref.astype(np.float64))
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_gemv_closed_forms(orc, op):
+    n = 300
+    # A = I gives c0 + x.
+    x = np.arange(1, n + 1, dtype=np.float64) * 0.5
+    c0 = np.linspace(-3, 3, n)
+    assert np.array_equal(orc.gemv(np.eye(n), x, c0, op=op), c0 + x)
+    # All-ones A with x = 1..n adds n(n+1)/2 to every entry.
+    m = 7
+    A = np.ones((m, n)) if op == 0 else np.ones((n, m))
+    got = orc.gemv(A, np.arange(1, n + 1, dtype=np.float64), np.zeros(m), op=op)
+    assert np.all(got == n * (n + 1) / 2)
+    # A_ij = i + j (0-based) with x = 1: row i sums to n*i + n(n-1)/2.
+    ii, jj = np.meshgrid(np.arange(m), np.arange(n), indexing="ij")
+    A = (ii + jj).astype(np.float64)
+    if op == 0:
+        got = orc.gemv(A, np.ones(n), np.zeros(m), op=0)
+        assert np.array_equal(got, n * np.arange(m) + n * (n - 1) / 2)
+    else:
+        got = orc.gemv(A.T.copy(), np.ones(n), np.zeros(m), op=1)
+        assert np.array_equal(got, n * np.arange(m) + n * (n - 1) / 2)
+    # Rank one integer A = u v^T gives u (v . x).
+    u = np.arange(-3, 4, dtype=np.float64)
+    v = np.arange(n, dtype=np.float64) % 5 - 2
+    xx = np.arange(n, dtype=np.float64) % 3 - 1
+    A = np.outer(u, v)
+    if op == 0:
+        assert np.array_equal(orc.gemv(A, xx, np.zeros(7), op=0), u * float(v @ xx))
+    else:
+        assert np.array_equal(orc.gemv(A.T.copy(), xx, np.zeros(7), op=1), u * float(v @ xx))
+
+
+def _rand_wide(rng, shape, e=60):
+    """binary64 values with random signs and exponents in [-e, e]."""
+    return rng.uniform(1, 2, size=shape) * np.exp2(rng.integers(-e, e + 1, size=shape)) * \
+        rng.choice([-1.0, 1.0], size=shape)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_gemv_fraction_bound(orc, seed):
+    """Exact rational reference: every entry within gamma_{K+1}(|c0|+sum|a||x|)."""
+    rng = np.random.default_rng(seed)
+    m, n = rng.integers(1, 7, size=2)
+    A, x, c0 = _rand_wide(rng, (m, n)), _rand_wide(rng, (n,)), _rand_wide(rng, (m,))
+    for op in (0, 1):
+        xx = x if op == 0 else _rand_wide(rng, (m,))
+        cc = c0 if op == 0 else _rand_wide(rng, (n,))
+        got = orc.gemv(A, xx, cc, op=op)
+        M = A if op == 0 else A.T
+        for i in range(M.shape[0]):
+            R = Fraction(cc[i]) + sum(Fraction(M[i, j]) * Fraction(xx[j]) for j in range(M.shape[1]))
+            mag = abs(cc[i]) + sum(abs(M[i, j] * xx[j]) for j in range(M.shape[1]))
+            assert abs(Fraction(got[i]) - R) <= Fraction(gamma(M.shape[1] + 1) * mag * (1 + 1e-12))
+
+
+def test_gemv_single_product_correctly_rounded(orc):
+    """K = 1 and c0 = 0: one rounding, so the result is fl(exact)."""
+    rng = np.random.default_rng(7)
+    A, x = _rand_wide(rng, (50, 1)), _rand_wide(rng, (1,))
+    got = orc.gemv(A, x, np.zeros(50))
+    for i in range(50):
+        assert got[i] == float(Fraction(A[i, 0]) * Fraction(x[0]))
+
+
+def test_gemv_initial_value_added_last(orc):
+    """Section 3.1: the products are summed first and the initial c_i is
+    added at the end.  With c0 = 1 and two products 2^-53 the sum-first order
+    gives 1 + 2^-52; adding c0 first would round twice back to 1."""
+    A = np.array([[1.0, 1.0]])
+    x = np.array([2.0 ** -53, 2.0 ** -53])
+    assert orc.gemv(A, x, np.array([1.0]))[0] == 1.0 + 2.0 ** -52
+    assert orc.gemv(A.T.copy(), x, np.array([1.0]), op=1)[0] == 1.0 + 2.0 ** -52
+
+
+def test_gemv_ascending_order(orc):
+    """Products are added in ascending j from +0.0: [1, 2^-53, 2^-53] sums to
+    1 (each tiny term is lost), while the reverse order would give 1+2^-52."""
+    A = np.array([[1.0, 2.0 ** -53, 2.0 ** -53]])
+    assert orc.gemv(A, np.ones(3), np.zeros(1))[0] == 1.0
+    assert orc.gemv(A[:, ::-1].copy(), np.ones(3), np.zeros(1))[0] == 1.0 + 2.0 ** -52
+
+
+def test_gemv_products_rounded_separately(orc):
+    """The definition names separate elementary multiplications: fl(a*b) is
+    rounded before it is added.  With t = -(1+2^-29) and a*b = 1+2^-29+2^-60
+    the unfused sum is 0 while a fused multiply-add would keep 2^-60."""
+    a = 1.0 + 2.0 ** -30
+    A = np.array([[-(1.0 + 2.0 ** -29), a]])
+    x = np.array([1.0, a])
+    assert orc.gemv(A, x, np.zeros(1))[0] == 0.0
+
+
+def test_gemv_t_matches_j_outer_definition(orc):
+    """The i-outer loop of op T gives the same bits as the j-outer statement."""
+    rng = np.random.default_rng(3)
+    A, x, c0 = rng.standard_normal((23, 19)), rng.standard_normal(23), rng.standard_normal(19)
+    got = orc.gemv(A, x, c0, op=1)
+    for j in range(19):
+        t = 0.0
+        for i in range(23):
+            t = t + float(A[i, j]) * float(x[i])
+        assert got[j] == c0[j] + t
+
+
+def test_gemv_layouts_and_entries(orc):
+    """Row- and column-major storage of the same matrix give the same bits;
+    (row-major, N) on a buffer equals (column-major, T) on the same buffer;
+    padded lda leaves results unchanged; entry sampling equals the full call."""
+    rng = np.random.default_rng(11)
+    m, n = 37, 53
+    A, x, c0 = rng.standard_normal((m, n)), rng.standard_normal(n), rng.standard_normal(m)
+    r = orc.gemv(A, x, c0, layout=0)
+    assert np.array_equal(r, orc.gemv(A, x, c0, layout=1))
+    buf = np.ascontiguousarray(A).reshape(-1)
+    # the buffer read column-major is the n x m matrix A^T; op T of it is A x
+    assert np.array_equal(r, orc.gemv(buf, x, c0, op=1, layout=1, lda=n, shape=(n, m)))
+    P = np.full((m, n + 5), np.nan)
+    P[:, :n] = A
+    assert np.array_equal(r, orc.gemv(P.reshape(-1), x, c0, lda=n + 5, shape=(m, n)))
+    idx = np.array([0, 5, 36])
+    assert np.array_equal(r[idx], orc.gemv_entries(A, x, idx, c0[idx]))
+    rt = orc.gemv(A, rng.standard_normal(m), np.zeros(n), op=1)
+    assert rt.shape == (n,)
+
+
+def test_gemv_empty_and_specials(orc):
+    # n = 0: the empty sum adds +0.0, so c is unchanged (including -0.0 -> -0.0 + 0.0 = +0.0).
+    c0 = np.array([1.5, -2.0])
+    assert np.array_equal(orc.gemv(np.zeros((2, 0)), np.zeros(0), c0), c0)
+    # m = 0
+    assert orc.gemv(np.zeros((0, 3)), np.ones(3), np.zeros(0)).shape == (0,)
+    # 0 * inf = NaN propagates; no skipping of zero x entries.
+    A = np.array([[np.inf, 1.0]])
+    assert np.isnan(orc.gemv(A, np.array([0.0, 1.0]), np.zeros(1))[0])
+    # binary64 subnormals survive (no flush to zero)
+    tiny = 2.0 ** -1070
+    assert orc.gemv(np.array([[tiny]]), np.array([0.5]), np.zeros(1))[0] == tiny / 2
+
+
+# ----------------------------------------------------------------- DOT ----
+
+def test_dot_closed_forms(orc):
+    for n in (1, 2, 100, 1 << 16):
+        v = np.arange(1, n + 1, dtype=np.float64)
+        assert orc.dot(v, v, 0.0) == n * (n + 1) * (2 * n + 1) // 6
+    n = 1 << 20
+    assert orc.dot(np.ones(n), np.ones(n), 5.0) == n + 5.0
+    assert orc.dot(np.zeros(0), np.zeros(0), 3.25) == 3.25
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_dot_fraction_bound(orc, seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(1, 40))
+    x, y, a0 = _rand_wide(rng, (n,)), _rand_wide(rng, (n,)), float(_rand_wide(rng, (1,))[0])
+    got = orc.dot(x, y, a0)
+    R = Fraction(a0) + sum(Fraction(a) * Fraction(b) for a, b in zip(x, y))
+    mag = abs(a0) + float(np.sum(np.abs(x * y)))
+    assert abs(Fraction(got) - R) <= Fraction(gamma(n + 1) * mag * (1 + 1e-12))
+
+
+def test_dot_order_and_alpha_last(orc):
+    x = np.array([1.0, 2.0 ** -53, 2.0 ** -53])
+    assert orc.dot(x, np.ones(3), 0.0) == 1.0
+    assert orc.dot(x[::-1].copy(), np.ones(3), 0.0) == 1.0 + 2.0 ** -52
+    assert orc.dot(np.array([2.0 ** -53] * 2), np.ones(2), 1.0) == 1.0 + 2.0 ** -52
+
+
+def test_dot_equals_gemv_one_row(orc):
+    rng = np.random.default_rng(5)
+    x, y = rng.standard_normal(1000), rng.standard_normal(1000)
+    assert orc.dot(x, y, 0.25) == orc.gemv(x[None, :], y, np.array([0.25]))[0]
+
+
+def test_dot_integer_exact(orc):
+    x, y, a0 = workloads.dot_inputs(100000, seed=9, dist="int8")
+    ref = int(a0[0]) + int(np.dot(x.astype(np.int64), y.astype(np.int64)))
+    assert orc.dot(x, y, a0[0]) == ref
+
+
+# ----------------------------------------------------------------- GER ----
+
+@pytest.mark.parametrize("layout", [0, 1])
+def test_ger_closed_form_and_integer(orc, layout):
+    m, n = 33, 47
+    i = np.arange(m, dtype=np.float64)
+    j = np.arange(n, dtype=np.float64)
+    got = orc.ger(i, j, np.zeros((m, n)), layout=layout)
+    assert np.array_equal(got, np.outer(i, j))
+    x, y, C0 = workloads.ger_inputs(m, n, seed=203, dist="int8")
+    ref = C0.astype(np.int64) + np.outer(x.astype(np.int64), y.astype(np.int64))
+    assert np.array_equal(orc.ger(x, y, C0, layout=layout), ref.astype(np.float64))
+
+
+def test_ger_two_roundings(orc):
+    """C_ij + fl(x_i y_j): the product is rounded, then the addition; with
+    C0 = 0 the result is the correctly rounded product; in general it lies
+    within gamma_2 of the exact value."""
+    rng = np.random.default_rng(21)
+    x, y = _rand_wide(rng, (9,)), _rand_wide(rng, (8,))
+    got = orc.ger(x, y, np.zeros((9, 8)))
+    for a in range(9):
+        for b in range(8):
+            assert got[a, b] == float(Fraction(x[a]) * Fraction(y[b]))
+    C0 = _rand_wide(rng, (9, 8))
+    got = orc.ger(x, y, C0)
+    for a in range(9):
+        for b in range(8):
+            R = Fraction(C0[a, b]) + Fraction(x[a]) * Fraction(y[b])
+            mag = abs(C0[a, b]) + abs(x[a] * y[b])
+            assert abs(Fraction(got[a, b]) - R) <= Fraction(gamma(2) * mag * (1 + 1e-12))
+    # a product below half an ulp of C0 but a fused add would still see it
+    a = 1.0 + 2.0 ** -30
+    got = orc.ger(np.array([a]), np.array([a]), np.array([[-(1.0 + 2.0 ** -29)]]))
+    assert got[0, 0] == 0.0
+
+
+# ------------------------------------------------------- storage formats ----
+
+def _f32_bits(v):
+    return struct.unpack("<I", struct.pack("<f", v))[0]
+
+
+def _f32_from_bits(u):
+    return struct.unpack("<f", struct.pack("<I", u))[0]
+
+
+def test_bf16_decode_all_codes(orc):
+    """bfloat16 is the upper half of a binary32: decoding every one of the
+    65536 codes equals the bit reinterpretation done by numpy."""
+    codes = np.arange(1 << 16, dtype=np.uint32)
+    ref = (codes << 16).view(np.float32)
+    got = np.array([orc.bf16_to_f32(int(c)) for c in codes], dtype=np.float32)
+    same = (got.view(np.uint32) == ref.view(np.uint32)) | (np.isnan(got) & np.isnan(ref))
+    assert same.all()
+
+
+def _rne_fraction(v: Fraction, grid):
+    """Nearest element of a sorted list of (Fraction value, code) pairs, ties
+    to the even code (the even significand)."""
+    lo, hi = 0, len(grid) - 1
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if grid[mid][0] <= v:
+            lo = mid
+        else:
+            hi = mid
+    a, b = grid[lo], grid[hi]
+    if v <= a[0]:
+        return a[1]
+    if v >= b[0]:
+        return b[1]
+    da, db = v - a[0], b[0] - v
+    if da < db:
+        return a[1]
+    if db < da:
+        return b[1]
+    return a[1] if a[1] % 2 == 0 else b[1]
+
+
+def test_bf16_encode_matches_torch_and_rational_rne(orc):
+    import torch
+    rng = np.random.default_rng(31)
+    v = np.concatenate([
+        rng.standard_normal(20000).astype(np.float32),
+        (rng.uniform(-1, 1, 20000) * np.exp2(rng.integers(-140, 128, 20000))).astype(np.float32),
+    ])
+    # exact ties: a bfloat16 value plus half its quantum
+    base = (rng.integers(0, 1 << 15, 2000, dtype=np.uint32) << 16) | 0x8000
+    v = np.concatenate([v, base.view(np.float32), np.array([0.0, -0.0, np.inf, -np.inf], np.float32)])
+    v = v[np.isfinite(v) | np.isinf(v)]
+    got = np.array([orc.bf16_from_f32(float(t)) for t in v], dtype=np.uint16)
+    ref = torch.from_numpy(v).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(got, ref)
+    # NaN encodes to the canonical quiet NaN with the input's sign
+    assert orc.bf16_from_f32(float("nan")) & 0x7FFF == 0x7FC0
+    # rational RNE on positive normal samples, grid of neighbouring bfloat16 values
+    for t in v[:500]:
+        if not np.isfinite(t) or t <= 0:
+            continue
+        c0 = _f32_bits(float(t)) >> 16
+        grid = [(Fraction(_f32_from_bits(c << 16)), c) for c in (c0, c0 + 1) if c < 0x7F80]
+        assert orc.bf16_from_f32(float(t)) == _rne_fraction(Fraction(float(t)), grid)
+
+
+def _e4m3_value(code):
+    """Value of an OCP E4M3FN code from the format definition (None for NaN)."""
+    s = -1 if code & 0x80 else 1
+    E, M = (code >> 3) & 0xF, code & 7
+    if E == 15 and M == 7:
+        return None
+    if E == 0:
+        return s * Fraction(M, 512)
+    return s * Fraction(8 + M, 8) * Fraction(2) ** (E - 7)
+
+
+def test_e4m3_decode_all_codes(orc):
+    import torch
+    tv = torch.arange(256, dtype=torch.uint8).view(torch.float8_e4m3fn).to(torch.float32).numpy()
+    for code in range(256):
+        ref = _e4m3_value(code)
+        got = orc.e4m3_to_f32(code)
+        if ref is None:
+            assert math.isnan(got) and math.isnan(tv[code])
+        else:
+            assert Fraction(got) == ref
+            assert got == tv[code] or (got == 0 and tv[code] == 0)
+    assert orc.e4m3_to_f32(0x7E) == 448.0 and orc.e4m3_to_f32(0x01) == 2.0 ** -9
+
+
+def test_e4m3_encode_rational_rne_saturating(orc):
+    import torch
+    pos = sorted((_e4m3_value(c), c) for c in range(0x7F))  # non-negative finite codes
+    rng = np.random.default_rng(41)
+    v = np.concatenate([
+        (rng.uniform(0, 1, 30000) * np.exp2(rng.integers(-14, 10, 30000))).astype(np.float32),
+        np.array([float(a + b) / 2 for (a, _), (b, _) in zip(pos, pos[1:])], dtype=np.float32),  # all ties
+        np.array([0.0, 447.9, 448.0, 464.0, 1e6, 2.0 ** -10, 2.0 ** -10 * 1.0001, 3e-38], np.float32),
+    ])
+    for t in v:
+        t = float(t)
+        want = 0x7E if t >= 448 else _rne_fraction(Fraction(t), pos)
+        assert orc.e4m3_from_f32(t) == want, t
+        assert orc.e4m3_from_f32(-t) == (want | 0x80), t
+    # agrees with torch's RNE conversion inside the finite range
+    small = v[v < 448].astype(np.float32)
+    tq = torch.from_numpy(small).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    got = np.array([orc.e4m3_from_f32(float(t)) for t in small], dtype=np.uint8)
+    assert np.array_equal(got, tq)
+    assert orc.e4m3_from_f32(float("nan")) & 0x7F == 0x7F
+
+
+def test_quantize_rows_properties(orc):
+    rng = np.random.default_rng(51)
+    A = rng.uniform(-1, 1, (64, 300)).astype(np.float32)
+    A[3] = 0.0
+    A[5, :] *= 1e-30
+    for q in (orc.Q_BF16, orc.Q_E4M3):
+        codes, s = orc.quantize_rows(A, q)
+        assert s[3] == 1.0 and not codes[3].any()
+        dec = np.vectorize(orc.bf16_to_f32 if q == orc.Q_BF16 else orc.e4m3_to_f32)(codes).astype(np.float64)
+        amax = np.abs(A).max(axis=1)
+        for i in range(64):
+            if i == 3:
+                continue
+            if q == orc.Q_BF16:
+                # power-of-two scale with amax/s in [1, 2): a plain bfloat16 cast error
+                assert s[i] == 2.0 ** math.floor(math.log2(amax[i]))
+                rel = np.abs(dec[i] * s[i] - A[i]) / np.maximum(np.abs(A[i]), 1e-300)
+                assert rel.max() <= 2.0 ** -8
+            else:
+                assert s[i] == np.float32(amax[i]) / np.float32(448.0)
+                assert np.abs(dec[i]).max() <= 448.0
+                err = np.abs(dec[i] * s[i] - A[i])
+                assert err.max() <= amax[i] * 2.0 ** -4 + 2.0 ** -9 * s[i]
+
+
+def test_gemv_q_integer_exact(orc):
+    """Unit scales and integer codes: every partial sum is an exact integer."""
+    rng = np.random.default_rng(61)
+    m, n = 40, 513
+    Aint = rng.integers(-8, 9, (m, n)).astype(np.float32)
+    x = rng.integers(-8, 9, n).astype(np.float32)
+    for q, enc in ((orc.Q_BF16, orc.bf16_from_f32), (orc.Q_E4M3, orc.e4m3_from_f32)):
+        codes = np.vectorize(enc)(Aint).astype(np.uint16 if q == orc.Q_BF16 else np.uint8)
+        got = orc.gemv_q(codes, np.ones(m, np.float32), x, np.zeros(m), q)
+        assert np.array_equal(got, (Aint.astype(np.int64) @ x.astype(np.int64)).astype(np.float64))
+        got = orc.gemv_q(codes, np.full(m, 0.25, np.float32), x, np.ones(m), q)
+        assert np.array_equal(got, 1.0 + 0.25 * (Aint.astype(np.int64) @ x.astype(np.int64)))
+
+
+# ------------------------------------------------------- exact dot (f32) ----
+
+@pytest.mark.parametrize("seed", range(6))
+def test_exact_dot_matches_fraction(orc, seed):
+    rng = np.random.default_rng(70 + seed)
+    n = int(rng.integers(1, 1 << 12))
+    x = (rng.uniform(1, 2, n) * np.exp2(rng.integers(-60, 60, n)) * rng.choice([-1, 1], n)).astype(np.float32)
+    y = (rng.uniform(1, 2, n) * np.exp2(rng.integers(-60, 60, n)) * rng.choice([-1, 1], n)).astype(np.float32)
+    a0 = np.float32(rng.standard_normal())
+    R = Fraction(float(a0)) + sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(x, y))
+    assert orc.dot_exact_f32(x, y, float(a0)) == float(R)
+    Rabs = abs(Fraction(float(a0))) + sum(abs(Fraction(float(a)) * Fraction(float(b))) for a, b in zip(x, y))
+    assert orc.dot_exact_f32(x, y, float(a0), absval=True) == float(Rabs)
+
+
+def test_exact_dot_matches_fsum(orc):
+    x, y, _, _ = workloads.illcond_dot_inputs(1 << 18, seed=402)
+    p = (x.astype(np.float64) * y.astype(np.float64)).tolist()
+    assert orc.dot_exact_f32(x, y) == math.fsum(p)
+    assert orc.sum_exact_f64(np.array(p)) == math.fsum(p)
+
+
+def test_exact_dot_cancellation(orc):
+    # 2^60 + 1 - 2^60 = 1 exactly; the carries must cross many digits
+    x = np.array([2.0 ** 30, 1.0, -(2.0 ** 30)], dtype=np.float32)
+    y = np.array([2.0 ** 30, 1.0, 2.0 ** 30], dtype=np.float32)
+    assert orc.dot_exact_f32(x, y) == 1.0
+    assert orc.dot_exact_f32(-x, y) == -1.0
+    assert orc.dot_exact_f32(np.zeros(5, np.float32), np.zeros(5, np.float32), 0.0) == 0.0
+    # a sum exactly halfway between binary64 neighbours rounds to even
+    x = np.array([1.0, 2.0 ** -53], dtype=np.float32)
+    assert orc.dot_exact_f32(x, np.ones(2, np.float32)) == 1.0
+    x = np.array([1.0, 2.0 ** -53, 2.0 ** -80], dtype=np.float32)
+    assert orc.dot_exact_f32(x, np.ones(3, np.float32)) == 1.0 + 2.0 ** -52
+
+
+def test_illcond_generator(orc):
+    x, y, a0, cond = workloads.illcond_dot_inputs(1 << 16, seed=402)
+    e = orc.dot_exact_f32(x, y)
+    ab = orc.dot_exact_f32(x, y, absval=True)
+    measured = 2 * ab / abs(e)
+    assert 0.5e8 <= measured <= 2e8
+    assert abs(measured / cond - 1) < 1e-9
+    p = np.abs(x.astype(np.float64) * y.astype(np.float64))
+    e2 = np.floor(np.log2(p[p > 0]))
+    assert e2.min() >= -42 and e2.max() <= 42
+    # plain binary32 summation is useless at this condition number
+    naive = float(np.sum(x * y, dtype=np.float32))
+    assert abs(naive - e) / abs(e) > 1e-4
+
+
+# ----------------------------------------------------------- generators ----
+
+def test_splitmix64_published_vector():
+    """First outputs of SplitMix64 seeded with 0 (reference implementation
+    by Vigna): 0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F."""
+    with np.errstate(over="ignore"):
+        z = workloads.splitmix64(0, np.arange(3, dtype=np.uint64))
+    assert [int(v) for v in z] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    u = workloads.splitmix_uniform(123, 0, 10000)
+    assert u.min() >= -1 and u.max() < 1 and abs(u.mean()) < 0.05
+
+
+def test_generators_deterministic():
+    a = workloads.gemv_inputs(5, 7, seed=1)
+    b = workloads.gemv_inputs(5, 7, seed=1)
+    assert all(np.array_equal(p, q) for p, q in zip(a, b))
+    A, _, _ = workloads.gemv_inputs(4, 6, seed=1, lda=9)
+    assert A.shape == (4, 9) and np.isnan(A[:, 6:]).all()
