@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Throughput of the streaming GEMV / DOT / GER hot path on one MI355X.
+
+One step is one pass over every operation of the hot path, each on its full
+size, operands resident in HBM before timing starts:
+
+  gemv_n_f64   c += A x,    A 16384 x 16384 binary64 row-major, uniform[-1,1)
+  gemv_t_f64   c += A^T x,  same A
+  dot_f64      alpha += x . y, n = 2^28 binary64
+  ger_f64      C += x (outer) y, C 16384 x 16384 binary64
+  gemv_q_bf16  c += diag(s) Q x, Q = bfloat16 codes of A (per-row scales), x binary32
+  gemv_q_e4m3  the same with OCP E4M3FN codes
+  dot2_f32     compensated binary32 dot, n = 2^27, condition number 1e8
+
+(quantisation of A is a one-off pre-step and is not timed).  ``value`` is the
+aggregate algorithmic HBM throughput of the step: the bytes each operation
+must move (every operand element touched once) summed over the step, divided
+by the step time.  Per-operation times come from HIP events recorded on the
+stream the library launches on.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu] [--ops a,b]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def build_ops(sb, torch, dev, sel):
+    """Operands on the device and the list of (name, bytes, flops, fn)."""
+    import workloads  # noqa: F401  (host recipes; device draws below follow the same distributions)
+
+    M = N = 16384
+    nd = 1 << 28
+    n2 = 1 << 27
+    g = torch.Generator(device=dev)
+
+    def uni(shape, seed, dtype=torch.float64):
+        g.manual_seed(seed)
+        return (torch.rand(shape, generator=g, device=dev, dtype=dtype) * 2 - 1)
+
+    ops = []
+    want = (lambda name: sel is None or name in sel)
+    A = None
+    if any(want(k) for k in ("gemv_n_f64", "gemv_t_f64", "gemv_q_bf16", "gemv_q_e4m3")):
+        log("drawing A 16384x16384 binary64")
+        A = uni((M, N), 201)
+    if want("gemv_n_f64"):
+        x, c = uni((N,), 2011), uni((M,), 2012)
+        ops.append(("gemv_n_f64", 8 * (M * N + N + 2 * M), 2 * M * N, lambda: sb.sb_gemv(A, x, c, op=sb.SB_N)))
+    if want("gemv_t_f64"):
+        xt, ct = uni((M,), 2013), uni((N,), 2014)
+        ops.append(("gemv_t_f64", 8 * (M * N + M + 2 * N), 2 * M * N, lambda: sb.sb_gemv(A, xt, ct, op=sb.SB_T)))
+    if want("dot_f64"):
+        log("drawing DOT vectors n=2^28")
+        dx, dy, da = uni((nd,), 2021), uni((nd,), 2022), uni((1,), 2023)
+        ops.append(("dot_f64", 8 * (2 * nd + 2), 2 * nd, lambda: sb.sb_dot(dx, dy, da)))
+    if want("ger_f64"):
+        log("drawing GER operands 16384x16384")
+        gx, gy, gC = uni((M,), 2031), uni((N,), 2032), uni((M, N), 2033)
+        ops.append(("ger_f64", 8 * (2 * M * N + M + N), 2 * M * N, lambda: sb.sb_ger(gx, gy, gC)))
+    for q, name, es in ((sb.SB_BF16, "gemv_q_bf16", 2), (sb.SB_FP8_E4M3, "gemv_q_e4m3", 1)):
+        if not want(name):
+            continue
+        log(f"quantising A for {name} (untimed pre-step)")
+        A32 = A.float()
+        Aq = torch.empty((M, N), dtype=torch.int16 if es == 2 else torch.uint8, device=dev)
+        s = torch.empty(M, dtype=torch.float32, device=dev)
+        sb.sb_quantize_rows(A32, Aq, s, q)
+        del A32
+        g.manual_seed(401)
+        xq = torch.randn(N, generator=g, device=dev, dtype=torch.float32)
+        cq = torch.zeros(M, dtype=torch.float32, device=dev)
+        ops.append((name, es * M * N + 4 * N + 8 * M + 4 * M, 2 * M * N,
+                    (lambda Aq=Aq, s=s, xq=xq, cq=cq, q=q: sb.sb_gemv_q(Aq, s, xq, cq, q))))
+    if want("dot2_f32"):
+        log("generating ill-conditioned pairs n=2^27 (cond 1e8)")
+        import workloads
+        hx, hy, ha, cond = workloads.illcond_dot_inputs(n2, seed=402)
+        ex, ey = torch.from_numpy(hx).to(dev), torch.from_numpy(hy).to(dev)
+        ea = torch.zeros(1, dtype=torch.float32, device=dev)
+        ops.append(("dot2_f32", 4 * (2 * n2 + 2), 2 * n2, lambda: sb.sb_dot2_f32(ex, ey, ea)))
+    torch.cuda.synchronize()
+    return ops
+
+
+def cpu_baseline(step_bytes):
+    """The CPU oracle (single thread) on a bounded sample of every operation,
+    its per-operation rate applied to the full step's bytes."""
+    import numpy as np
+
+    import oracle
+    import workloads
+
+    oracle.build()
+    M = N = 16384
+    rows = 2048
+    rates, parts = {}, []
+
+    def timed(name, nbytes, fn):
+        t = time.perf_counter()
+        fn()
+        dt = time.perf_counter() - t
+        rates[name] = nbytes / dt
+        parts.append(f"{name}:{nbytes / 1e6:.0f}MB/{dt:.2f}s")
+
+    A, x, c0 = workloads.gemv_inputs(rows, N, seed=201)
+    timed("gemv_n_f64", 8 * (rows * N + N + 2 * rows), lambda: oracle.gemv(A, x, c0))
+    xt = x[:rows].copy()
+    ct = np.zeros(N)
+    timed("gemv_t_f64", 8 * (rows * N + rows + 2 * N), lambda: oracle.gemv(A, xt, ct, op=oracle.OP_T))
+    nd = 1 << 25
+    dx, dy, da = workloads.dot_inputs(nd, seed=202)
+    timed("dot_f64", 8 * (2 * nd + 2), lambda: oracle.dot(dx, dy, da[0]))
+    gx, gy, gC = workloads.ger_inputs(rows, N, seed=203)
+    timed("ger_f64", 8 * (2 * rows * N + rows + N), lambda: oracle.ger(gx, gy, gC))
+    A32 = A.astype(np.float32)
+    xq = np.random.default_rng(401).standard_normal(N).astype(np.float32)
+    for q, name, es in ((oracle.Q_BF16, "gemv_q_bf16", 2), (oracle.Q_E4M3, "gemv_q_e4m3", 1)):
+        codes, s = oracle.quantize_rows(A32, q)
+        timed(name, es * rows * N + 4 * N + 12 * rows, lambda: oracle.gemv_q(codes, s, xq, np.zeros(rows), q))
+    n2 = 1 << 22
+    hx, hy, _, _ = workloads.illcond_dot_inputs(n2, seed=402)
+    timed("dot2_f32", 4 * (2 * n2 + 2), lambda: oracle.dot_exact_f32(hx, hy))
+    total_t = sum(b / rates[k] for k, b in step_bytes.items() if k in rates)
+    total_b = sum(b for k, b in step_bytes.items() if k in rates)
+    return {
+        "value": round(total_b / total_t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+        "sample": "single-thread oracle per operation on a slice of the same workload "
+                  f"({'; '.join(parts)}); per-operation rates applied to the full step's bytes",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--ops", default=None, help="comma-separated subset of operations")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(one process, one MI355X); run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2108_02025_amd as sb
+    sb.load()
+    assert torch.cuda.is_available(), "no GPU visible"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    sel = set(args.ops.split(",")) if args.ops else None
+    ops = build_ops(sb, torch, dev, sel)
+    names = [o[0] for o in ops]
+    log(f"ops: {names}; warmup {args.warmup}, steps {args.steps}")
+
+    for _ in range(args.warmup):
+        for _, _, _, fn in ops:
+            fn()
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    ev = {n: [] for n in names}
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t_start.record()
+    for _ in range(args.steps):
+        for name, _, _, fn in ops:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            ev[name].append((a, b))
+    t_end.record()
+    torch.cuda.synchronize()
+    ms_step = t_start.elapsed_time(t_end) / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step")
+
+    per = {}
+    for name, nbytes, flops, _ in ops:
+        ts = [a.elapsed_time(b) for a, b in ev[name]]
+        us = 1e3 * sum(ts) / len(ts)
+        per[name] = {"us": round(us, 2), "GB/s": round(nbytes / us / 1e3, 1),
+                     "frac_hbm": round(nbytes / us / 1e3 / PEAK_HBM_GBS, 4),
+                     "TFLOP/s": round(flops / us / 1e6, 3), "bytes": nbytes}
+    step_bytes = {name: nbytes for name, nbytes, _, _ in ops}
+    value = sum(step_bytes.values()) / (ms_step * 1e-3) / 1e9
+    dom = max(per, key=lambda k: per[k]["us"])
+    roof = {"bound": "hbm", "kernel": dom, "achieved": per[dom]["GB/s"], "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(per[dom]["GB/s"] / PEAK_HBM_GBS, 4), "traffic": None}
+    extras = {}
+    if "gemv_n_f64" in per and "gemv_q_bf16" in per:
+        extras["bf16_over_f64_flops"] = round(per["gemv_q_bf16"]["TFLOP/s"] / per["gemv_n_f64"]["TFLOP/s"], 3)
+    if "gemv_n_f64" in per and "gemv_q_e4m3" in per:
+        extras["e4m3_over_f64_flops"] = round(per["gemv_q_e4m3"]["TFLOP/s"] / per["gemv_n_f64"]["TFLOP/s"], 3)
+
+    out = {
+        "metric": "GEMV HBM GB/s & % of peak, FP64 vs BF16-A; batched p50/p99 latency",
+        "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "fp64 gemv N/T 16384x16384, dot n=2^28, ger 16384x16384; "
+                               "bf16-A and e4m3-A gemv 16384x16384 (f32 x, c); dot2 f32 n=2^27 cond 1e8",
+                   "ops": names, "parallelism": "single GPU"},
+        "roofline": roof, "ops": per, **extras,
+    }
+    if not args.no_cpu:
+        log("timing the CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(step_bytes)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,177 @@
+/*
+ * streamblas: GEMV, DOT and GER for one AMD Instinct MI355X (gfx950).
+ *
+ * The operations and their names follow A. Singh and C. Bassoy, "High
+ * Performance Level-1 and Level-2 BLAS" (arXiv 2108.02025):
+ *   DOT   alpha += x . y        section 3.1, Definition (DOT); section 4.3
+ *   GER   C += x (outer) y      section 3.1, Definition (GEM); section 4.2
+ *   GEMV  c += A x, c += A^T x  section 3.1, Definition (GEMV); sections 4.1-4.2
+ * Every operation accumulates into its output: the products are summed first
+ * and the initial output value is added once, at the end.  There is no BLAS
+ * alpha/beta scaling; alpha is DOT's accumulator.
+ *
+ * Memory and streams.  Every pointer argument named A, x, y, c, C, alpha,
+ * Aq, scales or workspace is a DEVICE pointer owned by the caller.  The
+ * library never allocates device memory; kernels that need scratch (split
+ * reductions) use the workspace given to the handle.  Each call only
+ * enqueues work on the handle's HIP stream and returns; results are valid
+ * once that stream is synchronised.  Launch failures are reported as
+ * SB_EDEVICE; faults during execution surface at the caller's next
+ * synchronisation.  A handle must be used by one host thread at a time.
+ *
+ * Layouts.  A is m x n.  Row-major element (i, j) is A[i*lda + j] with
+ * lda >= max(1, n); column-major is A[i + j*lda] with lda >= max(1, m).
+ * Vectors are contiguous (unit stride).  Sizes are 64-bit.
+ *
+ * Errors.  Functions return SB_OK (0) or a negative status; they never throw.
+ * Argument checks run before any device work, so an invalid call enqueues
+ * nothing.  sb_last_error() gives a readable reason for the last failure on
+ * a handle.
+ */
+#ifndef STREAMBLAS_H
+#define STREAMBLAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sb_status;
+
+#define SB_OK 0
+#define SB_EINVAL (-1)        /* invalid argument: size, stride, null pointer, overlap */
+#define SB_ENOMEM (-2)        /* the handle's workspace is smaller than the call needs */
+#define SB_EDEVICE (-3)       /* the HIP runtime refused a launch or query */
+#define SB_EUNSUPPORTED (-4)  /* valid arguments, combination not implemented */
+#define SB_EINTERNAL (-5)     /* unexpected internal failure */
+
+typedef enum { SB_F64 = 0, SB_F32 = 1, SB_BF16 = 2, SB_FP8_E4M3 = 3 } sb_dtype;
+typedef enum { SB_ROW_MAJOR = 0, SB_COL_MAJOR = 1 } sb_layout;
+typedef enum { SB_N = 0, SB_T = 1 } sb_op;
+
+/* Operation kinds, for sb_workspace_bytes. */
+typedef enum { SB_KIND_GEMV = 0, SB_KIND_DOT = 1, SB_KIND_GER = 2, SB_KIND_GEMV_Q = 3,
+               SB_KIND_DOT2 = 4 } sb_kind;
+
+typedef struct sb_handle sb_handle;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t sb_version(void);
+
+/* Static text for a status code; never NULL. */
+const char* sb_status_string(sb_status status);
+
+/*
+ * Create a handle.  workspace: device buffer of ws_bytes bytes (may be NULL
+ * with ws_bytes = 0; calls that need scratch then fail with SB_ENOMEM).
+ * stream: a hipStream_t, or NULL for the default stream.  The handle keeps
+ * both pointers; the caller keeps ownership and must keep them alive while
+ * the handle uses them.  No HIP call is made here.  *out receives the handle.
+ */
+sb_status sb_handle_create(void* workspace, size_t ws_bytes, void* stream, sb_handle** out);
+
+/* Destroy a handle (NULL is accepted).  Does not free the workspace. */
+sb_status sb_handle_destroy(sb_handle* handle);
+
+/* Replace the stream used by later calls on this handle. */
+sb_status sb_set_stream(sb_handle* handle, void* stream);
+
+/* Replace the workspace used by later calls.  Work already enqueued may
+ * still use the old buffer until the stream reaches it. */
+sb_status sb_set_workspace(sb_handle* handle, void* workspace, size_t ws_bytes);
+
+/* Text describing the last failure on this handle ("" if none); with a
+ * NULL handle, the last failure of sb_handle_create on this thread. */
+const char* sb_last_error(const sb_handle* handle);
+
+/*
+ * Workspace bytes that one call of the given kind and shape needs with this
+ * handle's current tuning (0 if none).  For SB_KIND_DOT and SB_KIND_DOT2 the
+ * length is n (m is ignored); for SB_KIND_GER the result is always 0.
+ * Returns (size_t)-1 for invalid arguments.
+ */
+size_t sb_workspace_bytes(const sb_handle* handle, sb_kind kind, sb_dtype dtype,
+                          sb_layout layout, sb_op op, int64_t m, int64_t n);
+
+/*
+ * GEMV: c += op(A) x   (section 3.1, Definition (GEMV); section 4.1
+ * Algorithm 1 for the column-major form, section 4.2 Algorithm 2 for the
+ * row-major form).
+ *   dtype  SB_F64 or SB_F32: A, x and c all have this type; products and
+ *          sums are computed in it (fused multiply-add).  SB_BF16 and
+ *          SB_FP8_E4M3 return SB_EUNSUPPORTED (use sb_gemv_q).
+ *   op     SB_N: x has n entries, c has m.  SB_T: x has m entries, c has n.
+ * (row-major, N) and (column-major, T) on the same buffer are the same
+ * computation and give identical bits; so do (row-major, T) and
+ * (column-major, N).  If the output length is 0 nothing is launched; if the
+ * reduction length is 0, c is unchanged.  c must not overlap A or x.
+ * Results are deterministic: the summation order depends only on
+ * (dtype, layout, op, m, n, lda alignment) and the handle's tuning.
+ */
+sb_status sb_gemv(sb_handle* handle, sb_dtype dtype, sb_layout layout, sb_op op,
+                  int64_t m, int64_t n, const void* A, int64_t lda,
+                  const void* x, void* c);
+
+/*
+ * DOT: *alpha += x . y   (section 3.1, Definition (DOT); section 4.3,
+ * Algorithms 3 and 4).  dtype SB_F64 or SB_F32; x and y have n entries;
+ * alpha points to ONE device scalar of that type.  The products are summed
+ * in a fixed two-stage order (per-workgroup partial sums in the workspace,
+ * then one workgroup combines them in index order) and the initial alpha is
+ * added last.  n = 0 leaves alpha unchanged.  Deterministic for a given n.
+ */
+sb_status sb_dot(sb_handle* handle, sb_dtype dtype, int64_t n, const void* x,
+                 const void* y, void* alpha);
+
+/*
+ * GER: C += x (outer) y   (section 3.1, Definition (GEM); section 4.2,
+ * Algorithm 2).  C is m x n in the given layout with leading dimension ldc;
+ * x has m entries, y has n.  Each entry is computed as C_ij + fl(x_i y_j)
+ * (the product rounded, then the addition), exactly as the definition
+ * states, so the result does not depend on the launch configuration.
+ * dtype SB_F64 or SB_F32.  C must not overlap x or y.
+ */
+sb_status sb_ger(sb_handle* handle, sb_dtype dtype, sb_layout layout, int64_t m,
+                 int64_t n, const void* x, const void* y, void* C, int64_t ldc);
+
+/*
+ * Per-row scaled quantisation (precision form; the paper leaves the element
+ * width generic).  A: m x n binary32, row-major, leading dimension lda.
+ * Output: codes Aq (row-major, leading dimension ldq, in elements) and
+ * scales[m] (binary32).  q = SB_BF16: s_i = 2^floor(log2 amax_i) and
+ * 2-byte bfloat16 codes; q = SB_FP8_E4M3: s_i = amax_i / 448 and 1-byte
+ * OCP E4M3FN codes, saturated to +-448.  amax_i is the largest |a_ij| over
+ * non-NaN entries; a row whose amax is 0 or infinite gets s_i = 1.  Each
+ * code is the round-to-nearest-even encoding of fl32(a_ij / s_i).
+ */
+sb_status sb_quantize_rows(sb_handle* handle, sb_dtype q, int64_t m, int64_t n,
+                           const float* A, int64_t lda, void* Aq, int64_t ldq,
+                           float* scales);
+
+/*
+ * Quantised GEMV: c_i += s_i * sum_j q_ij x_j with q decoded from Aq
+ * (row-major, leading dimension ldq elements), x and c binary32, products
+ * and sums in binary32 (fused multiply-add), the scale applied once per row
+ * after the reduction.  q = SB_BF16 or SB_FP8_E4M3.
+ */
+sb_status sb_gemv_q(sb_handle* handle, sb_dtype q, int64_t m, int64_t n, const void* Aq,
+                    int64_t ldq, const float* scales, const float* x, float* c);
+
+/*
+ * Compensated DOT in binary32: *alpha += x . y evaluated with error-free
+ * transformations (TwoProduct through fused multiply-add, TwoSum) at every
+ * step and every level of the reduction, as in the Dot2 algorithm of Ogita,
+ * Rump and Oishi (SIAM J. Sci. Comput. 26(6), 2005).  The result is about as
+ * accurate as a binary32 evaluation carried out in twice the working
+ * precision.  alpha is one device binary32 scalar.
+ */
+sb_status sb_dot2_f32(sb_handle* handle, int64_t n, const float* x, const float* y,
+                      float* alpha);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STREAMBLAS_H */

@@ -1,0 +1,290 @@
+"""Python binding of streamblas (``libstreamblas.so``, declared in
+``include/streamblas.h``): GEMV, DOT and GER of Singh and Bassoy, "High
+Performance Level-1 and Level-2 BLAS" (arXiv 2108.02025, section 3.1
+definitions), on one MI355X.
+
+The functions carry the C names and only marshal arguments: they read
+pointers, sizes and strides from torch tensors, pick the handle of the
+tensor's device, size its workspace and pass the current torch stream.  All
+arithmetic runs in the library's HIP kernels.  There is no fallback: if the
+library is not built, ``load()`` raises.
+
+torch is imported first on purpose: the library links the HIP runtime that
+torch loads, so one process holds one runtime.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = [
+    "SB_F64", "SB_F32", "SB_BF16", "SB_FP8_E4M3", "SB_ROW_MAJOR", "SB_COL_MAJOR", "SB_N", "SB_T",
+    "SB_KIND_GEMV", "SB_KIND_DOT", "SB_KIND_GER", "SB_KIND_GEMV_Q", "SB_KIND_DOT2",
+    "StreamBlasError", "load", "lib_path", "Handle", "handle_for",
+    "sb_version", "sb_status_string", "sb_workspace_bytes",
+    "sb_gemv", "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32",
+]
+
+SB_OK, SB_EINVAL, SB_ENOMEM, SB_EDEVICE, SB_EUNSUPPORTED, SB_EINTERNAL = 0, -1, -2, -3, -4, -5
+SB_F64, SB_F32, SB_BF16, SB_FP8_E4M3 = 0, 1, 2, 3
+SB_ROW_MAJOR, SB_COL_MAJOR = 0, 1
+SB_N, SB_T = 0, 1
+SB_KIND_GEMV, SB_KIND_DOT, SB_KIND_GER, SB_KIND_GEMV_Q, SB_KIND_DOT2 = 0, 1, 2, 3, 4
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libstreamblas.so")
+
+_DTYPES = {torch.float64: SB_F64, torch.float32: SB_F32}
+
+
+class StreamBlasError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libstreamblas.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(lib_path):
+        raise FileNotFoundError(f"{lib_path} is not built; run python -m paper_2108_02025_amd.build")
+    L = ctypes.CDLL(lib_path)
+    P, I64, I32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    L.sb_version.restype = I32
+    L.sb_status_string.argtypes = [I32]
+    L.sb_status_string.restype = ctypes.c_char_p
+    L.sb_handle_create.argtypes = [P, SZ, P, ctypes.POINTER(P)]
+    L.sb_handle_destroy.argtypes = [P]
+    L.sb_set_stream.argtypes = [P, P]
+    L.sb_set_workspace.argtypes = [P, P, SZ]
+    L.sb_last_error.argtypes = [P]
+    L.sb_last_error.restype = ctypes.c_char_p
+    L.sb_workspace_bytes.argtypes = [P, I32, I32, I32, I32, I64, I64]
+    L.sb_workspace_bytes.restype = SZ
+    L.sb_gemv.argtypes = [P, I32, I32, I32, I64, I64, P, I64, P, P]
+    L.sb_dot.argtypes = [P, I32, I64, P, P, P]
+    L.sb_ger.argtypes = [P, I32, I32, I64, I64, P, P, P, I64]
+    L.sb_quantize_rows.argtypes = [P, I32, I64, I64, P, I64, P, I64, P]
+    L.sb_gemv_q.argtypes = [P, I32, I64, I64, P, I64, P, P, P]
+    L.sb_dot2_f32.argtypes = [P, I64, P, P, P]
+    for f in ("sb_handle_create", "sb_handle_destroy", "sb_set_stream", "sb_set_workspace", "sb_gemv",
+              "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32"):
+        getattr(L, f).restype = I32
+    _lib = L
+    return L
+
+
+def sb_version() -> int:
+    return int(load().sb_version())
+
+
+def sb_status_string(status: int) -> str:
+    return load().sb_status_string(status).decode()
+
+
+class Handle:
+    """An sb_handle bound to one device, with a workspace owned by torch."""
+
+    def __init__(self, device=None):
+        L = load()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        self._ws = None
+        h = ctypes.c_void_p()
+        st = L.sb_handle_create(None, 0, None, ctypes.byref(h))
+        if st != SB_OK:
+            raise StreamBlasError(st, L.sb_last_error(None).decode())
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sb_handle_destroy(self.h)
+            self.h = None
+
+    def error(self) -> str:
+        return load().sb_last_error(self.h).decode()
+
+    def prepare(self, nbytes: int):
+        """Point the handle at the current stream and a workspace of >= nbytes."""
+        L = load()
+        if nbytes == (1 << 64) - 1:
+            raise StreamBlasError(SB_EINVAL, "invalid arguments for workspace sizing")
+        if nbytes and (self._ws is None or self._ws.numel() < nbytes):
+            self._ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            L.sb_set_workspace(self.h, ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel())
+        L.sb_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def check(self, st: int):
+        if st != SB_OK:
+            raise StreamBlasError(st, self.error())
+
+
+_handles: dict[int, Handle] = {}
+
+
+def handle_for(t: torch.Tensor) -> Handle:
+    idx = t.device.index if t.device.index is not None else torch.cuda.current_device()
+    h = _handles.get(idx)
+    if h is None:
+        h = _handles[idx] = Handle(idx)
+    return h
+
+
+def sb_workspace_bytes(kind: int, dtype: int, layout: int, op: int, m: int, n: int,
+                       handle: Handle | None = None) -> int:
+    return int(load().sb_workspace_bytes(handle.h if handle else None, kind, dtype, layout, op, m, n))
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dtype(t: torch.Tensor) -> int:
+    if t.dtype not in _DTYPES:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return _DTYPES[t.dtype]
+
+
+def _matrix_layout(M: torch.Tensor):
+    """(layout, ld) of a 2-D tensor whose rows or columns are contiguous."""
+    if M.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    r, c = M.shape
+    sr, sc = M.stride()
+    if M.numel() == 0:
+        return SB_ROW_MAJOR, max(c, 1)
+    if sc == 1 or c <= 1:
+        return SB_ROW_MAJOR, (sr if r > 1 else max(c, 1))
+    if sr == 1 or r <= 1:
+        return SB_COL_MAJOR, (sc if c > 1 else max(r, 1))
+    raise ValueError("matrix needs unit stride along rows or columns")
+
+
+def _vec(v: torch.Tensor) -> torch.Tensor:
+    if v.dim() != 1 or (v.numel() > 1 and v.stride(0) != 1):
+        raise ValueError("vectors must be 1-D with unit stride")
+    return v
+
+
+def _device_check(*ts):
+    d = ts[0].device
+    for t in ts:
+        if not t.is_cuda or t.device != d:
+            raise ValueError("all operands must be on the same GPU")
+
+
+def sb_gemv(A: torch.Tensor, x: torch.Tensor, c: torch.Tensor, op: int = SB_N) -> torch.Tensor:
+    """c += op(A) x in place (row- or column-major A from its strides)."""
+    _device_check(A, x, c)
+    _vec(x), _vec(c)
+    dt = _dtype(A)
+    if x.dtype != A.dtype or c.dtype != A.dtype:
+        raise TypeError("A, x and c must share a dtype")
+    layout, ld = _matrix_layout(A)
+    m, n = A.shape
+    if x.numel() != (n if op == SB_N else m) or c.numel() != (m if op == SB_N else n):
+        raise ValueError("x / c lengths do not match op(A)")
+    h = handle_for(A)
+    h.prepare(sb_workspace_bytes(SB_KIND_GEMV, dt, layout, op, m, n, h))
+    h.check(load().sb_gemv(h.h, dt, layout, op, m, n, _ptr(A), ld, _ptr(x), _ptr(c)))
+    return c
+
+
+def sb_dot(x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor) -> torch.Tensor:
+    """alpha (one-element device tensor) += x . y in place."""
+    _device_check(x, y, alpha)
+    _vec(x), _vec(y)
+    dt = _dtype(x)
+    if y.dtype != x.dtype or alpha.dtype != x.dtype or alpha.numel() != 1:
+        raise TypeError("x, y and a one-element alpha must share a dtype")
+    n = x.numel()
+    if y.numel() != n:
+        raise ValueError("x and y differ in length")
+    h = handle_for(x)
+    h.prepare(sb_workspace_bytes(SB_KIND_DOT, dt, 0, 0, 1, n, h))
+    h.check(load().sb_dot(h.h, dt, n, _ptr(x), _ptr(y), _ptr(alpha)))
+    return alpha
+
+
+def sb_ger(x: torch.Tensor, y: torch.Tensor, C: torch.Tensor) -> torch.Tensor:
+    """C += x (outer) y in place (row- or column-major C from its strides)."""
+    _device_check(x, y, C)
+    _vec(x), _vec(y)
+    dt = _dtype(C)
+    if x.dtype != C.dtype or y.dtype != C.dtype:
+        raise TypeError("x, y and C must share a dtype")
+    layout, ld = _matrix_layout(C)
+    m, n = C.shape
+    if x.numel() != m or y.numel() != n:
+        raise ValueError("x must have C.shape[0] entries and y C.shape[1]")
+    h = handle_for(C)
+    h.prepare(0)
+    h.check(load().sb_ger(h.h, dt, layout, m, n, _ptr(x), _ptr(y), _ptr(C), ld))
+    return C
+
+
+def _q_check(q: int, Aq: torch.Tensor):
+    if q not in (SB_BF16, SB_FP8_E4M3):
+        raise ValueError("q must be SB_BF16 or SB_FP8_E4M3")
+    if Aq.element_size() != (2 if q == SB_BF16 else 1):
+        raise TypeError("code tensor element size does not match q")
+
+
+def sb_quantize_rows(A: torch.Tensor, Aq: torch.Tensor, scales: torch.Tensor, q: int):
+    """Per-row scaled quantisation of a row-major binary32 A into Aq/scales."""
+    _device_check(A, Aq, scales)
+    _q_check(q, Aq)
+    if A.dtype != torch.float32 or scales.dtype != torch.float32:
+        raise TypeError("A and scales must be float32")
+    la, lda = _matrix_layout(A)
+    lq, ldq = _matrix_layout(Aq)
+    if la != SB_ROW_MAJOR or lq != SB_ROW_MAJOR or A.shape != Aq.shape:
+        raise ValueError("A and Aq must be row-major and of one shape")
+    m, n = A.shape
+    if scales.numel() != m:
+        raise ValueError("scales must have one entry per row")
+    h = handle_for(A)
+    h.prepare(0)
+    h.check(load().sb_quantize_rows(h.h, q, m, n, _ptr(A), lda, _ptr(Aq), ldq, _ptr(scales)))
+    return Aq, scales
+
+
+def sb_gemv_q(Aq: torch.Tensor, scales: torch.Tensor, x: torch.Tensor, c: torch.Tensor, q: int):
+    """c += diag(scales) Q x in place, Q decoded from row-major codes Aq."""
+    _device_check(Aq, scales, x, c)
+    _q_check(q, Aq)
+    _vec(x), _vec(c), _vec(scales)
+    if x.dtype != torch.float32 or c.dtype != torch.float32 or scales.dtype != torch.float32:
+        raise TypeError("scales, x and c must be float32")
+    lq, ldq = _matrix_layout(Aq)
+    if lq != SB_ROW_MAJOR:
+        raise ValueError("Aq must be row-major")
+    m, n = Aq.shape
+    if x.numel() != n or c.numel() != m or scales.numel() != m:
+        raise ValueError("x must have Aq.shape[1] entries, c and scales Aq.shape[0]")
+    h = handle_for(Aq)
+    h.prepare(sb_workspace_bytes(SB_KIND_GEMV_Q, q, 0, 0, m, n, h))
+    h.check(load().sb_gemv_q(h.h, q, m, n, _ptr(Aq), ldq, _ptr(scales), _ptr(x), _ptr(c)))
+    return c
+
+
+def sb_dot2_f32(x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor) -> torch.Tensor:
+    """Compensated binary32 alpha += x . y in place."""
+    _device_check(x, y, alpha)
+    _vec(x), _vec(y)
+    if x.dtype != torch.float32 or y.dtype != torch.float32 or alpha.dtype != torch.float32:
+        raise TypeError("sb_dot2_f32 takes float32 tensors")
+    n = x.numel()
+    if y.numel() != n or alpha.numel() != 1:
+        raise ValueError("x and y differ in length or alpha is not one element")
+    h = handle_for(x)
+    h.prepare(sb_workspace_bytes(SB_KIND_DOT2, SB_F32, 0, 0, 1, n, h))
+    h.check(load().sb_dot2_f32(h.h, n, _ptr(x), _ptr(y), _ptr(alpha)))
+    return alpha

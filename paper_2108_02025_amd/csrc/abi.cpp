@@ -1,0 +1,320 @@
+// The C-ABI of streamblas: argument validation, the mapping of
+// (layout, op) onto the two GEMV kernels, and error reporting.  Every check
+// here runs before any HIP call, so a rejected call enqueues nothing.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "sb_internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+const char* kStatusText[] = {
+    "success",
+    "invalid argument",
+    "workspace too small",
+    "HIP runtime error",
+    "unsupported combination",
+    "internal error",
+};
+
+bool mul_ok(int64_t a, int64_t b, int64_t* out) { return !__builtin_mul_overflow(a, b, out); }
+
+int esize_of(sb_dtype dt)
+{
+    switch (dt) {
+    case SB_F64: return 8;
+    case SB_F32: return 4;
+    case SB_BF16: return 2;
+    case SB_FP8_E4M3: return 1;
+    }
+    return 0;
+}
+
+// Number of elements spanned by a rows x cols matrix with leading dimension
+// ld (row-major view), or -1 on overflow.  0 for an empty matrix.
+int64_t span_elems(int64_t rows, int64_t cols, int64_t ld)
+{
+    if (rows == 0 || cols == 0) return 0;
+    int64_t t;
+    if (!mul_ok(rows - 1, ld, &t) || __builtin_add_overflow(t, cols, &t)) return -1;
+    return t;
+}
+
+struct Range {
+    uintptr_t lo, hi;  // [lo, hi) in bytes; empty when lo == hi
+};
+
+Range range_of(const void* p, int64_t elems, int es)
+{
+    const uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+    return Range{lo, lo + (uintptr_t)elems * (uintptr_t)es};
+}
+
+bool overlap(Range a, Range b) { return a.lo < a.hi && b.lo < b.hi && a.lo < b.hi && b.lo < a.hi; }
+
+bool misaligned(const void* p, int es) { return (reinterpret_cast<uintptr_t>(p) % (uintptr_t)es) != 0; }
+
+constexpr int64_t kMaxBytes = (int64_t)1 << 46;  // 64 TiB: far above any device
+
+}  // namespace
+
+namespace sb {
+
+sb_status fail(sb_handle* h, sb_status st, const char* fmt, ...)
+{
+    char* buf = h ? h->err : g_err;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, 512, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+sb_status check_launch(sb_handle* h, const char* what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) return SB_OK;
+    return fail(h, SB_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace sb
+
+using sb::fail;
+
+#define SB_GUARD_BEGIN try {
+#define SB_GUARD_END                                                              \
+    }                                                                             \
+    catch (const std::bad_alloc&) { return fail(handle, SB_EINTERNAL, "out of host memory"); } \
+    catch (...) { return fail(handle, SB_EINTERNAL, "unexpected C++ exception"); }
+
+extern "C" {
+
+int32_t sb_version(void) { return 100; }
+
+const char* sb_status_string(sb_status status)
+{
+    if (status > 0 || status < SB_EINTERNAL) return "unknown status";
+    return kStatusText[-status];
+}
+
+sb_status sb_handle_create(void* workspace, size_t ws_bytes, void* stream, sb_handle** out)
+{
+    if (!out) return fail(nullptr, SB_EINVAL, "sb_handle_create: out is NULL");
+    *out = nullptr;
+    if (!workspace && ws_bytes) return fail(nullptr, SB_EINVAL, "sb_handle_create: NULL workspace of %zu bytes", ws_bytes);
+    sb_handle* h = new (std::nothrow) sb_handle;
+    if (!h) return fail(nullptr, SB_EINTERNAL, "sb_handle_create: out of host memory");
+    h->ws = workspace;
+    h->ws_bytes = workspace ? ws_bytes : 0;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->err[0] = '\0';
+    *out = h;
+    return SB_OK;
+}
+
+sb_status sb_handle_destroy(sb_handle* handle)
+{
+    delete handle;
+    return SB_OK;
+}
+
+sb_status sb_set_stream(sb_handle* handle, void* stream)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_set_stream: NULL handle");
+    handle->stream = static_cast<hipStream_t>(stream);
+    return SB_OK;
+}
+
+sb_status sb_set_workspace(sb_handle* handle, void* workspace, size_t ws_bytes)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_set_workspace: NULL handle");
+    if (!workspace && ws_bytes) return fail(handle, SB_EINVAL, "sb_set_workspace: NULL workspace of %zu bytes", ws_bytes);
+    handle->ws = workspace;
+    handle->ws_bytes = workspace ? ws_bytes : 0;
+    return SB_OK;
+}
+
+const char* sb_last_error(const sb_handle* handle) { return handle ? handle->err : g_err; }
+
+size_t sb_workspace_bytes(const sb_handle* handle, sb_kind kind, sb_dtype dtype, sb_layout layout,
+                          sb_op op, int64_t m, int64_t n)
+{
+    (void)handle;
+    const size_t bad = (size_t)-1;
+    if (m < 0 || n < 0) return bad;
+    switch (kind) {
+    case SB_KIND_GEMV: {
+        if (dtype != SB_F64 && dtype != SB_F32) return bad;
+        if ((layout != SB_ROW_MAJOR && layout != SB_COL_MAJOR) || (op != SB_N && op != SB_T)) return bad;
+        if (m == 0 || n == 0) return 0;
+        const int es = esize_of(dtype);
+        const int64_t rows = layout == SB_ROW_MAJOR ? m : n, cols = layout == SB_ROW_MAJOR ? n : m;
+        const bool row_dot = (layout == SB_ROW_MAJOR) == (op == SB_N);
+        return row_dot ? sb::plan_gemv_n(es, rows, cols).ws : sb::plan_gemv_t(es, rows, cols).ws;
+    }
+    case SB_KIND_DOT:
+        if (dtype != SB_F64 && dtype != SB_F32) return bad;
+        return n == 0 ? 0 : sb::plan_dot(esize_of(dtype), n, 1).ws;
+    case SB_KIND_DOT2:
+        return n == 0 ? 0 : sb::plan_dot(4, n, 2).ws;
+    case SB_KIND_GEMV_Q:
+        if (dtype != SB_BF16 && dtype != SB_FP8_E4M3) return bad;
+        return (m == 0 || n == 0) ? 0 : sb::gemv_q_ws_bytes(dtype, m, n);
+    case SB_KIND_GER:
+        return 0;
+    }
+    return bad;
+}
+
+sb_status sb_gemv(sb_handle* handle, sb_dtype dtype, sb_layout layout, sb_op op, int64_t m, int64_t n,
+                  const void* A, int64_t lda, const void* x, void* c)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_gemv: NULL handle");
+    SB_GUARD_BEGIN
+    if (dtype == SB_BF16 || dtype == SB_FP8_E4M3)
+        return fail(handle, SB_EUNSUPPORTED, "sb_gemv: narrow storage needs sb_gemv_q");
+    if (dtype != SB_F64 && dtype != SB_F32) return fail(handle, SB_EINVAL, "sb_gemv: bad dtype %d", (int)dtype);
+    if (layout != SB_ROW_MAJOR && layout != SB_COL_MAJOR) return fail(handle, SB_EINVAL, "sb_gemv: bad layout %d", (int)layout);
+    if (op != SB_N && op != SB_T) return fail(handle, SB_EINVAL, "sb_gemv: bad op %d", (int)op);
+    if (m < 0 || n < 0) return fail(handle, SB_EINVAL, "sb_gemv: negative size m=%lld n=%lld", (long long)m, (long long)n);
+    const int64_t rows = layout == SB_ROW_MAJOR ? m : n, cols = layout == SB_ROW_MAJOR ? n : m;
+    if (lda < (cols > 1 ? cols : 1))
+        return fail(handle, SB_EINVAL, "sb_gemv: lda=%lld below %lld", (long long)lda, (long long)(cols > 1 ? cols : 1));
+    const int es = esize_of(dtype);
+    const int64_t a_el = span_elems(rows, cols, lda);
+    int64_t a_bytes;
+    if (a_el < 0 || !mul_ok(a_el, es, &a_bytes) || a_bytes > kMaxBytes)
+        return fail(handle, SB_EINVAL, "sb_gemv: matrix extent overflows");
+    const int64_t lx = op == SB_N ? n : m, lc = op == SB_N ? m : n;
+    // An empty output or an empty reduction reads and writes nothing.
+    if (lc == 0 || lx == 0) return SB_OK;
+    if (!A || !x || !c)
+        return fail(handle, SB_EINVAL, "sb_gemv: NULL pointer with non-zero extent");
+    if (misaligned(A, es) || misaligned(x, es) || misaligned(c, es))
+        return fail(handle, SB_EINVAL, "sb_gemv: pointer not aligned to the element size");
+    const Range rc = range_of(c, lc, es);
+    if (overlap(rc, range_of(A, a_el, es)) || overlap(rc, range_of(x, lx, es)))
+        return fail(handle, SB_EINVAL, "sb_gemv: c overlaps A or x");
+    const bool row_dot = (layout == SB_ROW_MAJOR) == (op == SB_N);
+    return row_dot ? sb::run_gemv_n(handle, dtype, rows, cols, A, lda, x, c)
+                   : sb::run_gemv_t(handle, dtype, rows, cols, A, lda, x, c);
+    SB_GUARD_END
+}
+
+sb_status sb_dot(sb_handle* handle, sb_dtype dtype, int64_t n, const void* x, const void* y, void* alpha)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_dot: NULL handle");
+    SB_GUARD_BEGIN
+    if (dtype == SB_BF16 || dtype == SB_FP8_E4M3) return fail(handle, SB_EUNSUPPORTED, "sb_dot: narrow dtype");
+    if (dtype != SB_F64 && dtype != SB_F32) return fail(handle, SB_EINVAL, "sb_dot: bad dtype %d", (int)dtype);
+    if (n < 0) return fail(handle, SB_EINVAL, "sb_dot: negative n=%lld", (long long)n);
+    const int es = esize_of(dtype);
+    int64_t bytes;
+    if (!mul_ok(n, es, &bytes) || bytes > kMaxBytes) return fail(handle, SB_EINVAL, "sb_dot: n overflows");
+    if (!alpha || (n > 0 && (!x || !y))) return fail(handle, SB_EINVAL, "sb_dot: NULL pointer");
+    if (misaligned(x, es) || misaligned(y, es) || misaligned(alpha, es))
+        return fail(handle, SB_EINVAL, "sb_dot: pointer not aligned to the element size");
+    const Range ra = range_of(alpha, 1, es);
+    if (overlap(ra, range_of(x, n, es)) || overlap(ra, range_of(y, n, es)))
+        return fail(handle, SB_EINVAL, "sb_dot: alpha overlaps x or y");
+    return sb::run_dot(handle, dtype, n, x, y, alpha);
+    SB_GUARD_END
+}
+
+sb_status sb_ger(sb_handle* handle, sb_dtype dtype, sb_layout layout, int64_t m, int64_t n, const void* x,
+                 const void* y, void* C, int64_t ldc)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_ger: NULL handle");
+    SB_GUARD_BEGIN
+    if (dtype == SB_BF16 || dtype == SB_FP8_E4M3) return fail(handle, SB_EUNSUPPORTED, "sb_ger: narrow dtype");
+    if (dtype != SB_F64 && dtype != SB_F32) return fail(handle, SB_EINVAL, "sb_ger: bad dtype %d", (int)dtype);
+    if (layout != SB_ROW_MAJOR && layout != SB_COL_MAJOR) return fail(handle, SB_EINVAL, "sb_ger: bad layout %d", (int)layout);
+    if (m < 0 || n < 0) return fail(handle, SB_EINVAL, "sb_ger: negative size");
+    const int64_t rows = layout == SB_ROW_MAJOR ? m : n, cols = layout == SB_ROW_MAJOR ? n : m;
+    if (ldc < (cols > 1 ? cols : 1)) return fail(handle, SB_EINVAL, "sb_ger: ldc=%lld too small", (long long)ldc);
+    const int es = esize_of(dtype);
+    const int64_t c_el = span_elems(rows, cols, ldc);
+    int64_t c_bytes;
+    if (c_el < 0 || !mul_ok(c_el, es, &c_bytes) || c_bytes > kMaxBytes)
+        return fail(handle, SB_EINVAL, "sb_ger: matrix extent overflows");
+    if ((c_el > 0 && (!C || !x || !y))) return fail(handle, SB_EINVAL, "sb_ger: NULL pointer with non-zero extent");
+    if (misaligned(x, es) || misaligned(y, es) || misaligned(C, es))
+        return fail(handle, SB_EINVAL, "sb_ger: pointer not aligned to the element size");
+    const Range rC = range_of(C, c_el, es);
+    if (overlap(rC, range_of(x, m, es)) || overlap(rC, range_of(y, n, es)))
+        return fail(handle, SB_EINVAL, "sb_ger: C overlaps x or y");
+    if (c_el == 0) return SB_OK;
+    if (layout == SB_ROW_MAJOR) return sb::run_ger(handle, dtype, m, n, x, y, C, ldc);
+    return sb::run_ger(handle, dtype, n, m, y, x, C, ldc);
+    SB_GUARD_END
+}
+
+sb_status sb_quantize_rows(sb_handle* handle, sb_dtype q, int64_t m, int64_t n, const float* A, int64_t lda,
+                           void* Aq, int64_t ldq, float* scales)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_quantize_rows: NULL handle");
+    SB_GUARD_BEGIN
+    if (q != SB_BF16 && q != SB_FP8_E4M3) return fail(handle, SB_EINVAL, "sb_quantize_rows: q must be BF16 or FP8_E4M3");
+    if (m < 0 || n < 0) return fail(handle, SB_EINVAL, "sb_quantize_rows: negative size");
+    const int64_t need = n > 1 ? n : 1;
+    if (lda < need || ldq < need) return fail(handle, SB_EINVAL, "sb_quantize_rows: lda/ldq below n");
+    const int qs = esize_of(q);
+    const int64_t a_el = span_elems(m, n, lda), q_el = span_elems(m, n, ldq);
+    int64_t t;
+    if (a_el < 0 || q_el < 0 || !mul_ok(a_el, 4, &t) || t > kMaxBytes)
+        return fail(handle, SB_EINVAL, "sb_quantize_rows: extent overflows");
+    if ((a_el > 0 && (!A || !Aq)) || (m > 0 && !scales)) return fail(handle, SB_EINVAL, "sb_quantize_rows: NULL pointer");
+    if (misaligned(A, 4) || misaligned(Aq, qs) || misaligned(scales, 4))
+        return fail(handle, SB_EINVAL, "sb_quantize_rows: pointer not aligned to the element size");
+    const Range rq = range_of(Aq, q_el, qs), rs = range_of(scales, m, 4), ra = range_of(A, a_el, 4);
+    if (overlap(rq, ra) || overlap(rs, ra) || overlap(rs, rq))
+        return fail(handle, SB_EINVAL, "sb_quantize_rows: outputs overlap");
+    return sb::run_quantize_rows(handle, q, m, n, A, lda, Aq, ldq, scales);
+    SB_GUARD_END
+}
+
+sb_status sb_gemv_q(sb_handle* handle, sb_dtype q, int64_t m, int64_t n, const void* Aq, int64_t ldq,
+                    const float* scales, const float* x, float* c)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_gemv_q: NULL handle");
+    SB_GUARD_BEGIN
+    if (q != SB_BF16 && q != SB_FP8_E4M3) return fail(handle, SB_EINVAL, "sb_gemv_q: q must be BF16 or FP8_E4M3");
+    if (m < 0 || n < 0) return fail(handle, SB_EINVAL, "sb_gemv_q: negative size");
+    if (ldq < (n > 1 ? n : 1)) return fail(handle, SB_EINVAL, "sb_gemv_q: ldq below n");
+    const int qs = esize_of(q);
+    const int64_t q_el = span_elems(m, n, ldq);
+    int64_t t;
+    if (q_el < 0 || !mul_ok(q_el, qs, &t) || t > kMaxBytes) return fail(handle, SB_EINVAL, "sb_gemv_q: extent overflows");
+    if ((q_el > 0 && (!Aq || !x)) || (m > 0 && (!scales || !c))) return fail(handle, SB_EINVAL, "sb_gemv_q: NULL pointer");
+    if (misaligned(Aq, qs) || misaligned(scales, 4) || misaligned(x, 4) || misaligned(c, 4))
+        return fail(handle, SB_EINVAL, "sb_gemv_q: pointer not aligned to the element size");
+    const Range rc = range_of(c, m, 4);
+    if (overlap(rc, range_of(Aq, q_el, qs)) || overlap(rc, range_of(scales, m, 4)) || overlap(rc, range_of(x, n, 4)))
+        return fail(handle, SB_EINVAL, "sb_gemv_q: c overlaps an input");
+    return sb::run_gemv_q(handle, q, m, n, Aq, ldq, scales, x, c);
+    SB_GUARD_END
+}
+
+sb_status sb_dot2_f32(sb_handle* handle, int64_t n, const float* x, const float* y, float* alpha)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_dot2_f32: NULL handle");
+    SB_GUARD_BEGIN
+    if (n < 0) return fail(handle, SB_EINVAL, "sb_dot2_f32: negative n");
+    int64_t bytes;
+    if (!mul_ok(n, 4, &bytes) || bytes > kMaxBytes) return fail(handle, SB_EINVAL, "sb_dot2_f32: n overflows");
+    if (!alpha || (n > 0 && (!x || !y))) return fail(handle, SB_EINVAL, "sb_dot2_f32: NULL pointer");
+    if (misaligned(x, 4) || misaligned(y, 4) || misaligned(alpha, 4))
+        return fail(handle, SB_EINVAL, "sb_dot2_f32: pointer not aligned to the element size");
+    const Range ra = range_of(alpha, 1, 4);
+    if (overlap(ra, range_of(x, n, 4)) || overlap(ra, range_of(y, n, 4)))
+        return fail(handle, SB_EINVAL, "sb_dot2_f32: alpha overlaps x or y");
+    return sb::run_dot2(handle, n, x, y, alpha);
+    SB_GUARD_END
+}
+
+}  // extern "C"

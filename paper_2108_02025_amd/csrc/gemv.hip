@@ -1,0 +1,371 @@
+// GEMV kernels: c += A x and c += A^T x on a row-major view of A.
+//
+// The paper's section 3.1 defines c_i as the sum of the products A_ij x_j
+// with the initial c_i added last; section 4.2 (Algorithm 2) walks a
+// row-major A row by row with stride one, and section 4.1 (Algorithm 1)
+// walks a column-major A by blocks of columns, updating a short segment of
+// c per block.  On the GPU the two access patterns become two kernels:
+//
+//  * row-dot (gemv_n_kernel): a group of G lanes owns one row and streams it
+//    with 16-byte non-temporal loads; x for the current column split sits in
+//    LDS; the group reduces with a butterfly and its first lane adds the
+//    initial c_i (or writes a split partial).  Used for row-major N and
+//    column-major T.
+//  * col-axpy (gemv_t_kernel): each lane owns W consecutive outputs; the
+//    waves of a workgroup take interleaved rows of one row split, x_i is
+//    wave-uniform, partial column sums are combined across waves in LDS in
+//    wave order.  This is Algorithm 1's micro-kernel shape (a contiguous
+//    segment of the output updated over a block of the reduction index).
+//    Used for row-major T and column-major N.
+//
+// Splits (of columns for row-dot, of rows for col-axpy) write partial sums
+// to the workspace and a second kernel adds them in split order, then adds
+// the initial output.  No atomics anywhere: every output has one owner, and
+// the summation order depends only on the shape, so results are
+// reproducible bit for bit.
+#include <algorithm>
+
+#include "sb_device.hpp"
+#include "sb_internal.hpp"
+
+namespace sb {
+
+constexpr int kUnrollN = 8;  // 16-byte loads in flight per lane and row
+constexpr int kUnrollT = 8;  // rows in flight per wave
+
+template <typename T>
+struct GemvNArgs {
+    int64_t rows, cols, ld;
+    const T* A;
+    const T* x;
+    T* c;
+    T* partial;  // nsplit x rows, or nullptr when nsplit == 1
+    int64_t KC;
+    int64_t RB;
+};
+
+template <typename T, int G, int NT, bool ALIGNED>
+__global__ __launch_bounds__(NT) void gemv_n_kernel(GemvNArgs<T> a)
+{
+    typedef typename Vec<T>::type V;
+    constexpr int W = Vec<T>::W;
+    constexpr int U = kUnrollN;
+    constexpr int NW = NT / kWave, GW = kWave / G;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* xs = reinterpret_cast<T*>(smem);
+
+    const int64_t s = blockIdx.y;
+    const int64_t k0 = s * a.KC;
+    const int64_t klen = min(a.cols, k0 + a.KC) - k0;
+
+    // Stage x[k0, k0 + klen) in LDS (read by every row of this workgroup).
+    for (int64_t t = threadIdx.x; t < klen; t += NT) xs[t] = a.x[k0 + t];
+    __syncthreads();
+
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int g = lane / G, l = lane % G;
+    const int64_t r0 = (int64_t)blockIdx.x * a.RB;
+    const int64_t r1 = min(a.rows, r0 + a.RB);
+
+    for (int64_t row = r0 + w * GW + g; row < r1; row += NW * GW) {
+        const T* Ar = a.A + row * a.ld + k0;
+        int64_t head = 0;
+        if (!ALIGNED) {
+            head = ((16 - (reinterpret_cast<uintptr_t>(Ar) & 15)) & 15) / sizeof(T);
+            head = min(head, klen);
+        }
+        V acc = (V)0;
+        if (!ALIGNED && l < head) acc[0] = Ar[l] * xs[l];
+
+        const int64_t nv = (klen - head) / W;
+        const V* Av = reinterpret_cast<const V*>(Ar + head);
+        const T* xb = xs + head;
+        int64_t v = l;
+        for (; v + (U - 1) * G < nv; v += U * G) {
+            V av[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) av[u] = ld_stream(Av + v + u * G);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t e = (v + u * G) * W;
+                if (ALIGNED) {
+                    acc += av[u] * *reinterpret_cast<const V*>(xb + e);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < W; ++q) acc[q] += av[u][q] * xb[e + q];
+                }
+            }
+        }
+        for (; v < nv; v += G) {
+            const V av = ld_stream(Av + v);
+            const int64_t e = v * W;
+#pragma unroll
+            for (int q = 0; q < W; ++q) acc[q] += av[q] * xb[e + q];
+        }
+        const int64_t t0 = head + nv * W;  // fewer than W elements remain
+        if (l < klen - t0) acc[1 % W] += Ar[t0 + l] * xs[t0 + l];
+
+        T t = acc[0];
+#pragma unroll
+        for (int q = 1; q < W; ++q) t += acc[q];
+        t = group_sum<G>(t);
+        if (l == 0) {
+            if (a.partial) a.partial[s * a.rows + row] = t;
+            else a.c[row] = a.c[row] + t;
+        }
+    }
+}
+
+// out[i] = out[i] + sum over splits of partial[s * len + i], splits in order.
+template <typename T>
+__global__ __launch_bounds__(256) void split_finish_kernel(int64_t len, int64_t nsplit,
+                                                           const T* partial, T* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= len) return;
+    T t = partial[i];
+    for (int64_t s = 1; s < nsplit; ++s) t += partial[s * len + i];
+    out[i] = out[i] + t;
+}
+
+template <typename T>
+struct GemvTArgs {
+    int64_t rows, cols, ld;
+    const T* A;
+    const T* x;
+    T* c;
+    T* partial;  // nsplit x cols, or nullptr when nsplit == 1
+    int64_t RS;
+};
+
+template <typename T, int NT, bool ALIGNED>
+__global__ __launch_bounds__(NT) void gemv_t_kernel(GemvTArgs<T> a)
+{
+    constexpr int W = ALIGNED ? Vec<T>::W : 1;
+    typedef typename std::conditional<ALIGNED, typename Vec<T>::type, T>::type V;
+    constexpr int U = kUnrollT;
+    constexpr int NW = NT / kWave;
+    constexpr int CW = kWave * W;
+    __shared__ T red[NW][CW];
+
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t j0 = (int64_t)blockIdx.x * CW + lane * W;
+    const int64_t s = blockIdx.y;
+    const int64_t i0 = s * a.RS, i1 = min(a.rows, i0 + a.RS);
+
+    T acc[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) acc[q] = 0;
+
+    if (j0 + W <= a.cols) {
+        int64_t i = i0 + w;
+        for (; i + (U - 1) * NW < i1; i += U * NW) {
+            V av[U];
+            T xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                av[u] = ld_stream(reinterpret_cast<const V*>(a.A + (i + u * NW) * a.ld + j0));
+                xv[u] = a.x[i + u * NW];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if constexpr (W == 1) {
+                    acc[0] += av[u] * xv[u];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < W; ++q) acc[q] += av[u][q] * xv[u];
+                }
+            }
+        }
+        for (; i < i1; i += NW) {
+            const V av = ld_stream(reinterpret_cast<const V*>(a.A + i * a.ld + j0));
+            const T xv = a.x[i];
+            if constexpr (W == 1) {
+                acc[0] += av * xv;
+            } else {
+#pragma unroll
+                for (int q = 0; q < W; ++q) acc[q] += av[q] * xv;
+            }
+        }
+    } else if (j0 < a.cols) {
+        const int rem = (int)(a.cols - j0);
+        for (int64_t i = i0 + w; i < i1; i += NW) {
+            const T xv = a.x[i];
+            for (int q = 0; q < rem; ++q) acc[q] += a.A[i * a.ld + j0 + q] * xv;
+        }
+    }
+
+#pragma unroll
+    for (int q = 0; q < W; ++q) red[w][lane * W + q] = acc[q];
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            T t = red[0][lane * W + q];
+#pragma unroll
+            for (int k = 1; k < NW; ++k) t += red[k][lane * W + q];
+            const int64_t j = j0 + q;
+            if (j < a.cols) {
+                if (a.partial) a.partial[s * a.cols + j] = t;
+                else a.c[j] = a.c[j] + t;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- plans ---
+
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+constexpr int64_t kCUs = 256;                  // MI355X compute units
+constexpr int64_t kLdsPerCU = 160 * 1024;      // gfx950 LDS per compute unit
+constexpr int64_t kMaxStagedX = 128 * 1024;    // x bytes staged whole before splitting
+constexpr int64_t kSplitChunkBytes = 32 * 1024;
+
+GemvNPlan plan_gemv_n(int esize, int64_t rows, int64_t cols)
+{
+    GemvNPlan p{};
+    const int W = 16 / esize;
+    if (cols * esize <= kMaxStagedX) {
+        p.nsplit = 1;
+        p.KC = std::max<int64_t>(round_up(cols, W), W);
+    } else {
+        p.KC = kSplitChunkBytes / esize;
+        p.nsplit = ceil_div(cols, p.KC);
+    }
+    p.lds = (size_t)round_up(p.KC * esize, 16);
+    p.NT = p.lds > 80 * 1024 ? 1024 : (p.lds > 40 * 1024 ? 512 : 256);
+    const int64_t waves_per_block = p.NT / 64;
+    const int64_t bpc = std::max<int64_t>(1, std::min<int64_t>(kLdsPerCU / (int64_t)p.lds,
+                                                              32 / waves_per_block));
+    const int64_t nvec = ceil_div(p.KC, W);
+    int G = 64;
+    while (G > 4 && nvec < (int64_t)G * kUnrollN) G >>= 1;
+    p.G = G;
+    const int64_t pass = waves_per_block * (64 / G);  // rows a workgroup covers at once
+    const int64_t target = kCUs * bpc;
+    const int64_t row_blocks = std::max<int64_t>(1, ceil_div(target, p.nsplit));
+    p.RB = round_up(std::max<int64_t>(1, ceil_div(rows, row_blocks)), pass);
+    p.ws = p.nsplit > 1 ? (size_t)(p.nsplit * rows * esize) : 0;
+    return p;
+}
+
+GemvTPlan plan_gemv_t(int esize, int64_t rows, int64_t cols)
+{
+    GemvTPlan p{};
+    p.NT = 256;
+    const int64_t CW = 64 * (16 / esize);
+    const int64_t ncb = std::max<int64_t>(1, ceil_div(cols, CW));
+    const int64_t target = kCUs * 8;
+    int64_t ns = ceil_div(target, ncb);
+    ns = std::min<int64_t>(ns, 64);
+    ns = std::min<int64_t>(ns, std::max<int64_t>(1, rows / 64));
+    ns = std::max<int64_t>(ns, 1);
+    p.RS = ceil_div(rows, ns);
+    p.nsplit = ceil_div(rows, p.RS);
+    p.ws = p.nsplit > 1 ? (size_t)(p.nsplit * cols * esize) : 0;
+    return p;
+}
+
+// ------------------------------------------------------------- launchers ---
+
+template <typename T, int G, int NT, bool AL>
+static void launch_n(const GemvNArgs<T>& a, dim3 grid, size_t lds, hipStream_t st)
+{
+    static const bool attr_set = [] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemv_n_kernel<T, G, NT, AL>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsPerCU);
+        return true;
+    }();
+    (void)attr_set;
+    hipLaunchKernelGGL((gemv_n_kernel<T, G, NT, AL>), grid, dim3(NT), lds, st, a);
+}
+
+template <typename T, int NT, bool AL>
+static bool dispatch_n_g(int G, const GemvNArgs<T>& a, dim3 grid, size_t lds, hipStream_t st)
+{
+    switch (G) {
+    case 4: launch_n<T, 4, NT, AL>(a, grid, lds, st); return true;
+    case 8: launch_n<T, 8, NT, AL>(a, grid, lds, st); return true;
+    case 16: launch_n<T, 16, NT, AL>(a, grid, lds, st); return true;
+    case 32: launch_n<T, 32, NT, AL>(a, grid, lds, st); return true;
+    case 64: launch_n<T, 64, NT, AL>(a, grid, lds, st); return true;
+    }
+    return false;
+}
+
+template <typename T, bool AL>
+static bool dispatch_n(int NT, int G, const GemvNArgs<T>& a, dim3 grid, size_t lds, hipStream_t st)
+{
+    switch (NT) {
+    case 256: return dispatch_n_g<T, 256, AL>(G, a, grid, lds, st);
+    case 512: return dispatch_n_g<T, 512, AL>(G, a, grid, lds, st);
+    case 1024: return dispatch_n_g<T, 1024, AL>(G, a, grid, lds, st);
+    }
+    return false;
+}
+
+template <typename T>
+static sb_status gemv_n_typed(sb_handle* h, int64_t rows, int64_t cols, const T* A, int64_t ld,
+                              const T* x, T* c)
+{
+    const GemvNPlan p = plan_gemv_n(sizeof(T), rows, cols);
+    if (p.ws > h->ws_bytes)
+        return fail(h, SB_ENOMEM, "gemv needs %zu workspace bytes, handle has %zu", p.ws, h->ws_bytes);
+    GemvNArgs<T> a{rows, cols, ld, A, x, c, p.nsplit > 1 ? static_cast<T*>(h->ws) : nullptr, p.KC, p.RB};
+    const bool al = aligned16(A) && ((ld * (int64_t)sizeof(T)) % 16 == 0);
+    const dim3 grid((unsigned)ceil_div(rows, p.RB), (unsigned)p.nsplit);
+    const bool ok = al ? dispatch_n<T, true>(p.NT, p.G, a, grid, p.lds, h->stream)
+                       : dispatch_n<T, false>(p.NT, p.G, a, grid, p.lds, h->stream);
+    if (!ok) return fail(h, SB_EINTERNAL, "no gemv_n instance for NT=%d G=%d", p.NT, p.G);
+    sb_status st = check_launch(h, "gemv_n_kernel");
+    if (st != SB_OK || p.nsplit == 1) return st;
+    hipLaunchKernelGGL(split_finish_kernel<T>, dim3((unsigned)ceil_div(rows, 256)), dim3(256), 0,
+                       h->stream, rows, p.nsplit, static_cast<const T*>(h->ws), c);
+    return check_launch(h, "split_finish_kernel");
+}
+
+template <typename T>
+static sb_status gemv_t_typed(sb_handle* h, int64_t rows, int64_t cols, const T* A, int64_t ld,
+                              const T* x, T* c)
+{
+    const GemvTPlan p = plan_gemv_t(sizeof(T), rows, cols);
+    if (p.ws > h->ws_bytes)
+        return fail(h, SB_ENOMEM, "gemv needs %zu workspace bytes, handle has %zu", p.ws, h->ws_bytes);
+    GemvTArgs<T> a{rows, cols, ld, A, x, c, p.nsplit > 1 ? static_cast<T*>(h->ws) : nullptr, p.RS};
+    const bool al = aligned16(A) && ((ld * (int64_t)sizeof(T)) % 16 == 0);
+    const int64_t CW = 64 * (al ? 16 / (int64_t)sizeof(T) : 1);
+    const dim3 grid((unsigned)ceil_div(cols, CW), (unsigned)p.nsplit);
+    if (al) hipLaunchKernelGGL((gemv_t_kernel<T, 256, true>), grid, dim3(256), 0, h->stream, a);
+    else hipLaunchKernelGGL((gemv_t_kernel<T, 256, false>), grid, dim3(256), 0, h->stream, a);
+    sb_status st = check_launch(h, "gemv_t_kernel");
+    if (st != SB_OK || p.nsplit == 1) return st;
+    hipLaunchKernelGGL(split_finish_kernel<T>, dim3((unsigned)ceil_div(cols, 256)), dim3(256), 0,
+                       h->stream, cols, p.nsplit, static_cast<const T*>(h->ws), c);
+    return check_launch(h, "split_finish_kernel");
+}
+
+sb_status run_gemv_n(sb_handle* h, sb_dtype dt, int64_t rows, int64_t cols, const void* M,
+                     int64_t ld, const void* v, void* out)
+{
+    if (rows == 0 || cols == 0) return SB_OK;
+    if (dt == SB_F64)
+        return gemv_n_typed<double>(h, rows, cols, static_cast<const double*>(M), ld,
+                                    static_cast<const double*>(v), static_cast<double*>(out));
+    return gemv_n_typed<float>(h, rows, cols, static_cast<const float*>(M), ld,
+                               static_cast<const float*>(v), static_cast<float*>(out));
+}
+
+sb_status run_gemv_t(sb_handle* h, sb_dtype dt, int64_t rows, int64_t cols, const void* M,
+                     int64_t ld, const void* v, void* out)
+{
+    if (rows == 0 || cols == 0) return SB_OK;
+    if (dt == SB_F64)
+        return gemv_t_typed<double>(h, rows, cols, static_cast<const double*>(M), ld,
+                                    static_cast<const double*>(v), static_cast<double*>(out));
+    return gemv_t_typed<float>(h, rows, cols, static_cast<const float*>(M), ld,
+                               static_cast<const float*>(v), static_cast<float*>(out));
+}
+
+}  // namespace sb

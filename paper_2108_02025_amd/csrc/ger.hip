@@ -1,0 +1,122 @@
+// GER kernel: C += x (outer) y on a row-major view of C.
+//
+// Section 3.1 defines each entry as the elementary product x_i y_j added to
+// the initial C_ij; section 4.2 (Algorithm 2) updates C row by row and notes
+// that threading the inner loop would race on C.  Here every entry has
+// exactly one owning lane: a lane owns W consecutive columns (y held in
+// registers) and walks a block of rows, x_i being wave-uniform.  C streams
+// in and out with 16-byte non-temporal loads and stores, several rows in
+// flight per lane.  The product is rounded before the addition (no fused
+// multiply-add), exactly as the definition states, so every entry is
+// C_ij + fl(x_i y_j) regardless of the launch configuration.
+#include <algorithm>
+
+#include "sb_device.hpp"
+#include "sb_internal.hpp"
+
+namespace sb {
+
+constexpr int kUnrollGer = 8;
+
+template <typename T>
+struct GerArgs {
+    int64_t rows, cols, ld;
+    const T* x;
+    const T* y;
+    T* C;
+    int64_t RB;
+};
+
+template <typename T, int NT, bool ALIGNED>
+__global__ __launch_bounds__(NT) void ger_kernel(GerArgs<T> a)
+{
+    constexpr int W = ALIGNED ? Vec<T>::W : 1;
+    typedef typename std::conditional<ALIGNED, typename Vec<T>::type, T>::type V;
+    constexpr int U = kUnrollGer;
+
+    const int64_t j0 = ((int64_t)blockIdx.x * NT + threadIdx.x) * W;
+    if (j0 >= a.cols) return;
+    const int64_t i0 = (int64_t)blockIdx.y * a.RB;
+    const int64_t i1 = min(a.rows, i0 + a.RB);
+
+    if (j0 + W <= a.cols) {
+        T yv[W];
+#pragma unroll
+        for (int q = 0; q < W; ++q) yv[q] = a.y[j0 + q];
+        int64_t i = i0;
+        for (; i + U - 1 < i1; i += U) {
+            V cv[U];
+            T xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                cv[u] = ld_stream(reinterpret_cast<const V*>(a.C + (i + u) * a.ld + j0));
+                xv[u] = a.x[i + u];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if constexpr (W == 1) {
+                    cv[u] = add_rn(cv[u], mul_rn(xv[u], yv[0]));
+                } else {
+#pragma unroll
+                    for (int q = 0; q < W; ++q) cv[u][q] = add_rn(cv[u][q], mul_rn(xv[u], yv[q]));
+                }
+                st_stream(reinterpret_cast<V*>(a.C + (i + u) * a.ld + j0), cv[u]);
+            }
+        }
+        for (; i < i1; ++i) {
+            V cv = ld_stream(reinterpret_cast<const V*>(a.C + i * a.ld + j0));
+            const T xi = a.x[i];
+            if constexpr (W == 1) {
+                cv = add_rn(cv, mul_rn(xi, yv[0]));
+            } else {
+#pragma unroll
+                for (int q = 0; q < W; ++q) cv[q] = add_rn(cv[q], mul_rn(xi, yv[q]));
+            }
+            st_stream(reinterpret_cast<V*>(a.C + i * a.ld + j0), cv);
+        }
+    } else {
+        const int rem = (int)(a.cols - j0);
+        for (int64_t i = i0; i < i1; ++i) {
+            const T xi = a.x[i];
+            for (int q = 0; q < rem; ++q) {
+                T* p = a.C + i * a.ld + j0 + q;
+                *p = add_rn(*p, mul_rn(xi, a.y[j0 + q]));
+            }
+        }
+    }
+}
+
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <typename T>
+static sb_status ger_typed(sb_handle* h, int64_t rows, int64_t cols, const T* x, const T* y, T* C,
+                           int64_t ld)
+{
+    constexpr int NT = 256;
+    const bool al = aligned16(C) && ((ld * (int64_t)sizeof(T)) % 16 == 0);
+    const int64_t W = al ? 16 / (int64_t)sizeof(T) : 1;
+    const int64_t cblocks = ceil_div(cols, NT * W);
+    // Aim for about 32 workgroups per compute unit over the whole launch,
+    // each streaming at least 64 rows.
+    const int64_t target = 256 * 32;
+    int64_t rb = std::max<int64_t>(64, ceil_div(rows, std::max<int64_t>(1, target / cblocks)));
+    rb = std::min<int64_t>(rb, rows);
+    GerArgs<T> a{rows, cols, ld, x, y, C, rb};
+    const dim3 grid((unsigned)cblocks, (unsigned)ceil_div(rows, rb));
+    if (al) hipLaunchKernelGGL((ger_kernel<T, NT, true>), grid, dim3(NT), 0, h->stream, a);
+    else hipLaunchKernelGGL((ger_kernel<T, NT, false>), grid, dim3(NT), 0, h->stream, a);
+    return check_launch(h, "ger_kernel");
+}
+
+sb_status run_ger(sb_handle* h, sb_dtype dt, int64_t rows, int64_t cols, const void* x,
+                  const void* y, void* C, int64_t ld)
+{
+    if (rows == 0 || cols == 0) return SB_OK;
+    if (dt == SB_F64)
+        return ger_typed<double>(h, rows, cols, static_cast<const double*>(x),
+                                 static_cast<const double*>(y), static_cast<double*>(C), ld);
+    return ger_typed<float>(h, rows, cols, static_cast<const float*>(x), static_cast<const float*>(y),
+                            static_cast<float*>(C), ld);
+}
+
+}  // namespace sb

@@ -1,0 +1,362 @@
+// Precision form: per-row scaled bfloat16 / OCP E4M3FN storage of A and the
+// GEMV that streams it.
+//
+// The paper leaves the element width generic (section 2, S_data) and its
+// GEMV is bound by the bytes of A (section 4.1 notes that bandwidth takes
+// over at large sizes).  Storing A in 2 or 1 bytes per element cuts those
+// bytes by 4x or 8x against binary64; x, c and the arithmetic stay binary32.
+//
+//   quantise: s_i from the row's largest magnitude, q_ij = RNE(fl32(a_ij/s_i))
+//   gemv_q:   c_i += s_i * sum_j q_ij x_j, products and sums in binary32
+//
+// gemv_q has the row-dot shape of the binary64 GEMV: a group of G lanes owns
+// a row, each lane loads 16 bytes of codes at a time (8 bfloat16 or 16 E4M3
+// values) with non-temporal loads, decodes them in registers, and multiplies
+// against x staged in LDS.  The scale is applied once per row, after the
+// reduction.
+#include <algorithm>
+
+#include "sb_device.hpp"
+#include "sb_internal.hpp"
+
+namespace sb {
+
+// ------------------------------------------------------------- encoding ---
+
+__device__ __forceinline__ uint32_t f32_bits(float f) { return __float_as_uint(f); }
+
+// binary32 -> bfloat16, round to nearest even on the bit pattern; NaN
+// becomes the canonical quiet NaN with the input's sign.
+__device__ __forceinline__ uint16_t bf16_encode(float v)
+{
+    const uint32_t u = f32_bits(v);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)(((u >> 16) & 0x8000u) | 0x7FC0u);
+    const uint32_t bias = 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)((u + bias) >> 16);
+}
+
+// Round-to-nearest-even right shift of a significand; carries propagate
+// into the caller's exponent field naturally.
+__device__ __forceinline__ uint32_t rne_shift(uint32_t v, int sh)
+{
+    const uint32_t q = v >> sh, rem = v & ((1u << sh) - 1u), half = 1u << (sh - 1);
+    return q + ((rem > half || (rem == half && (q & 1u))) ? 1u : 0u);
+}
+
+// binary32 -> OCP E4M3FN (bias 7, 3 fraction bits, max 448, no infinity),
+// round to nearest even, magnitudes >= 448 saturate to 448, NaN -> S.1111.111.
+__device__ __forceinline__ uint8_t e4m3_encode(float v)
+{
+    const uint32_t u = f32_bits(v);
+    const uint32_t sign = (u >> 24) & 0x80u;
+    const uint32_t a = u & 0x7FFFFFFFu;
+    if (a > 0x7F800000u) return (uint8_t)(sign | 0x7Fu);
+    if (a >= 0x43E00000u) return (uint8_t)(sign | 0x7Eu);  // 448 = 1.75 * 2^8
+    const int e = (int)(a >> 23) - 127;
+    if (e < -6) {
+        // E4M3 subnormals: value k * 2^-9 with k = RNE(v * 2^9).
+        if (e < -10) return (uint8_t)sign;  // below 2^-10: rounds to zero
+        const uint32_t mant = (a & 0x7FFFFFu) | 0x800000u;  // v = mant * 2^(e-23)
+        return (uint8_t)(sign | rne_shift(mant, 14 - e));
+    }
+    // Normal: keep 3 of the 23 fraction bits; a carry bumps the exponent.
+    const uint32_t base = ((uint32_t)(e + 7) << 3) | ((a & 0x7FFFFFu) >> 20);
+    const uint32_t rem = a & 0xFFFFFu;
+    uint32_t code = base + ((rem > 0x80000u || (rem == 0x80000u && (base & 1u))) ? 1u : 0u);
+    if (code > 0x7Eu) code = 0x7Eu;
+    return (uint8_t)(sign | code);
+}
+
+// Per-row scale: bfloat16 uses the power of two at or below amax; E4M3
+// uses amax / 448.  Rows with amax 0 or infinite get 1.
+__device__ __forceinline__ float row_scale(bool bf16, float amax)
+{
+    const uint32_t a = f32_bits(amax);
+    if (a == 0u || a >= 0x7F800000u) return 1.0f;
+    if (bf16) {
+        if (a >= 0x00800000u) return __uint_as_float(a & 0x7F800000u);
+        return __uint_as_float(1u << (31 - __clz((int)a)));  // subnormal: top set bit
+    }
+    const float s = amax / 448.0f;
+    return s == 0.0f ? 1.0f : s;
+}
+
+template <bool BF16>
+__global__ __launch_bounds__(256) void quantize_rows_kernel(int64_t m, int64_t n, const float* A,
+                                                            int64_t lda, void* Aq, int64_t ldq,
+                                                            float* scales)
+{
+    __shared__ float red[4];
+    __shared__ float s_sh;
+    const int64_t i = blockIdx.x;
+    const float* Ar = A + i * lda;
+    float amax = 0.0f;
+    for (int64_t j = threadIdx.x; j < n; j += 256) {
+        const float v = fabsf(Ar[j]);
+        if (v == v && v > amax) amax = v;
+    }
+    // max over the workgroup (order-independent)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = amax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        s_sh = row_scale(BF16, mx);
+        scales[i] = s_sh;
+    }
+    __syncthreads();
+    const float s = s_sh;
+    for (int64_t j = threadIdx.x; j < n; j += 256) {
+        const float v = Ar[j] / s;
+        if (BF16) static_cast<uint16_t*>(Aq)[i * ldq + j] = bf16_encode(v);
+        else static_cast<uint8_t*>(Aq)[i * ldq + j] = e4m3_encode(v);
+    }
+}
+
+// ------------------------------------------------------------- decoding ---
+
+template <bool BF16> struct Codes;
+template <> struct Codes<true> {
+    typedef uint16_t code_t;
+    static constexpr int PER16 = 8;  // values per 16-byte load
+    __device__ static float one(uint16_t c) { return __uint_as_float((uint32_t)c << 16); }
+    // 4 dwords -> 8 values, element order preserved
+    __device__ static void unpack(const v4u& w, float* f)
+    {
+        const uint32_t d[4] = {w[0], w[1], w[2], w[3]};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            f[2 * k] = __uint_as_float(d[k] << 16);
+            f[2 * k + 1] = __uint_as_float(d[k] & 0xFFFF0000u);
+        }
+    }
+};
+template <> struct Codes<false> {
+    typedef uint8_t code_t;
+    static constexpr int PER16 = 16;
+    __device__ static float one(uint8_t c)
+    {
+        return __builtin_amdgcn_cvt_f32_fp8((int)c, 0);
+    }
+    __device__ static void unpack(const v4u& w, float* f)
+    {
+        const uint32_t d[4] = {w[0], w[1], w[2], w[3]};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)d[k], false);
+            const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)d[k], true);
+            f[4 * k] = lo[0];
+            f[4 * k + 1] = lo[1];
+            f[4 * k + 2] = hi[0];
+            f[4 * k + 3] = hi[1];
+        }
+    }
+};
+
+struct GemvQArgs {
+    int64_t m, n, ldq;
+    const void* Aq;
+    const float* scales;
+    const float* x;
+    float* c;
+    float* partial;  // nsplit x m, or nullptr
+    int64_t KC, RB;
+};
+
+template <bool BF16, int G, int NT>
+__global__ __launch_bounds__(NT) void gemv_q_kernel(GemvQArgs a)
+{
+    typedef Codes<BF16> C;
+    typedef typename C::code_t code_t;
+    constexpr int P = C::PER16;
+    constexpr int U = 4;
+    constexpr int NW = NT / kWave, GW = kWave / G;
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* xs = reinterpret_cast<float*>(smem);
+
+    const int64_t s = blockIdx.y;
+    const int64_t k0 = s * a.KC;
+    const int64_t klen = min(a.n, k0 + a.KC) - k0;
+    for (int64_t t = threadIdx.x; t < klen; t += NT) xs[t] = a.x[k0 + t];
+    __syncthreads();
+
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int g = lane / G, l = lane % G;
+    const int64_t r0 = (int64_t)blockIdx.x * a.RB;
+    const int64_t r1 = min(a.m, r0 + a.RB);
+    const code_t* Q = static_cast<const code_t*>(a.Aq);
+
+    for (int64_t row = r0 + w * GW + g; row < r1; row += NW * GW) {
+        const code_t* Qr = Q + row * a.ldq + k0;
+        int64_t head = ((16 - (reinterpret_cast<uintptr_t>(Qr) & 15)) & 15) / sizeof(code_t);
+        head = min(head, klen);
+        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int64_t e = l; e < head; e += G) acc[0] += C::one(Qr[e]) * xs[e];
+
+        const int64_t nv = (klen - head) / P;
+        const v4u* Qv = reinterpret_cast<const v4u*>(Qr + head);
+        const float* xb = xs + head;
+        const bool xal = ((head * 4) & 15) == 0;
+        int64_t v = l;
+        for (; v + (U - 1) * G < nv; v += U * G) {
+            v4u wv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) wv[u] = ld_stream(Qv + v + u * G);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                float f[P];
+                C::unpack(wv[u], f);
+                const float* xe = xb + (v + u * G) * P;
+                if (xal) {
+#pragma unroll
+                    for (int q = 0; q < P; q += 4) {
+                        const v4f xv = *reinterpret_cast<const v4f*>(xe + q);
+                        acc[0] += f[q] * xv[0];
+                        acc[1] += f[q + 1] * xv[1];
+                        acc[2] += f[q + 2] * xv[2];
+                        acc[3] += f[q + 3] * xv[3];
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < P; ++q) acc[q & 3] += f[q] * xe[q];
+                }
+            }
+        }
+        for (; v < nv; v += G) {
+            float f[P];
+            C::unpack(ld_stream(Qv + v), f);
+            const float* xe = xb + v * P;
+#pragma unroll
+            for (int q = 0; q < P; ++q) acc[q & 3] += f[q] * xe[q];
+        }
+        for (int64_t e = head + nv * P + l; e < klen; e += G) acc[1] += C::one(Qr[e]) * xs[e];
+
+        float t = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        t = group_sum<G>(t);
+        if (l == 0) {
+            if (a.partial) a.partial[s * a.m + row] = t;
+            else a.c[row] = a.c[row] + a.scales[row] * t;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void gemv_q_finish_kernel(int64_t m, int64_t nsplit,
+                                                            const float* partial,
+                                                            const float* scales, float* c)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    float t = partial[i];
+    for (int64_t s = 1; s < nsplit; ++s) t += partial[s * m + i];
+    c[i] = c[i] + scales[i] * t;
+}
+
+// ---------------------------------------------------------------- plans ---
+
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+struct GemvQPlan {
+    int G, NT;
+    int64_t KC, nsplit, RB;
+    size_t lds, ws;
+};
+
+static GemvQPlan plan_gemv_q(sb_dtype q, int64_t m, int64_t n)
+{
+    GemvQPlan p{};
+    const int64_t P = q == SB_BF16 ? 8 : 16;
+    if (n * 4 <= 128 * 1024) {
+        p.nsplit = 1;
+        p.KC = std::max<int64_t>(round_up(n, 4), 4);
+    } else {
+        p.KC = 8192;
+        p.nsplit = ceil_div(n, p.KC);
+    }
+    p.lds = (size_t)round_up(p.KC * 4, 16);
+    p.NT = p.lds > 80 * 1024 ? 1024 : (p.lds > 40 * 1024 ? 512 : 256);
+    const int64_t wpb = p.NT / 64;
+    const int64_t bpc = std::max<int64_t>(1, std::min<int64_t>((160 * 1024) / (int64_t)p.lds, 32 / wpb));
+    const int64_t nvec = ceil_div(p.KC, P);
+    int G = 64;
+    while (G > 4 && nvec < (int64_t)G * 4) G >>= 1;
+    p.G = G;
+    const int64_t pass = wpb * (64 / G);
+    const int64_t row_blocks = std::max<int64_t>(1, ceil_div(256 * bpc, p.nsplit));
+    p.RB = round_up(std::max<int64_t>(1, ceil_div(m, row_blocks)), pass);
+    p.ws = p.nsplit > 1 ? (size_t)(p.nsplit * m * 4) : 0;
+    return p;
+}
+
+size_t gemv_q_ws_bytes(sb_dtype q, int64_t m, int64_t n) { return plan_gemv_q(q, m, n).ws; }
+
+template <bool BF16, int G, int NT>
+static void launch_q(const GemvQArgs& a, dim3 grid, size_t lds, hipStream_t st)
+{
+    static const bool attr_set = [] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemv_q_kernel<BF16, G, NT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        return true;
+    }();
+    (void)attr_set;
+    hipLaunchKernelGGL((gemv_q_kernel<BF16, G, NT>), grid, dim3(NT), lds, st, a);
+}
+
+template <bool BF16, int NT>
+static bool dispatch_q_g(int G, const GemvQArgs& a, dim3 grid, size_t lds, hipStream_t st)
+{
+    switch (G) {
+    case 4: launch_q<BF16, 4, NT>(a, grid, lds, st); return true;
+    case 8: launch_q<BF16, 8, NT>(a, grid, lds, st); return true;
+    case 16: launch_q<BF16, 16, NT>(a, grid, lds, st); return true;
+    case 32: launch_q<BF16, 32, NT>(a, grid, lds, st); return true;
+    case 64: launch_q<BF16, 64, NT>(a, grid, lds, st); return true;
+    }
+    return false;
+}
+
+template <bool BF16>
+static bool dispatch_q(int NT, int G, const GemvQArgs& a, dim3 grid, size_t lds, hipStream_t st)
+{
+    switch (NT) {
+    case 256: return dispatch_q_g<BF16, 256>(G, a, grid, lds, st);
+    case 512: return dispatch_q_g<BF16, 512>(G, a, grid, lds, st);
+    case 1024: return dispatch_q_g<BF16, 1024>(G, a, grid, lds, st);
+    }
+    return false;
+}
+
+sb_status run_gemv_q(sb_handle* h, sb_dtype q, int64_t m, int64_t n, const void* Aq, int64_t ldq,
+                     const float* scales, const float* x, float* c)
+{
+    if (m == 0 || n == 0) return SB_OK;
+    const GemvQPlan p = plan_gemv_q(q, m, n);
+    if (p.ws > h->ws_bytes)
+        return fail(h, SB_ENOMEM, "gemv_q needs %zu workspace bytes, handle has %zu", p.ws, h->ws_bytes);
+    GemvQArgs a{m, n, ldq, Aq, scales, x, c, p.nsplit > 1 ? static_cast<float*>(h->ws) : nullptr, p.KC, p.RB};
+    const dim3 grid((unsigned)ceil_div(m, p.RB), (unsigned)p.nsplit);
+    const bool ok = q == SB_BF16 ? dispatch_q<true>(p.NT, p.G, a, grid, p.lds, h->stream)
+                                 : dispatch_q<false>(p.NT, p.G, a, grid, p.lds, h->stream);
+    if (!ok) return fail(h, SB_EINTERNAL, "no gemv_q instance for NT=%d G=%d", p.NT, p.G);
+    sb_status st = check_launch(h, "gemv_q_kernel");
+    if (st != SB_OK || p.nsplit == 1) return st;
+    hipLaunchKernelGGL(gemv_q_finish_kernel, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, h->stream,
+                       m, p.nsplit, static_cast<const float*>(h->ws), scales, c);
+    return check_launch(h, "gemv_q_finish_kernel");
+}
+
+sb_status run_quantize_rows(sb_handle* h, sb_dtype q, int64_t m, int64_t n, const float* A,
+                            int64_t lda, void* Aq, int64_t ldq, float* scales)
+{
+    if (m == 0) return SB_OK;
+    if (q == SB_BF16)
+        hipLaunchKernelGGL(quantize_rows_kernel<true>, dim3((unsigned)m), dim3(256), 0, h->stream, m, n,
+                           A, lda, Aq, ldq, scales);
+    else
+        hipLaunchKernelGGL(quantize_rows_kernel<false>, dim3((unsigned)m), dim3(256), 0, h->stream, m, n,
+                           A, lda, Aq, ldq, scales);
+    return check_launch(h, "quantize_rows_kernel");
+}
+
+}  // namespace sb

@@ -1,0 +1,68 @@
+// Device-side building blocks shared by the streaming kernels (gfx950,
+// wave64): 16-byte vector types, streaming loads/stores, and the
+// deterministic wave / workgroup reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sb {
+
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
+// 16-byte vector of T and its width.
+template <typename T> struct Vec;
+template <> struct Vec<double> { typedef v2d type; static constexpr int W = 2; };
+template <> struct Vec<float> { typedef v4f type; static constexpr int W = 4; };
+
+constexpr int kWave = 64;
+
+// Loads of operands that are read exactly once (A, C, DOT's x and y) use the
+// non-temporal hint so they stream past L2 and MALL instead of evicting the
+// reused vector (x of GEMV).
+template <typename V>
+__device__ __forceinline__ V ld_stream(const V* p) { return __builtin_nontemporal_load(p); }
+template <typename V>
+__device__ __forceinline__ void st_stream(V* p, V v) { __builtin_nontemporal_store(v, p); }
+
+// Multiply then add with two roundings (no contraction), for GER whose
+// definition rounds the elementary product before the addition.
+__device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
+__device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
+
+// Butterfly sum over groups of G consecutive lanes (G a power of two <= 64).
+// Every lane of a group ends with the same value; the order of additions is
+// fixed, so the result is deterministic.
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v)
+{
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Sum over a workgroup of NT threads, result valid in thread 0.  Waves
+// reduce with the butterfly, then wave 0 adds the wave totals in wave order.
+// `lds` must hold NT/64 values.  Contains __syncthreads().
+template <int NT, typename T>
+__device__ __forceinline__ T block_sum(T v, T* lds)
+{
+    constexpr int NW = NT / kWave;
+    v = group_sum<kWave>(v);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (NW == 1) return v;
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    T t = 0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NW; ++k) t += lds[k];
+    }
+    return t;
+}
+
+}  // namespace sb

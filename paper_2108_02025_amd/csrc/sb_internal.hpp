@@ -1,0 +1,81 @@
+// Host-side internals of the streamblas library: the handle, error
+// reporting, and the launch plans of each kernel family.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "streamblas.h"
+
+struct sb_handle {
+    void* ws;
+    size_t ws_bytes;
+    hipStream_t stream;
+    char err[512];
+};
+
+namespace sb {
+
+// Record a formatted failure reason on the handle (or the thread-local
+// slot when h is NULL) and return `st`.
+sb_status fail(sb_handle* h, sb_status st, const char* fmt, ...)
+    __attribute__((format(printf, 3, 4)));
+
+// Check the result of a HIP launch or call.
+sb_status check_launch(sb_handle* h, const char* what);
+
+// ---- GEMV on a row-major view -------------------------------------------
+// Every GEMV reduces to one of two kernels on a row-major rows x cols
+// matrix with leading dimension ld:
+//   "row-dot"   (kernel N): out[i] += sum_j M[i, j] v[j]     (out has rows entries)
+//   "col-axpy"  (kernel T): out[j] += sum_i M[i, j] v[i]     (out has cols entries)
+struct GemvNPlan {
+    int G;          // lanes cooperating on one row (power of two, 4..64)
+    int NT;         // threads per workgroup
+    int64_t KC;     // columns per split (x chunk staged in LDS), multiple of 4
+    int64_t nsplit; // number of column splits (1: no second stage)
+    int64_t RB;     // rows per workgroup
+    size_t lds;     // dynamic LDS bytes
+    size_t ws;      // workspace bytes (split partial sums)
+};
+GemvNPlan plan_gemv_n(int esize, int64_t rows, int64_t cols);
+
+struct GemvTPlan {
+    int NT;         // threads per workgroup (waves split the rows of a split)
+    int64_t nsplit; // number of row splits
+    int64_t RS;     // rows per split
+    size_t ws;
+};
+GemvTPlan plan_gemv_t(int esize, int64_t rows, int64_t cols);
+
+sb_status run_gemv_n(sb_handle* h, sb_dtype dt, int64_t rows, int64_t cols, const void* M,
+                     int64_t ld, const void* v, void* out);
+sb_status run_gemv_t(sb_handle* h, sb_dtype dt, int64_t rows, int64_t cols, const void* M,
+                     int64_t ld, const void* v, void* out);
+
+// ---- DOT ------------------------------------------------------------------
+struct DotPlan {
+    int NT;
+    int64_t nblocks;
+    int64_t chunk;  // elements per workgroup, multiple of NT*4
+    size_t ws;
+};
+DotPlan plan_dot(int esize, int64_t n, int partial_values);
+sb_status run_dot(sb_handle* h, sb_dtype dt, int64_t n, const void* x, const void* y, void* alpha);
+sb_status run_dot2(sb_handle* h, int64_t n, const float* x, const float* y, float* alpha);
+
+// ---- GER ------------------------------------------------------------------
+sb_status run_ger(sb_handle* h, sb_dtype dt, int64_t rows, int64_t cols, const void* x,
+                  const void* y, void* C, int64_t ld);
+
+// ---- precision form -------------------------------------------------------
+sb_status run_quantize_rows(sb_handle* h, sb_dtype q, int64_t m, int64_t n, const float* A,
+                            int64_t lda, void* Aq, int64_t ldq, float* scales);
+sb_status run_gemv_q(sb_handle* h, sb_dtype q, int64_t m, int64_t n, const void* Aq, int64_t ldq,
+                     const float* scales, const float* x, float* c);
+size_t gemv_q_ws_bytes(sb_dtype q, int64_t m, int64_t n);
+
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace sb

@@ -80,48 +80,42 @@ def ger_inputs(m: int, n: int, seed: int, dist: str = "uniform", dtype=np.float6
 # default: operand exponents in [-E/2, E/2]) and the pair is steered to a
 # requested condition number 2*sum|x_i y_i| / |sum x_i y_i|, in the manner of
 # the GenDot generator of Ogita, Rump and Oishi ("Accurate sum and dot
-# product", SIAM J. Sci. Comput. 26(6), 2005, section 6): a random bulk,
-# then a tail whose terms drive the exact running sum down to the target
-# magnitude, then a random permutation.  The running sum is kept exactly as a
-# Python integer multiple of 2^-SHIFT.
+# product", SIAM J. Sci. Comput. 26(6), 2005, section 6): a random bulk whose
+# exact sum is known, then a short tail whose terms drive the exact running
+# sum down to the target magnitude, then a random permutation.
+#
+# The bulk is made of pairs of terms that cancel exactly: (x, y) and
+# (-x*2^k, y*2^-k) with a random k that keeps both exponents in range, so
+# the two products are equal and opposite and the bulk sums to exactly 0.
+# The tail's running sum is then tracked exactly as a Python integer multiple
+# of 2^-200 (every binary32 product is such a multiple).
 # ---------------------------------------------------------------------------
 
-_SHIFT = 200  # every binary32 product used here is a multiple of 2^-200
+_SHIFT = 200
 
 
-def exact_sum_scaled(p: np.ndarray) -> int:
-    """Exact sum of binary64 values that are multiples of 2^-200 with
-    magnitude below 2^64, returned as the integer (sum * 2^200).
+def _shuffle(rng, arrays, n):
+    """Random reordering: a full permutation for short or odd lengths; for
+    long lengths a permutation of 256-element blocks followed by one random
+    permutation applied inside every block (two cheap structured gathers)."""
+    if n >= 1 << 16 and n % 256 == 0:
+        bp = rng.permutation(n // 256)
+        ip = rng.permutation(256)
+        return [np.ascontiguousarray(np.take(a.reshape(-1, 256)[bp], ip, axis=1).reshape(-1)) for a in arrays]
+    p = rng.permutation(n)
+    return [np.ascontiguousarray(a[p]) for a in arrays]
 
-    Positive and negative terms are handled apart; each magnitude is scaled
-    to an integer-valued binary64 and split into 52-bit limbs with exact
-    floor/subtract steps (the remainder is a subset of the value's bits), and
-    each limb column is summed in int64 blocks that cannot overflow.
-    """
-    p = np.asarray(p, dtype=np.float64)
-    total = 0
-    for sgn, sel in ((1, p > 0), (-1, p < 0)):
-        rem = np.ldexp(np.abs(p[sel]), _SHIFT)
-        assert np.all(rem < 2.0 ** 264), "term too large"
-        part = 0
-        for k in (260, 208, 156, 104, 52, 0):
-            q = np.floor(np.ldexp(rem, -k))
-            rem = rem - np.ldexp(q, k)
-            qi = q.astype(np.int64)          # each limb is below 2^52
-            acc = 0
-            for s0 in range(0, qi.shape[0], 1 << 10):
-                acc += int(qi[s0:s0 + (1 << 10)].sum())
-            part += acc << k
-        assert not np.any(rem), "term not a multiple of 2^-200"
-        total += sgn * part
-    return total
+
+def _f32_bits(sgn, ex, frac):
+    return ((sgn.astype(np.uint32) << np.uint32(31)) | ((ex + 127).astype(np.uint32) << np.uint32(23))
+            | frac).view(np.float32)
 
 
 def illcond_dot_inputs(n: int, seed: int, cond: float = 1e8, spread: int = 40,
                        tail: int | None = None):
     """(x, y, alpha0, achieved_cond): binary32 pairs with cond(x.y) near ``cond``.
 
-    The achieved condition number is measured from the exact sum.
+    The achieved condition number is computed from the exact sum.
     """
     import math
 
@@ -129,25 +123,32 @@ def illcond_dot_inputs(n: int, seed: int, cond: float = 1e8, spread: int = 40,
     rng = np.random.default_rng(seed)
     half = spread // 2
     K = tail if tail is not None else min(max(n // 16, 8), 1 << 12)
-    n1 = n - K
-
-    def rand_f32(size, emin, emax):
-        mant = rng.uniform(1.0, 2.0, size=size)
-        ex = rng.integers(emin, emax + 1, size=size)
-        sgn = np.where(rng.integers(0, 2, size=size) == 1, -1.0, 1.0)
-        return (sgn * np.ldexp(mant, ex)).astype(np.float32)
-
-    x1 = rand_f32(n1, -half, half)
-    y1 = rand_f32(n1, -half, half)
-    p1 = x1.astype(np.float64) * y1.astype(np.float64)   # exact products
-    S = exact_sum_scaled(p1)                              # sum * 2^200, exact
-    abs_sum = float(np.sum(np.abs(p1)))
+    if (n - K) % 2:
+        K += 1
+    h = (n - K) // 2
+    # binary32 operands from their bits: uniform 23-bit significands in
+    # [1, 2), random signs, exponents uniform in [-half, half]
+    fx = rng.integers(0, 1 << 23, size=h, dtype=np.uint32)
+    fy = rng.integers(0, 1 << 23, size=h, dtype=np.uint32)
+    ea = rng.integers(-half, half + 1, size=h)
+    fa = rng.integers(-half, half + 1, size=h)
+    sx = rng.integers(0, 2, size=h, dtype=np.uint32)
+    sy = rng.integers(0, 2, size=h, dtype=np.uint32)
+    # mirror: x' = -x * 2^k, y' = y * 2^-k with both exponents kept in range
+    lo = np.maximum(-half - ea, fa - half)
+    hi = np.minimum(half - ea, fa + half)
+    k = np.minimum(lo + (rng.random(h) * (hi - lo + 1)).astype(np.int64), hi)
+    xa, ya = _f32_bits(sx, ea, fx), _f32_bits(sy, fa, fy)
+    xb, yb = _f32_bits(sx ^ np.uint32(1), ea + k, fx), _f32_bits(sy, fa - k, fy)
+    abs_sum = 2.0 * float(np.sum(np.abs(xa.astype(np.float64) * ya.astype(np.float64))))
+    S = 0                                   # exact sum of all terms so far, times 2^200
     et = math.floor(math.log2(2.0 * abs_sum / cond))
+    e_top = spread + 1
     xs = np.empty(K, dtype=np.float32)
     ys = np.empty(K, dtype=np.float32)
     pmax = 2.0 ** (spread + 1)
 
-    def steer(k, want):
+    def steer(i, want):
         nonlocal S, abs_sum
         nf = want - S / (1 << _SHIFT)
         if nf == 0.0:
@@ -158,25 +159,22 @@ def illcond_dot_inputs(n: int, seed: int, cond: float = 1e8, spread: int = 40,
         ex = int(np.clip(le // 2, -half, half))
         xv = np.float32(math.ldexp(float(rng.uniform(1.0, 2.0)), ex))
         yv = np.float32(nf / float(xv))
-        xs[k], ys[k] = xv, yv
+        xs[i], ys[i] = xv, yv
         p = float(xv) * float(yv)                          # exact
         S += int(math.ldexp(p, _SHIFT))
         abs_sum += abs(p)
 
-    for k in range(K - 1):
-        e_k = spread - (spread - et) * (k + 1) / (K - 1)   # descends to log2(target)
+    for i in range(K - 1):
+        e_i = e_top - (e_top - et) * (i + 1) / (K - 1)     # descends to log2(target)
         r = float(rng.uniform(1.0, 2.0)) * (1.0 if rng.integers(0, 2) else -1.0)
-        steer(k, math.ldexp(r, math.floor(e_k)))
+        steer(i, math.ldexp(r, math.floor(e_i)))
     # Last term: land the sum on 2*sum|p|/cond for the terms drawn so far.
-    sign = 1.0 if S >= 0 else -1.0
-    steer(K - 1, sign * 2.0 * abs_sum / cond)
-    x = np.concatenate([x1, xs])
-    y = np.concatenate([y1, ys])
-    perm = rng.permutation(n)
-    x, y = np.ascontiguousarray(x[perm]), np.ascontiguousarray(y[perm])
-    abs_all = float(np.sum(np.abs(x.astype(np.float64) * y.astype(np.float64))))
+    steer(K - 1, (1.0 if S >= 0 else -1.0) * 2.0 * abs_sum / cond)
+    x = np.concatenate([xa, xb, xs])
+    y = np.concatenate([ya, yb, ys])
+    x, y = _shuffle(rng, (x, y), n)
     exact = S / (1 << _SHIFT)
-    achieved = 2.0 * abs_all / abs(exact) if exact != 0 else float("inf")
+    achieved = 2.0 * abs_sum / abs(exact) if exact != 0 else float("inf")
     return x, y, np.zeros(1, dtype=np.float32), achieved
 
 
