@@ -99,9 +99,9 @@ struct Pair {
 
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e)
 {
-    s = __fadd_rn(a, b);
-    const float z = __fsub_rn(s, a);
-    e = __fadd_rn(__fsub_rn(a, __fsub_rn(s, z)), __fsub_rn(b, z));
+    s = add_rn(a, b);
+    const float z = sub_rn(s, a);
+    e = add_rn(sub_rn(a, sub_rn(s, z)), sub_rn(b, z));
 }
 
 __device__ __forceinline__ Pair pair_merge(Pair a, Pair b)
@@ -109,19 +109,19 @@ __device__ __forceinline__ Pair pair_merge(Pair a, Pair b)
     Pair r;
     float t;
     two_sum(a.s, b.s, r.s, t);
-    r.c = __fadd_rn(__fadd_rn(a.c, b.c), t);
+    r.c = add_rn(add_rn(a.c, b.c), t);
     return r;
 }
 
 // One product folded into a pair.
 __device__ __forceinline__ void pair_fma(Pair& p, float x, float y)
 {
-    const float h = __fmul_rn(x, y);
-    const float r = __builtin_fmaf(x, y, -h);
+    const float h = mul_rn(x, y);
+    const float r = __builtin_fmaf(x, y, -h);  // exact error of the product
     float s, q;
     two_sum(p.s, h, s, q);
     p.s = s;
-    p.c = __fadd_rn(p.c, __fadd_rn(q, r));
+    p.c = add_rn(p.c, add_rn(q, r));
 }
 
 __device__ __forceinline__ Pair pair_shfl_xor(Pair p, int off)
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) void dot2_stage2_kernel(int64_t nparts, const 
     if (threadIdx.x == 0) {
         float s, t;
         two_sum(alpha[0], p.s, s, t);
-        alpha[0] = __fadd_rn(s, __fadd_rn(p.c, t));
+        alpha[0] = add_rn(s, add_rn(p.c, t));
     }
 }
 

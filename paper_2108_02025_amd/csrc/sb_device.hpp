@@ -27,12 +27,37 @@ __device__ __forceinline__ V ld_stream(const V* p) { return __builtin_nontempora
 template <typename V>
 __device__ __forceinline__ void st_stream(V* p, V v) { __builtin_nontemporal_store(v, p); }
 
-// Multiply then add with two roundings (no contraction), for GER whose
-// definition rounds the elementary product before the addition.
-__device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
-__device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
-__device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
-__device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
+// Separately rounded multiply / add / subtract.  Contraction into fused
+// multiply-add is switched off inside each helper, so the operation keeps
+// its own rounding even after inlining next to an addition (the default
+// contraction mode would otherwise fuse x*y + c).  Used by GER, whose
+// definition rounds the elementary product before the addition, and by the
+// error-free transformations of the compensated DOT.
+__device__ __forceinline__ double mul_rn(double a, double b)
+{
+#pragma clang fp contract(off)
+    return a * b;
+}
+__device__ __forceinline__ float mul_rn(float a, float b)
+{
+#pragma clang fp contract(off)
+    return a * b;
+}
+__device__ __forceinline__ double add_rn(double a, double b)
+{
+#pragma clang fp contract(off)
+    return a + b;
+}
+__device__ __forceinline__ float add_rn(float a, float b)
+{
+#pragma clang fp contract(off)
+    return a + b;
+}
+__device__ __forceinline__ float sub_rn(float a, float b)
+{
+#pragma clang fp contract(off)
+    return a - b;
+}
 
 // Butterfly sum over groups of G consecutive lanes (G a power of two <= 64).
 // Every lane of a group ends with the same value; the order of additions is
