@@ -93,9 +93,43 @@ def build_ops(sb, torch, dev, sel):
     return ops
 
 
+def build_probes(sb, torch, dev):
+    """Streaming read of 4 GiB and copy of 2 GiB with the library's probes:
+    the practical HBM ceilings the operations are compared against."""
+    src = torch.empty(1 << 29, dtype=torch.float64, device=dev)   # 4 GiB
+    src.fill_(1.0)
+    half = src[: 1 << 28]
+    dst = torch.empty(1 << 28, dtype=torch.float64, device=dev)   # 2 GiB
+    return [("probe_read", 8 << 29, 0, lambda: sb.sb_stream_read(src)),
+            ("probe_copy", 2 * (8 << 28), 0, lambda: sb.sb_stream_copy(half, dst))]
+
+
+def time_ops(torch, ops, steps):
+    """Per-operation HIP-event times (us) over `steps` passes, and the total."""
+    ev = {n: [] for n, *_ in ops}
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        for name, _, _, fn in ops:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            ev[name].append((a, b))
+    t1.record()
+    torch.cuda.synchronize()
+    per = {n: 1e3 * sum(a.elapsed_time(b) for a, b in v) / len(v) for n, v in ev.items()}
+    return per, t0.elapsed_time(t1) / steps
+
+
 def cpu_baseline(step_bytes):
-    """The CPU oracle (single thread) on a bounded sample of every operation,
-    its per-operation rate applied to the full step's bytes."""
+    """The CPU oracle (single thread, as it stands) on the step's operations:
+    binary64 GEMV N/T, GER on the full 16384 x 16384 size and DOT on the full
+    2^28; the quantised GEMV on 4096 rows and the exact dot on 2^24 pairs.
+    Each operation's rate is applied to the full step's bytes."""
     import numpy as np
 
     import oracle
@@ -103,7 +137,6 @@ def cpu_baseline(step_bytes):
 
     oracle.build()
     M = N = 16384
-    rows = 2048
     rates, parts = {}, []
 
     def timed(name, nbytes, fn):
@@ -112,31 +145,36 @@ def cpu_baseline(step_bytes):
         dt = time.perf_counter() - t
         rates[name] = nbytes / dt
         parts.append(f"{name}:{nbytes / 1e6:.0f}MB/{dt:.2f}s")
+        log(f"oracle {name}: {nbytes / dt / 1e9:.2f} GB/s")
 
-    A, x, c0 = workloads.gemv_inputs(rows, N, seed=201)
-    timed("gemv_n_f64", 8 * (rows * N + N + 2 * rows), lambda: oracle.gemv(A, x, c0))
-    xt = x[:rows].copy()
-    ct = np.zeros(N)
-    timed("gemv_t_f64", 8 * (rows * N + rows + 2 * N), lambda: oracle.gemv(A, xt, ct, op=oracle.OP_T))
-    nd = 1 << 25
-    dx, dy, da = workloads.dot_inputs(nd, seed=202)
-    timed("dot_f64", 8 * (2 * nd + 2), lambda: oracle.dot(dx, dy, da[0]))
-    gx, gy, gC = workloads.ger_inputs(rows, N, seed=203)
-    timed("ger_f64", 8 * (2 * rows * N + rows + N), lambda: oracle.ger(gx, gy, gC))
-    A32 = A.astype(np.float32)
+    A, x, c0 = workloads.gemv_inputs(M, N, seed=201)
+    timed("gemv_n_f64", 8 * (M * N + N + 2 * M), lambda: oracle.gemv(A, x, c0))
+    timed("gemv_t_f64", 8 * (M * N + M + 2 * N), lambda: oracle.gemv(A, x, c0, op=oracle.OP_T))
+    rows = 4096
+    A32 = np.ascontiguousarray(A[:rows]).astype(np.float32)
+    del A
     xq = np.random.default_rng(401).standard_normal(N).astype(np.float32)
     for q, name, es in ((oracle.Q_BF16, "gemv_q_bf16", 2), (oracle.Q_E4M3, "gemv_q_e4m3", 1)):
         codes, s = oracle.quantize_rows(A32, q)
         timed(name, es * rows * N + 4 * N + 12 * rows, lambda: oracle.gemv_q(codes, s, xq, np.zeros(rows), q))
-    n2 = 1 << 22
+    del A32
+    nd = 1 << 28
+    dx, dy, da = workloads.dot_inputs(nd, seed=202)
+    timed("dot_f64", 8 * (2 * nd + 2), lambda: oracle.dot(dx, dy, da[0]))
+    del dx, dy
+    gx, gy, gC = workloads.ger_inputs(M, N, seed=203)
+    timed("ger_f64", 8 * (2 * M * N + M + N), lambda: oracle.ger(gx, gy, gC))
+    del gC
+    n2 = 1 << 24
     hx, hy, _, _ = workloads.illcond_dot_inputs(n2, seed=402)
     timed("dot2_f32", 4 * (2 * n2 + 2), lambda: oracle.dot_exact_f32(hx, hy))
     total_t = sum(b / rates[k] for k, b in step_bytes.items() if k in rates)
     total_b = sum(b for k, b in step_bytes.items() if k in rates)
     return {
         "value": round(total_b / total_t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-        "sample": "single-thread oracle per operation on a slice of the same workload "
-                  f"({'; '.join(parts)}); per-operation rates applied to the full step's bytes",
+        "sample": "single-thread oracle: fp64 gemv N/T and ger on 16384x16384, dot on 2^28 (full size); "
+                  "quantised gemv on 4096 of the 16384 rows, exact dot on 2^24 ill-conditioned pairs; "
+                  "each operation's rate applied to the full step's bytes (" + "; ".join(parts) + ")",
     }
 
 
@@ -147,6 +185,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ops", default=None, help="comma-separated subset of operations")
+    ap.add_argument("--no-probes", action="store_true", help="skip the HBM read/copy ceiling probes")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -172,28 +211,12 @@ def main():
     torch.cuda.synchronize()
     log("warmup done")
 
-    ev = {n: [] for n in names}
-    torch.cuda.synchronize()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    t_start.record()
-    for _ in range(args.steps):
-        for name, _, _, fn in ops:
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record()
-            fn()
-            b.record()
-            ev[name].append((a, b))
-    t_end.record()
-    torch.cuda.synchronize()
-    ms_step = t_start.elapsed_time(t_end) / args.steps
+    us_per, ms_step = time_ops(torch, ops, args.steps)
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step")
 
     per = {}
     for name, nbytes, flops, _ in ops:
-        ts = [a.elapsed_time(b) for a, b in ev[name]]
-        us = 1e3 * sum(ts) / len(ts)
+        us = us_per[name]
         per[name] = {"us": round(us, 2), "GB/s": round(nbytes / us / 1e3, 1),
                      "frac_hbm": round(nbytes / us / 1e3 / PEAK_HBM_GBS, 4),
                      "TFLOP/s": round(flops / us / 1e6, 3), "bytes": nbytes}
@@ -203,6 +226,17 @@ def main():
     roof = {"bound": "hbm", "kernel": dom, "achieved": per[dom]["GB/s"], "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": round(per[dom]["GB/s"] / PEAK_HBM_GBS, 4), "traffic": None}
     extras = {}
+    if not args.no_probes:
+        probes = build_probes(sb, torch, dev)
+        for _, _, _, fn in probes:
+            fn()
+        p_us, _ = time_ops(torch, probes, max(3, args.steps // 2))
+        ceil = {name: round(nb / p_us[name] / 1e3, 1) for name, nb, _, _ in probes}
+        extras["hbm_ceiling_GBs"] = {"read": ceil["probe_read"], "copy": ceil["probe_copy"]}
+        for name in per:
+            ref = ceil["probe_copy"] if name == "ger_f64" else ceil["probe_read"]
+            per[name]["frac_ceiling"] = round(per[name]["GB/s"] / ref, 4)
+        log(f"probes: read {ceil['probe_read']} GB/s, copy {ceil['probe_copy']} GB/s")
     if "gemv_n_f64" in per and "gemv_q_bf16" in per:
         extras["bf16_over_f64_flops"] = round(per["gemv_q_bf16"]["TFLOP/s"] / per["gemv_n_f64"]["TFLOP/s"], 3)
     if "gemv_n_f64" in per and "gemv_q_e4m3" in per:

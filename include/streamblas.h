@@ -53,7 +53,7 @@ typedef enum { SB_N = 0, SB_T = 1 } sb_op;
 
 /* Operation kinds, for sb_workspace_bytes. */
 typedef enum { SB_KIND_GEMV = 0, SB_KIND_DOT = 1, SB_KIND_GER = 2, SB_KIND_GEMV_Q = 3,
-               SB_KIND_DOT2 = 4 } sb_kind;
+               SB_KIND_DOT2 = 4, SB_KIND_PROBE_READ = 5 } sb_kind;
 
 typedef struct sb_handle sb_handle;
 
@@ -169,6 +169,81 @@ sb_status sb_gemv_q(sb_handle* handle, sb_dtype q, int64_t m, int64_t n, const v
  */
 sb_status sb_dot2_f32(sb_handle* handle, int64_t n, const float* x, const float* y,
                       float* alpha);
+
+/*
+ * Batched GEMV (batching form).  The paper notes that for small problems the
+ * cost of starting threads dominates (section 4.2); on the GPU that cost is
+ * a launch, so many row-major problems c += A x share one persistent launch.
+ * Each problem is cut into tiles of rows_per_tile rows by one column chunk
+ * (split chunks per row; split > 1 is split-K: per-chunk partial sums are
+ * added in chunk order, then the initial c); a fixed grid of workgroups
+ * takes contiguous ranges of the numbered tiles.  A problem's result depends
+ * only on the problem and its configuration, so it is bit-identical alone and
+ * in any mix.  The same per-row arithmetic as sb_gemv / sb_gemv_q is used.
+ *
+ *   dtype  SB_F64 or SB_F32: A, x and c of that type.  SB_BF16 or
+ *          SB_FP8_E4M3: A holds codes (lda in elements) with per-row binary32
+ *          scales as written by sb_quantize_rows; x and c are binary32 and
+ *          c_i += s_i * sum_j q_ij x_j.
+ *   group  lanes cooperating on a row: 4, 8, 16, 32 or 64 (0: automatic).
+ *   rows_per_tile  a multiple of 4 * (64 / group) (0: automatic).
+ *   split  column chunks; each chunk's x must fit 32 KiB of LDS (0: automatic).
+ * Outputs of different problems must not overlap.  Problems with m = 0 or
+ * n = 0 are skipped.
+ */
+typedef struct {
+    int32_t dtype;
+    int32_t group;
+    int32_t rows_per_tile;
+    int32_t split;
+    int64_t m, n, lda;
+    const void* A;
+    const float* scales;
+    const void* x;
+    void* c;
+} sb_gemv_desc;
+
+/* Device bytes of the batch table (header, problem records, split counters
+ * and split scratch) for these descriptors; *image_bytes (if not NULL)
+ * receives the size of the part sb_gemv_batched_encode writes.  Returns
+ * (size_t)-1 for invalid descriptors. */
+size_t sb_gemv_batched_table_bytes(const sb_gemv_desc* descs, int32_t count, size_t* image_bytes);
+
+/* Copy the descriptors to out with every automatic field (0) replaced by
+ * the value the batched kernel will use. */
+sb_status sb_gemv_batched_resolve(const sb_gemv_desc* descs, int32_t count, sb_gemv_desc* out);
+
+/* Write the table image for a table that will live at device address
+ * dev_table (16-byte aligned, sb_gemv_batched_table_bytes bytes) into the
+ * HOST buffer host_image (image_bytes long).  The caller copies the image to
+ * dev_table before sb_gemv_batched_run.  No HIP call is made. */
+sb_status sb_gemv_batched_encode(const sb_gemv_desc* descs, int32_t count, void* dev_table,
+                                 void* host_image, size_t image_bytes);
+
+/* Launch the persistent kernel over the table at dev_table on the handle's
+ * stream (grid workgroups; 0 = 1024).  The tile count is read from the
+ * table, so a captured launch can be replayed over new tables written to
+ * the same address.  The table stays valid for further launches. */
+sb_status sb_gemv_batched_run(sb_handle* handle, const void* dev_table, int32_t grid);
+
+/* Encode, copy the table into the handle's workspace (needs
+ * sb_gemv_batched_table_bytes) and run, all on the handle's stream. */
+sb_status sb_gemv_batched(sb_handle* handle, const sb_gemv_desc* descs, int32_t count);
+
+/*
+ * Measurement probes (not operations of the paper).  They stream a byte
+ * range with the same 16-byte non-temporal accesses as the operation
+ * kernels, giving the practical HBM ceiling the operations are measured
+ * against and a transfer of known size for calibrating hardware traffic
+ * counters.  src and dst must be 16-byte aligned and bytes a multiple of
+ * 16; the ranges must not overlap (SB_EINVAL otherwise).
+ *   sb_stream_read: reads bytes from src; needs sb_workspace_bytes of kind
+ *                   SB_KIND_PROBE_READ (m ignored, n = bytes) in the
+ *                   workspace, where it leaves one XOR fold per workgroup.
+ *   sb_stream_copy: copies bytes from src to dst; needs no workspace.
+ */
+sb_status sb_stream_read(sb_handle* handle, const void* src, size_t bytes);
+sb_status sb_stream_copy(sb_handle* handle, const void* src, void* dst, size_t bytes);
 
 #ifdef __cplusplus
 }

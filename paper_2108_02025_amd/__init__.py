@@ -25,18 +25,27 @@ __all__ = [
     "StreamBlasError", "load", "lib_path", "Handle", "handle_for",
     "sb_version", "sb_status_string", "sb_workspace_bytes",
     "sb_gemv", "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32",
+    "sb_stream_read", "sb_stream_copy", "sb_gemv_desc", "GemvProblem", "make_descs", "sb_gemv_batched",
+    "sb_gemv_batched_resolve", "sb_gemv_batched_table_bytes", "BatchTable",
 ]
 
 SB_OK, SB_EINVAL, SB_ENOMEM, SB_EDEVICE, SB_EUNSUPPORTED, SB_EINTERNAL = 0, -1, -2, -3, -4, -5
 SB_F64, SB_F32, SB_BF16, SB_FP8_E4M3 = 0, 1, 2, 3
 SB_ROW_MAJOR, SB_COL_MAJOR = 0, 1
 SB_N, SB_T = 0, 1
-SB_KIND_GEMV, SB_KIND_DOT, SB_KIND_GER, SB_KIND_GEMV_Q, SB_KIND_DOT2 = 0, 1, 2, 3, 4
+SB_KIND_GEMV, SB_KIND_DOT, SB_KIND_GER, SB_KIND_GEMV_Q, SB_KIND_DOT2, SB_KIND_PROBE_READ = 0, 1, 2, 3, 4, 5
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libstreamblas.so")
 
 _DTYPES = {torch.float64: SB_F64, torch.float32: SB_F32}
+
+
+class sb_gemv_desc(ctypes.Structure):
+    """One problem of a batched GEMV (layout of the C struct)."""
+    _fields_ = [("dtype", ctypes.c_int32), ("group", ctypes.c_int32), ("rows_per_tile", ctypes.c_int32),
+                ("split", ctypes.c_int32), ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("lda", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("x", ctypes.c_void_p), ("c", ctypes.c_void_p)]
 
 
 class StreamBlasError(RuntimeError):
@@ -74,7 +83,16 @@ def load():
     L.sb_quantize_rows.argtypes = [P, I32, I64, I64, P, I64, P, I64, P]
     L.sb_gemv_q.argtypes = [P, I32, I64, I64, P, I64, P, P, P]
     L.sb_dot2_f32.argtypes = [P, I64, P, P, P]
-    for f in ("sb_handle_create", "sb_handle_destroy", "sb_set_stream", "sb_set_workspace", "sb_gemv",
+    L.sb_gemv_batched_table_bytes.argtypes = [ctypes.POINTER(sb_gemv_desc), I32, ctypes.POINTER(SZ)]
+    L.sb_gemv_batched_table_bytes.restype = SZ
+    L.sb_gemv_batched_resolve.argtypes = [ctypes.POINTER(sb_gemv_desc), I32, ctypes.POINTER(sb_gemv_desc)]
+    L.sb_gemv_batched_encode.argtypes = [ctypes.POINTER(sb_gemv_desc), I32, P, P, SZ]
+    L.sb_gemv_batched_run.argtypes = [P, P, I32]
+    L.sb_gemv_batched.argtypes = [P, ctypes.POINTER(sb_gemv_desc), I32]
+    L.sb_stream_read.argtypes = [P, P, SZ]
+    L.sb_stream_copy.argtypes = [P, P, P, SZ]
+    for f in ("sb_gemv_batched_resolve", "sb_gemv_batched_encode", "sb_gemv_batched_run", "sb_gemv_batched",
+              "sb_stream_read", "sb_stream_copy", "sb_handle_create", "sb_handle_destroy", "sb_set_stream", "sb_set_workspace", "sb_gemv",
               "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32"):
         getattr(L, f).restype = I32
     _lib = L
@@ -288,3 +306,145 @@ def sb_dot2_f32(x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor) -> torch.
     h.prepare(sb_workspace_bytes(SB_KIND_DOT2, SB_F32, 0, 0, 1, n, h))
     h.check(load().sb_dot2_f32(h.h, n, _ptr(x), _ptr(y), _ptr(alpha)))
     return alpha
+
+
+def sb_stream_read(src: torch.Tensor) -> None:
+    """Measurement probe: stream the bytes of a contiguous device tensor."""
+    if not src.is_cuda or not src.is_contiguous():
+        raise ValueError("src must be a contiguous device tensor")
+    nbytes = src.numel() * src.element_size()
+    h = handle_for(src)
+    h.prepare(sb_workspace_bytes(SB_KIND_PROBE_READ, 0, 0, 0, 0, nbytes, h))
+    h.check(load().sb_stream_read(h.h, _ptr(src), nbytes))
+
+
+def sb_stream_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
+    """Measurement probe: copy the bytes of src into dst (same byte size)."""
+    _device_check(src, dst)
+    if not src.is_contiguous() or not dst.is_contiguous():
+        raise ValueError("src and dst must be contiguous")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst differ in size")
+    h = handle_for(src)
+    h.prepare(0)
+    h.check(load().sb_stream_copy(h.h, _ptr(src), _ptr(dst), nbytes))
+
+
+class GemvProblem:
+    """One row-major problem c += A x (or c += diag(scales) Q x for codes).
+
+    A is a 2-D device tensor with unit column stride (float64/float32, or
+    2-byte / 1-byte codes with q = SB_BF16 / SB_FP8_E4M3 and scales);
+    group / rows_per_tile / split select the launch configuration (0: automatic).
+    """
+
+    __slots__ = ("A", "x", "c", "scales", "q", "group", "rows_per_tile", "split")
+
+    def __init__(self, A, x, c, scales=None, q=None, group=0, rows_per_tile=0, split=0):
+        self.A, self.x, self.c, self.scales, self.q = A, x, c, scales, q
+        self.group, self.rows_per_tile, self.split = group, rows_per_tile, split
+
+    def dtype(self) -> int:
+        if self.q is not None:
+            return self.q
+        return _dtype(self.A)
+
+
+def make_descs(problems) -> "ctypes.Array":
+    """Marshal a list of GemvProblem into a C array of sb_gemv_desc."""
+    arr = (sb_gemv_desc * max(len(problems), 1))()
+    for i, p in enumerate(problems):
+        layout, ld = _matrix_layout(p.A)
+        if layout != SB_ROW_MAJOR:
+            raise ValueError("batched problems must be row-major")
+        m, n = p.A.shape
+        dt = p.dtype()
+        if dt in (SB_BF16, SB_FP8_E4M3):
+            _q_check(dt, p.A)
+            if p.scales is None or p.scales.numel() != m or p.x.dtype != torch.float32 or p.c.dtype != torch.float32:
+                raise ValueError("quantised problems need m scales and float32 x, c")
+        elif p.x.dtype != p.A.dtype or p.c.dtype != p.A.dtype:
+            raise TypeError("A, x and c must share a dtype")
+        _vec(p.x), _vec(p.c)
+        if p.x.numel() != n or p.c.numel() != m:
+            raise ValueError("x must have n entries and c m")
+        d = arr[i]
+        d.dtype, d.group, d.rows_per_tile, d.split = dt, p.group, p.rows_per_tile, p.split
+        d.m, d.n, d.lda = m, n, ld
+        d.A, d.x, d.c = p.A.data_ptr(), p.x.data_ptr(), p.c.data_ptr()
+        d.scales = p.scales.data_ptr() if p.scales is not None else None
+    return arr
+
+
+def sb_gemv_batched_table_bytes(problems) -> tuple[int, int]:
+    descs = make_descs(problems)
+    img = ctypes.c_size_t(0)
+    total = load().sb_gemv_batched_table_bytes(descs, len(problems), ctypes.byref(img))
+    if total == (1 << 64) - 1:
+        raise StreamBlasError(SB_EINVAL, "invalid batched descriptors")
+    return int(total), int(img.value)
+
+
+def sb_gemv_batched_resolve(problems) -> list[dict]:
+    """The (group, rows_per_tile, split) the batched kernel will use per problem."""
+    descs = make_descs(problems)
+    out = (sb_gemv_desc * max(len(problems), 1))()
+    st = load().sb_gemv_batched_resolve(descs, len(problems), out)
+    if st != SB_OK:
+        raise StreamBlasError(st, load().sb_last_error(None).decode())
+    return [{"group": out[i].group, "rows_per_tile": out[i].rows_per_tile, "split": out[i].split}
+            for i in range(len(problems))]
+
+
+def sb_gemv_batched(problems) -> None:
+    """All problems in one persistent launch on the current stream."""
+    if not problems:
+        return
+    descs = make_descs(problems)
+    total, _ = sb_gemv_batched_table_bytes(problems)
+    h = handle_for(problems[0].A)
+    h.prepare(total)
+    h.check(load().sb_gemv_batched(h.h, descs, len(problems)))
+
+
+class BatchTable:
+    """A device batch table at a fixed address plus a pinned host image.
+
+    encode() writes the table for a list of problems into the pinned image and
+    copies it to the device table on the current stream; run() launches the
+    persistent kernel over it.  Because the kernel reads the tile count from
+    the table, a run() captured in a HIP graph can be replayed after encode()
+    has written a new batch to the same address.
+    """
+
+    def __init__(self, capacity_bytes: int, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        self.capacity = int(capacity_bytes)
+        self.dev = torch.empty(self.capacity, dtype=torch.uint8, device=self.device)
+        self.host = torch.empty(self.capacity, dtype=torch.uint8, pin_memory=True)
+        self.h = Handle(self.device.index)
+        self._copied = None  # event after the last host-to-device copy of the image
+
+    def fits(self, problems) -> bool:
+        return sb_gemv_batched_table_bytes(problems)[0] <= self.capacity
+
+    def encode(self, problems) -> None:
+        descs = make_descs(problems)
+        total, img = sb_gemv_batched_table_bytes(problems)
+        if total > self.capacity:
+            raise StreamBlasError(SB_ENOMEM, f"batch table needs {total} bytes, capacity {self.capacity}")
+        if self._copied is not None:
+            self._copied.synchronize()  # the pinned image may still be in flight
+        st = load().sb_gemv_batched_encode(descs, len(problems), ctypes.c_void_p(self.dev.data_ptr()),
+                                           ctypes.c_void_p(self.host.data_ptr()), img)
+        if st != SB_OK:
+            raise StreamBlasError(st, load().sb_last_error(None).decode())
+        self.dev[:img].copy_(self.host[:img], non_blocking=True)
+        self._copied = torch.cuda.Event()
+        self._copied.record()
+
+    def run(self, grid: int = 0) -> None:
+        self.h.prepare(0)
+        self.h.check(load().sb_gemv_batched_run(self.h.h, ctypes.c_void_p(self.dev.data_ptr()), grid))

@@ -167,6 +167,8 @@ size_t sb_workspace_bytes(const sb_handle* handle, sb_kind kind, sb_dtype dtype,
         return (m == 0 || n == 0) ? 0 : sb::gemv_q_ws_bytes(dtype, m, n);
     case SB_KIND_GER:
         return 0;
+    case SB_KIND_PROBE_READ:
+        return sb::probe_ws_bytes((size_t)n);
     }
     return bad;
 }
@@ -314,6 +316,37 @@ sb_status sb_dot2_f32(sb_handle* handle, int64_t n, const float* x, const float*
     if (overlap(ra, range_of(x, n, 4)) || overlap(ra, range_of(y, n, 4)))
         return fail(handle, SB_EINVAL, "sb_dot2_f32: alpha overlaps x or y");
     return sb::run_dot2(handle, n, x, y, alpha);
+    SB_GUARD_END
+}
+
+static sb_status probe_check(sb_handle* handle, const char* what, const void* src, const void* dst, size_t bytes)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "%s: NULL handle", what);
+    if (bytes % 16) return fail(handle, SB_EINVAL, "%s: bytes must be a multiple of 16", what);
+    if (bytes > (size_t)kMaxBytes) return fail(handle, SB_EINVAL, "%s: size too large", what);
+    if (bytes && (!src || !sb::aligned16(src) || (dst && !sb::aligned16(dst))))
+        return fail(handle, SB_EINVAL, "%s: NULL or misaligned pointer", what);
+    if (dst && overlap(range_of(src, (int64_t)bytes, 1), range_of(dst, (int64_t)bytes, 1)))
+        return fail(handle, SB_EINVAL, "%s: ranges overlap", what);
+    return SB_OK;
+}
+
+sb_status sb_stream_read(sb_handle* handle, const void* src, size_t bytes)
+{
+    sb_status st = probe_check(handle, "sb_stream_read", src, nullptr, bytes);
+    if (st != SB_OK) return st;
+    SB_GUARD_BEGIN
+    return sb::run_stream_read(handle, src, bytes);
+    SB_GUARD_END
+}
+
+sb_status sb_stream_copy(sb_handle* handle, const void* src, void* dst, size_t bytes)
+{
+    if (bytes && !dst) return fail(handle, SB_EINVAL, "sb_stream_copy: NULL destination");
+    sb_status st = probe_check(handle, "sb_stream_copy", src, dst, bytes);
+    if (st != SB_OK) return st;
+    SB_GUARD_BEGIN
+    return sb::run_stream_copy(handle, src, dst, bytes);
     SB_GUARD_END
 }
 

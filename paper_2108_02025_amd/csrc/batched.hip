@@ -1,0 +1,450 @@
+// Batched GEMV: many uneven problems c += A x in one persistent launch.
+//
+// The paper (section 4.2) observes that for small problems the cost of
+// starting threads dominates and proposes fewer or no threads for them.  On
+// the GPU the analogous fixed cost is a kernel launch, so a batch of
+// problems shares one launch: every problem is cut into tiles of RT rows x KC
+// columns (KC covering all of n unless the problem is split along its
+// columns), the tiles of all problems are numbered consecutively, and a
+// fixed grid of workgroups takes contiguous ranges of tile numbers.  A tile
+// stages its x chunk in LDS (kept if the workgroup's
+// next tile uses the same chunk) and runs the same per-row dot products as
+// the single-call kernels.
+//
+// A problem split into S column chunks writes per-split partial sums to
+// scratch; the tile that completes a row tile (a per-row-tile counter
+// reaches S) adds the partials in split order and then the initial c.  Every
+// result therefore depends only on the problem and its (group, rows per
+// tile, split) configuration, never on the rest of the batch or on which
+// workgroup ran it: a problem gives the same bits alone and in a mix.
+//
+// The table (header, problem records, zeroed counters) is encoded on the
+// host and copied to device memory before the launch; the kernel reads the
+// tile count from it, so a captured launch can be replayed over new tables
+// written to the same address.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "sb_device.hpp"
+#include "sb_internal.hpp"
+#include "sb_rowdot.hpp"
+
+namespace sb {
+
+constexpr int kBatNT = 256;
+constexpr int kBatWaves = kBatNT / kWave;
+constexpr int64_t kBatLds = 32 * 1024;     // x chunk bytes per tile
+constexpr int kBatGrid = 1024;             // default persistent grid: 4 workgroups per CU
+constexpr int64_t kBatTileBytes = 256 * 1024;  // automatic tile size target (bytes of A)
+constexpr int kBatUnrollPlain = 8, kBatUnrollBf16 = 2, kBatUnrollE4m3 = 4;
+
+struct BatHeader {
+    int64_t count;
+    int64_t ntiles;
+    int64_t pad[6];
+};
+
+struct BatProblem {
+    int32_t dtype, G, RT, S;
+    int64_t m, n, lda, KC;
+    int64_t tile0, rtiles;
+    const void* A;
+    const float* scales;
+    const void* x;
+    void* c;
+    void* partial;
+    int32_t* counters;
+    int32_t aligned, pad;
+    int64_t pad2;
+};
+static_assert(sizeof(BatHeader) == 64, "header layout");
+static_assert(sizeof(BatProblem) == 128, "problem record layout");
+
+// Rows [r0, r1) of one tile, per-row results to c or to the split partials.
+// Not inlined: each (dtype, group, alignment) variant gets its own register
+// allocation instead of the kernel carrying all thirty at once.
+template <int DT, int G, bool AL>
+__device__ __attribute__((noinline)) void bat_rows(const BatProblem& p, int64_t s, int64_t r0, int64_t r1, int64_t k0,
+                                         int64_t klen, const unsigned char* xs_raw)
+{
+    constexpr int GW = kWave / G;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int g = lane / G, l = lane % G;
+    for (int64_t row = r0 + w * GW + g; row < r1; row += kBatWaves * GW) {
+        if constexpr (DT == SB_F64 || DT == SB_F32) {
+            typedef typename std::conditional<DT == SB_F64, double, float>::type T;
+            const T* Ar = static_cast<const T*>(p.A) + row * p.lda + k0;
+            T t = row_dot<T, G, kBatUnrollPlain, AL, true>(Ar, klen, reinterpret_cast<const T*>(xs_raw), l);
+            t = group_sum<G>(t);
+            if (l == 0) {
+                if (p.S > 1) static_cast<T*>(p.partial)[s * p.m + row] = t;
+                else static_cast<T*>(p.c)[row] = static_cast<T*>(p.c)[row] + t;
+            }
+        } else {
+            typedef Codes<DT == SB_BF16> C;
+            typedef typename C::code_t code_t;
+            constexpr int U = DT == SB_BF16 ? kBatUnrollBf16 : kBatUnrollE4m3;
+            float t[1];
+            tile_dot<C, G, U, 1, true>(static_cast<const code_t*>(p.A) + row * p.lda + k0, p.lda, klen,
+                                       reinterpret_cast<const float*>(xs_raw), l, t);
+            float v = group_sum<G>(t[0]);
+            if (l == 0) {
+                if (p.S > 1) static_cast<float*>(p.partial)[s * p.m + row] = v;
+                else static_cast<float*>(p.c)[row] = static_cast<float*>(p.c)[row] + p.scales[row] * v;
+            }
+        }
+    }
+}
+
+template <int DT, bool AL>
+__device__ __forceinline__ void bat_rows_g(const BatProblem& p, int64_t s, int64_t r0, int64_t r1, int64_t k0,
+                                           int64_t klen, const unsigned char* xs)
+{
+    switch (p.G) {
+    case 4: bat_rows<DT, 4, AL>(p, s, r0, r1, k0, klen, xs); break;
+    case 8: bat_rows<DT, 8, AL>(p, s, r0, r1, k0, klen, xs); break;
+    case 16: bat_rows<DT, 16, AL>(p, s, r0, r1, k0, klen, xs); break;
+    case 32: bat_rows<DT, 32, AL>(p, s, r0, r1, k0, klen, xs); break;
+    default: bat_rows<DT, 64, AL>(p, s, r0, r1, k0, klen, xs); break;
+    }
+}
+
+// Second stage of a split row tile: c_i += (scale *) sum over splits in order.
+template <typename T>
+__device__ __forceinline__ void bat_finish(const BatProblem& p, int64_t r0, int64_t r1)
+{
+    const T* part = static_cast<const T*>(p.partial);
+    T* c = static_cast<T*>(p.c);
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += kBatNT) {
+        T t = part[row];
+        for (int64_t s = 1; s < p.S; ++s) t += part[s * p.m + row];
+        if (p.dtype == SB_BF16 || p.dtype == SB_FP8_E4M3) c[row] = c[row] + p.scales[row] * t;
+        else c[row] = c[row] + t;
+    }
+}
+
+// At least 4 waves per SIMD (4 workgroups per CU with 32 KiB of LDS each).
+__global__ __launch_bounds__(kBatNT, 4) void gemv_batched_kernel(const unsigned char* table)
+{
+    __shared__ __align__(16) unsigned char xs[kBatLds];
+    __shared__ int last_flag;
+    const BatHeader* hdr = reinterpret_cast<const BatHeader*>(table);
+    const BatProblem* probs = reinterpret_cast<const BatProblem*>(table + sizeof(BatHeader));
+    const int64_t count = hdr->count, ntiles = hdr->ntiles;
+    int64_t cached_p = -1, cached_s = -1;
+    // Workgroup b takes the contiguous tile range [b*T/grid, (b+1)*T/grid),
+    // so consecutive tiles of one problem reuse the staged x chunk.
+    const int64_t t_begin = (int64_t)blockIdx.x * ntiles / gridDim.x;
+    const int64_t t_end = ((int64_t)blockIdx.x + 1) * ntiles / gridDim.x;
+
+    for (int64_t t = t_begin; t < t_end; ++t) {
+        // The problem owning tile t: the last record with tile0 <= t.
+        int64_t lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (probs[mid].tile0 <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatProblem p = probs[lo];
+        const int64_t local = t - p.tile0;
+        const int64_t s = local % p.S, rt = local / p.S;
+        const int64_t r0 = rt * p.RT, r1 = min(p.m, r0 + p.RT);
+        const int64_t k0 = s * p.KC, klen = min(p.n, k0 + p.KC) - k0;
+
+        if (lo != cached_p || s != cached_s) {
+            __syncthreads();  // every row of the previous tile has read x
+            if (p.dtype == SB_F64) {
+                const double* xg = static_cast<const double*>(p.x) + k0;
+                for (int64_t e = threadIdx.x; e < klen; e += kBatNT) reinterpret_cast<double*>(xs)[e] = xg[e];
+            } else {
+                const float* xg = static_cast<const float*>(p.x) + k0;
+                for (int64_t e = threadIdx.x; e < klen; e += kBatNT) reinterpret_cast<float*>(xs)[e] = xg[e];
+            }
+            __syncthreads();
+            cached_p = lo;
+            cached_s = s;
+        }
+
+        switch (p.dtype) {
+        case SB_F64:
+            if (p.aligned) bat_rows_g<SB_F64, true>(p, s, r0, r1, k0, klen, xs);
+            else bat_rows_g<SB_F64, false>(p, s, r0, r1, k0, klen, xs);
+            break;
+        case SB_F32:
+            if (p.aligned) bat_rows_g<SB_F32, true>(p, s, r0, r1, k0, klen, xs);
+            else bat_rows_g<SB_F32, false>(p, s, r0, r1, k0, klen, xs);
+            break;
+        case SB_BF16: bat_rows_g<SB_BF16, false>(p, s, r0, r1, k0, klen, xs); break;
+        default: bat_rows_g<SB_FP8_E4M3, false>(p, s, r0, r1, k0, klen, xs); break;
+        }
+
+        if (p.S > 1) {
+            // Publish this split's partials; the tile that completes the row
+            // tile adds all splits in order.
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                last_flag = atomicAdd(&p.counters[rt], 1) == p.S - 1;
+                // every split of this row tile has arrived: rearm the counter
+                // so the same table can be launched again
+                if (last_flag) atomicExch(&p.counters[rt], 0);
+            }
+            __syncthreads();
+            if (last_flag) {
+                __threadfence();
+                if (p.dtype == SB_F64) bat_finish<double>(p, r0, r1);
+                else bat_finish<float>(p, r0, r1);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host ---
+
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+static int esize(int32_t dt) { return dt == SB_F64 ? 8 : dt == SB_F32 ? 4 : dt == SB_BF16 ? 2 : 1; }
+static int xsize(int32_t dt) { return dt == SB_F64 ? 8 : 4; }
+
+// Fill the automatic fields of one descriptor; false if it cannot be run.
+static bool resolve(const sb_gemv_desc& in, sb_gemv_desc& out, int64_t* KC, char* why, size_t whylen)
+{
+    out = in;
+    const int es = esize(in.dtype), xs = xsize(in.dtype);
+    const int64_t vec = 16 / es;  // elements per 16-byte load
+    const int64_t max_kc = kBatLds / xs;
+    if (in.split < 0 || in.group < 0 || in.rows_per_tile < 0) {
+        snprintf(why, whylen, "negative configuration value");
+        return false;
+    }
+    int64_t S = in.split ? in.split : std::max<int64_t>(1, ceil_div(in.n, max_kc));
+    int64_t kc = round_up(std::max<int64_t>(1, ceil_div(in.n, S)), 16);
+    if (kc > max_kc) {
+        snprintf(why, whylen, "split %lld leaves %lld columns per chunk, above %lld", (long long)S, (long long)kc,
+                 (long long)max_kc);
+        return false;
+    }
+    S = ceil_div(std::max<int64_t>(in.n, 1), kc);
+    int G = in.group;
+    if (G == 0) {
+        const int U = in.dtype == SB_BF16 ? kBatUnrollBf16 : in.dtype == SB_FP8_E4M3 ? kBatUnrollE4m3 : kBatUnrollPlain;
+        const int64_t nvec = ceil_div(kc, vec);
+        G = 64;
+        while (G > 4 && nvec < (int64_t)G * U) G >>= 1;
+    } else if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64) {
+        snprintf(why, whylen, "group %d is not 4, 8, 16, 32 or 64", G);
+        return false;
+    }
+    const int64_t pass = (int64_t)kBatWaves * (64 / G);
+    int64_t RT = in.rows_per_tile;
+    if (RT == 0) {
+        const int64_t row_bytes = std::max<int64_t>(1, std::min<int64_t>(kc, in.n)) * es;
+        RT = std::max<int64_t>(pass, (kBatTileBytes / row_bytes) / pass * pass);
+        RT = std::min<int64_t>(RT, round_up(std::max<int64_t>(in.m, 1), pass));
+    } else if (RT % pass) {
+        snprintf(why, whylen, "rows_per_tile %lld is not a multiple of %lld", (long long)RT, (long long)pass);
+        return false;
+    }
+    if (RT > (1 << 30)) RT = 1 << 30;
+    out.group = G;
+    out.rows_per_tile = (int32_t)RT;
+    out.split = (int32_t)S;
+    *KC = kc;
+    return true;
+}
+
+struct BatLayout {
+    std::vector<sb_gemv_desc> res;
+    std::vector<int64_t> kc, tiles, rtiles, counter_off, partial_off;
+    size_t image = 0, total = 0;
+    int64_t ntiles = 0;
+};
+
+static sb_status layout(const sb_gemv_desc* d, int32_t count, BatLayout& L, char* why, size_t whylen)
+{
+    if (count < 0 || (count > 0 && !d)) {
+        snprintf(why, whylen, "bad descriptor array");
+        return SB_EINVAL;
+    }
+    L.res.resize(count);
+    L.kc.resize(count);
+    L.tiles.resize(count);
+    L.rtiles.resize(count);
+    L.counter_off.resize(count);
+    L.partial_off.resize(count);
+    size_t off = sizeof(BatHeader) + (size_t)count * sizeof(BatProblem);
+    for (int32_t i = 0; i < count; ++i) {
+        const sb_gemv_desc& in = d[i];
+        if (in.dtype < SB_F64 || in.dtype > SB_FP8_E4M3 || in.m < 0 || in.n < 0 || in.lda < std::max<int64_t>(1, in.n)) {
+            snprintf(why, whylen, "descriptor %d: bad dtype, size or lda", i);
+            return SB_EINVAL;
+        }
+        if (in.m > 0 && in.n > 0 && (!in.A || !in.x || !in.c ||
+                                     ((in.dtype == SB_BF16 || in.dtype == SB_FP8_E4M3) && !in.scales))) {
+            snprintf(why, whylen, "descriptor %d: NULL pointer", i);
+            return SB_EINVAL;
+        }
+        const int es = esize(in.dtype), xs = xsize(in.dtype);
+        if ((uintptr_t)in.A % es || (uintptr_t)in.x % xs || (uintptr_t)in.c % xs || (uintptr_t)in.scales % 4) {
+            snprintf(why, whylen, "descriptor %d: misaligned pointer", i);
+            return SB_EINVAL;
+        }
+        if (in.m > (int64_t)1 << 40 || in.n > (int64_t)1 << 40 || in.lda > (int64_t)1 << 40) {
+            snprintf(why, whylen, "descriptor %d: size too large", i);
+            return SB_EINVAL;
+        }
+        char sub[160];
+        if (!resolve(in, L.res[i], &L.kc[i], sub, sizeof sub)) {
+            snprintf(why, whylen, "descriptor %d: %s", i, sub);
+            return SB_EINVAL;
+        }
+        const int64_t rt = (in.m == 0 || in.n == 0) ? 0 : ceil_div(in.m, L.res[i].rows_per_tile);
+        L.rtiles[i] = rt;
+        L.tiles[i] = rt * L.res[i].split;
+        L.ntiles += L.tiles[i];
+        L.counter_off[i] = -1;
+        if (L.res[i].split > 1 && rt > 0) {
+            L.counter_off[i] = (int64_t)off;
+            off += (size_t)rt * sizeof(int32_t);
+        }
+    }
+    L.image = round_up((int64_t)off, 64);
+    size_t total = L.image;
+    for (int32_t i = 0; i < count; ++i) {
+        L.partial_off[i] = -1;
+        if (L.res[i].split > 1 && L.rtiles[i] > 0) {
+            L.partial_off[i] = (int64_t)total;
+            total += (size_t)round_up(L.res[i].split * d[i].m * xsize(d[i].dtype), 64);
+        }
+    }
+    L.total = total;
+    // Outputs of different problems must not overlap (each c has one owner).
+    std::vector<std::pair<uintptr_t, uintptr_t>> cs;
+    for (int32_t i = 0; i < count; ++i) {
+        if (d[i].m > 0 && d[i].n > 0) {
+            const uintptr_t lo = (uintptr_t)d[i].c;
+            cs.push_back({lo, lo + (uintptr_t)d[i].m * xsize(d[i].dtype)});
+        }
+    }
+    std::sort(cs.begin(), cs.end());
+    for (size_t k = 1; k < cs.size(); ++k) {
+        if (cs[k].first < cs[k - 1].second) {
+            snprintf(why, whylen, "outputs of two problems overlap");
+            return SB_EINVAL;
+        }
+    }
+    return SB_OK;
+}
+
+static void encode(const sb_gemv_desc* d, int32_t count, const BatLayout& L, unsigned char* dev_table,
+                   unsigned char* image)
+{
+    memset(image, 0, L.image);
+    BatHeader* hdr = reinterpret_cast<BatHeader*>(image);
+    hdr->count = count;
+    hdr->ntiles = L.ntiles;
+    BatProblem* P = reinterpret_cast<BatProblem*>(image + sizeof(BatHeader));
+    int64_t tile0 = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const sb_gemv_desc& r = L.res[i];
+        BatProblem& p = P[i];
+        p.dtype = r.dtype;
+        p.G = r.group;
+        p.RT = r.rows_per_tile;
+        p.S = r.split;
+        p.m = d[i].m;
+        p.n = d[i].n;
+        p.lda = d[i].lda;
+        p.KC = L.kc[i];
+        p.tile0 = tile0;
+        p.rtiles = L.rtiles[i];
+        p.A = d[i].A;
+        p.scales = d[i].scales;
+        p.x = d[i].x;
+        p.c = d[i].c;
+        p.partial = L.partial_off[i] >= 0 ? dev_table + L.partial_off[i] : nullptr;
+        p.counters = L.counter_off[i] >= 0 ? reinterpret_cast<int32_t*>(dev_table + L.counter_off[i]) : nullptr;
+        const int es = esize(r.dtype);
+        p.aligned = (r.dtype == SB_F64 || r.dtype == SB_F32) && aligned16(d[i].A) && (d[i].lda * es) % 16 == 0;
+        tile0 += L.tiles[i];
+    }
+}
+
+}  // namespace sb
+
+using sb::fail;
+
+extern "C" {
+
+size_t sb_gemv_batched_table_bytes(const sb_gemv_desc* descs, int32_t count, size_t* image_bytes)
+{
+    sb::BatLayout L;
+    char why[256];
+    if (sb::layout(descs, count, L, why, sizeof why) != SB_OK) return (size_t)-1;
+    if (image_bytes) *image_bytes = L.image;
+    return L.total;
+}
+
+sb_status sb_gemv_batched_resolve(const sb_gemv_desc* descs, int32_t count, sb_gemv_desc* out)
+{
+    sb::BatLayout L;
+    char why[256];
+    if (!out && count > 0) return fail(nullptr, SB_EINVAL, "sb_gemv_batched_resolve: NULL output");
+    const sb_status st = sb::layout(descs, count, L, why, sizeof why);
+    if (st != SB_OK) return fail(nullptr, st, "sb_gemv_batched_resolve: %s", why);
+    for (int32_t i = 0; i < count; ++i) out[i] = L.res[i];
+    return SB_OK;
+}
+
+sb_status sb_gemv_batched_encode(const sb_gemv_desc* descs, int32_t count, void* dev_table, void* host_image,
+                                 size_t image_bytes)
+{
+    sb::BatLayout L;
+    char why[256];
+    const sb_status st = sb::layout(descs, count, L, why, sizeof why);
+    if (st != SB_OK) return fail(nullptr, st, "sb_gemv_batched_encode: %s", why);
+    if (!dev_table || !host_image || image_bytes < L.image || !sb::aligned16(dev_table))
+        return fail(nullptr, SB_EINVAL, "sb_gemv_batched_encode: table buffers missing, misaligned or too small");
+    sb::encode(descs, count, L, static_cast<unsigned char*>(dev_table), static_cast<unsigned char*>(host_image));
+    return SB_OK;
+}
+
+sb_status sb_gemv_batched_run(sb_handle* handle, const void* dev_table, int32_t grid)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_gemv_batched_run: NULL handle");
+    if (!dev_table || !sb::aligned16(dev_table)) return fail(handle, SB_EINVAL, "sb_gemv_batched_run: bad table");
+    if (grid < 0 || grid > (1 << 20)) return fail(handle, SB_EINVAL, "sb_gemv_batched_run: bad grid %d", grid);
+    const int g = grid ? grid : sb::kBatGrid;
+    hipLaunchKernelGGL(sb::gemv_batched_kernel, dim3(g), dim3(sb::kBatNT), 0, handle->stream,
+                       static_cast<const unsigned char*>(dev_table));
+    return sb::check_launch(handle, "gemv_batched_kernel");
+}
+
+sb_status sb_gemv_batched(sb_handle* handle, const sb_gemv_desc* descs, int32_t count)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_gemv_batched: NULL handle");
+    try {
+        sb::BatLayout L;
+        char why[256];
+        const sb_status st = sb::layout(descs, count, L, why, sizeof why);
+        if (st != SB_OK) return fail(handle, st, "sb_gemv_batched: %s", why);
+        if (L.ntiles == 0) return SB_OK;
+        if (L.total > handle->ws_bytes || !sb::aligned16(handle->ws))
+            return fail(handle, SB_ENOMEM, "sb_gemv_batched needs %zu workspace bytes, handle has %zu", L.total,
+                        handle->ws_bytes);
+        std::vector<unsigned char> image(L.image);
+        sb::encode(descs, count, L, static_cast<unsigned char*>(handle->ws), image.data());
+        // From pageable memory the copy is staged before the call returns,
+        // so the local image may be released afterwards.
+        const hipError_t e = hipMemcpyAsync(handle->ws, image.data(), L.image, hipMemcpyHostToDevice, handle->stream);
+        if (e != hipSuccess) return fail(handle, SB_EDEVICE, "sb_gemv_batched: copy of the table: %s", hipGetErrorString(e));
+        return sb_gemv_batched_run(handle, handle->ws, 0);
+    } catch (...) {
+        return fail(handle, SB_EINTERNAL, "sb_gemv_batched: unexpected C++ exception");
+    }
+}
+
+}  // extern "C"

@@ -17,7 +17,18 @@
 
 namespace sb {
 
-constexpr int kUnrollDot = 8;
+// Build-time launch constants (overridable with -D for tuning sweeps).
+#ifndef SB_DOT_UNROLL
+#define SB_DOT_UNROLL 16
+#endif
+#ifndef SB_DOT_LOAD_NT
+#define SB_DOT_LOAD_NT 1
+#endif
+#ifndef SB_DOT_BLOCKS
+#define SB_DOT_BLOCKS 1024
+#endif
+constexpr int kUnrollDot = SB_DOT_UNROLL;
+constexpr bool kDotNT = SB_DOT_LOAD_NT;
 
 template <typename T>
 struct DotArgs {
@@ -48,13 +59,13 @@ __global__ __launch_bounds__(NT) void dot_stage1_kernel(DotArgs<T> a)
         V xa[U], ya[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            xa[u] = ld_stream(xv + v + u * NT);
-            ya[u] = ld_stream(yv + v + u * NT);
+            xa[u] = ld_stream<kDotNT>(xv + v + u * NT);
+            ya[u] = ld_stream<kDotNT>(yv + v + u * NT);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) acc += xa[u] * ya[u];
     }
-    for (; v < nv; v += NT) acc += ld_stream(xv + v) * ld_stream(yv + v);
+    for (; v < nv; v += NT) acc += ld_stream<kDotNT>(xv + v) * ld_stream<kDotNT>(yv + v);
 
     T t;
     if constexpr (W == 1) {
@@ -174,8 +185,8 @@ __global__ __launch_bounds__(NT) void dot2_stage1_kernel(int64_t n, const float*
         V xa[U], ya[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            xa[u] = ld_stream(xv + v + u * NT);
-            ya[u] = ld_stream(yv + v + u * NT);
+            xa[u] = ld_stream<kDotNT>(xv + v + u * NT);
+            ya[u] = ld_stream<kDotNT>(yv + v + u * NT);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -188,7 +199,7 @@ __global__ __launch_bounds__(NT) void dot2_stage1_kernel(int64_t n, const float*
         }
     }
     for (; v < nv; v += NT) {
-        const V xa = ld_stream(xv + v), ya = ld_stream(yv + v);
+        const V xa = ld_stream<kDotNT>(xv + v), ya = ld_stream<kDotNT>(yv + v);
         if constexpr (W == 1) {
             pair_fma(acc[0], xa, ya);
         } else {
@@ -228,7 +239,7 @@ __global__ __launch_bounds__(256) void dot2_stage2_kernel(int64_t nparts, const 
 
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-constexpr int64_t kMaxDotBlocks = 2048;  // 8 workgroups per compute unit
+constexpr int64_t kMaxDotBlocks = SB_DOT_BLOCKS;  // default: 4 workgroups per compute unit
 
 DotPlan plan_dot(int esize, int64_t n, int partial_values)
 {

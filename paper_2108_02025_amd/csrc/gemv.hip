@@ -27,11 +27,29 @@
 
 #include "sb_device.hpp"
 #include "sb_internal.hpp"
+#include "sb_rowdot.hpp"
 
 namespace sb {
 
-constexpr int kUnrollN = 8;  // 16-byte loads in flight per lane and row
-constexpr int kUnrollT = 8;  // rows in flight per wave
+// Build-time launch constants (overridable with -D for tuning sweeps).
+#ifndef SB_GEMV_N_UNROLL
+#define SB_GEMV_N_UNROLL 16
+#endif
+#ifndef SB_GEMV_T_UNROLL
+#define SB_GEMV_T_UNROLL 8
+#endif
+#ifndef SB_GEMV_LOAD_NT
+#define SB_GEMV_LOAD_NT 1
+#endif
+#ifndef SB_GEMV_T_BLOCKS
+#define SB_GEMV_T_BLOCKS 1024
+#endif
+#ifndef SB_GEMV_N_WAVES_PER_CU
+#define SB_GEMV_N_WAVES_PER_CU 32
+#endif
+constexpr int kUnrollN = SB_GEMV_N_UNROLL;  // 16-byte loads in flight per lane and row
+constexpr int kUnrollT = SB_GEMV_T_UNROLL;  // rows in flight per wave
+constexpr bool kGemvNT = SB_GEMV_LOAD_NT;
 
 template <typename T>
 struct GemvNArgs {
@@ -47,8 +65,6 @@ struct GemvNArgs {
 template <typename T, int G, int NT, bool ALIGNED>
 __global__ __launch_bounds__(NT) void gemv_n_kernel(GemvNArgs<T> a)
 {
-    typedef typename Vec<T>::type V;
-    constexpr int W = Vec<T>::W;
     constexpr int U = kUnrollN;
     constexpr int NW = NT / kWave, GW = kWave / G;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -68,46 +84,7 @@ __global__ __launch_bounds__(NT) void gemv_n_kernel(GemvNArgs<T> a)
     const int64_t r1 = min(a.rows, r0 + a.RB);
 
     for (int64_t row = r0 + w * GW + g; row < r1; row += NW * GW) {
-        const T* Ar = a.A + row * a.ld + k0;
-        int64_t head = 0;
-        if (!ALIGNED) {
-            head = ((16 - (reinterpret_cast<uintptr_t>(Ar) & 15)) & 15) / sizeof(T);
-            head = min(head, klen);
-        }
-        V acc = (V)0;
-        if (!ALIGNED && l < head) acc[0] = Ar[l] * xs[l];
-
-        const int64_t nv = (klen - head) / W;
-        const V* Av = reinterpret_cast<const V*>(Ar + head);
-        const T* xb = xs + head;
-        int64_t v = l;
-        for (; v + (U - 1) * G < nv; v += U * G) {
-            V av[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) av[u] = ld_stream(Av + v + u * G);
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t e = (v + u * G) * W;
-                if (ALIGNED) {
-                    acc += av[u] * *reinterpret_cast<const V*>(xb + e);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < W; ++q) acc[q] += av[u][q] * xb[e + q];
-                }
-            }
-        }
-        for (; v < nv; v += G) {
-            const V av = ld_stream(Av + v);
-            const int64_t e = v * W;
-#pragma unroll
-            for (int q = 0; q < W; ++q) acc[q] += av[q] * xb[e + q];
-        }
-        const int64_t t0 = head + nv * W;  // fewer than W elements remain
-        if (l < klen - t0) acc[1 % W] += Ar[t0 + l] * xs[t0 + l];
-
-        T t = acc[0];
-#pragma unroll
-        for (int q = 1; q < W; ++q) t += acc[q];
+        T t = row_dot<T, G, U, ALIGNED, kGemvNT>(a.A + row * a.ld + k0, klen, xs, l);
         t = group_sum<G>(t);
         if (l == 0) {
             if (a.partial) a.partial[s * a.rows + row] = t;
@@ -164,7 +141,7 @@ __global__ __launch_bounds__(NT) void gemv_t_kernel(GemvTArgs<T> a)
             T xv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                av[u] = ld_stream(reinterpret_cast<const V*>(a.A + (i + u * NW) * a.ld + j0));
+                av[u] = ld_stream<kGemvNT>(reinterpret_cast<const V*>(a.A + (i + u * NW) * a.ld + j0));
                 xv[u] = a.x[i + u * NW];
             }
 #pragma unroll
@@ -178,7 +155,7 @@ __global__ __launch_bounds__(NT) void gemv_t_kernel(GemvTArgs<T> a)
             }
         }
         for (; i < i1; i += NW) {
-            const V av = ld_stream(reinterpret_cast<const V*>(a.A + i * a.ld + j0));
+            const V av = ld_stream<kGemvNT>(reinterpret_cast<const V*>(a.A + i * a.ld + j0));
             const T xv = a.x[i];
             if constexpr (W == 1) {
                 acc[0] += av * xv;
@@ -238,7 +215,7 @@ GemvNPlan plan_gemv_n(int esize, int64_t rows, int64_t cols)
     p.NT = p.lds > 80 * 1024 ? 1024 : (p.lds > 40 * 1024 ? 512 : 256);
     const int64_t waves_per_block = p.NT / 64;
     const int64_t bpc = std::max<int64_t>(1, std::min<int64_t>(kLdsPerCU / (int64_t)p.lds,
-                                                              32 / waves_per_block));
+                                                              SB_GEMV_N_WAVES_PER_CU / waves_per_block));
     const int64_t nvec = ceil_div(p.KC, W);
     int G = 64;
     while (G > 4 && nvec < (int64_t)G * kUnrollN) G >>= 1;
@@ -257,9 +234,9 @@ GemvTPlan plan_gemv_t(int esize, int64_t rows, int64_t cols)
     p.NT = 256;
     const int64_t CW = 64 * (16 / esize);
     const int64_t ncb = std::max<int64_t>(1, ceil_div(cols, CW));
-    const int64_t target = kCUs * 8;
+    const int64_t target = SB_GEMV_T_BLOCKS;
     int64_t ns = ceil_div(target, ncb);
-    ns = std::min<int64_t>(ns, 64);
+    ns = std::min<int64_t>(ns, 512);
     ns = std::min<int64_t>(ns, std::max<int64_t>(1, rows / 64));
     ns = std::max<int64_t>(ns, 1);
     p.RS = ceil_div(rows, ns);

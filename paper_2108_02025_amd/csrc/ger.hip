@@ -16,7 +16,28 @@
 
 namespace sb {
 
-constexpr int kUnrollGer = 8;
+// Build-time launch constants (overridable with -D for tuning sweeps).
+#ifndef SB_GER_UNROLL
+#define SB_GER_UNROLL 32
+#endif
+#ifndef SB_GER_LOAD_NT
+#define SB_GER_LOAD_NT 1
+#endif
+#ifndef SB_GER_STORE_NT
+#define SB_GER_STORE_NT 1
+#endif
+#ifndef SB_GER_BLOCKS
+#define SB_GER_BLOCKS 32768
+#endif
+#ifndef SB_GER_MIN_ROWS
+#define SB_GER_MIN_ROWS 32
+#endif
+#ifndef SB_GER_COLS
+#define SB_GER_COLS 1
+#endif
+constexpr int kUnrollGer = SB_GER_UNROLL;
+constexpr int kGerCols = SB_GER_COLS;
+constexpr bool kGerLoadNT = SB_GER_LOAD_NT, kGerStoreNT = SB_GER_STORE_NT;
 
 template <typename T>
 struct GerArgs {
@@ -33,54 +54,74 @@ __global__ __launch_bounds__(NT) void ger_kernel(GerArgs<T> a)
     constexpr int W = ALIGNED ? Vec<T>::W : 1;
     typedef typename std::conditional<ALIGNED, typename Vec<T>::type, T>::type V;
     constexpr int U = kUnrollGer;
+    constexpr int CH = ALIGNED ? kGerCols : 1;  // column chunks per lane, NT*W columns apart
 
-    const int64_t j0 = ((int64_t)blockIdx.x * NT + threadIdx.x) * W;
+    // This lane's chunks start at j0 + k * NT * W, k < CH.
+    const int64_t j0 = (int64_t)blockIdx.x * NT * W * CH + (int64_t)threadIdx.x * W;
     if (j0 >= a.cols) return;
     const int64_t i0 = (int64_t)blockIdx.y * a.RB;
     const int64_t i1 = min(a.rows, i0 + a.RB);
 
-    if (j0 + W <= a.cols) {
-        T yv[W];
+    if (j0 + (int64_t)(CH - 1) * NT * W + W <= a.cols) {
+        T yv[CH][W];
 #pragma unroll
-        for (int q = 0; q < W; ++q) yv[q] = a.y[j0 + q];
+        for (int k = 0; k < CH; ++k) {
+#pragma unroll
+            for (int q = 0; q < W; ++q) yv[k][q] = a.y[j0 + (int64_t)k * NT * W + q];
+        }
         int64_t i = i0;
         for (; i + U - 1 < i1; i += U) {
-            V cv[U];
+            V cv[U][CH];
             T xv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                cv[u] = ld_stream(reinterpret_cast<const V*>(a.C + (i + u) * a.ld + j0));
+#pragma unroll
+                for (int k = 0; k < CH; ++k)
+                    cv[u][k] = ld_stream<kGerLoadNT>(
+                        reinterpret_cast<const V*>(a.C + (i + u) * a.ld + j0 + (int64_t)k * NT * W));
                 xv[u] = a.x[i + u];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if constexpr (W == 1) {
-                    cv[u] = add_rn(cv[u], mul_rn(xv[u], yv[0]));
-                } else {
 #pragma unroll
-                    for (int q = 0; q < W; ++q) cv[u][q] = add_rn(cv[u][q], mul_rn(xv[u], yv[q]));
+                for (int k = 0; k < CH; ++k) {
+                    if constexpr (W == 1) {
+                        cv[u][k] = add_rn(cv[u][k], mul_rn(xv[u], yv[k][0]));
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < W; ++q) cv[u][k][q] = add_rn(cv[u][k][q], mul_rn(xv[u], yv[k][q]));
+                    }
+                    st_stream<kGerStoreNT>(reinterpret_cast<V*>(a.C + (i + u) * a.ld + j0 + (int64_t)k * NT * W),
+                                           cv[u][k]);
                 }
-                st_stream(reinterpret_cast<V*>(a.C + (i + u) * a.ld + j0), cv[u]);
             }
         }
         for (; i < i1; ++i) {
-            V cv = ld_stream(reinterpret_cast<const V*>(a.C + i * a.ld + j0));
             const T xi = a.x[i];
-            if constexpr (W == 1) {
-                cv = add_rn(cv, mul_rn(xi, yv[0]));
-            } else {
 #pragma unroll
-                for (int q = 0; q < W; ++q) cv[q] = add_rn(cv[q], mul_rn(xi, yv[q]));
+            for (int k = 0; k < CH; ++k) {
+                V* p = reinterpret_cast<V*>(a.C + i * a.ld + j0 + (int64_t)k * NT * W);
+                V cv = ld_stream<kGerLoadNT>(p);
+                if constexpr (W == 1) {
+                    cv = add_rn(cv, mul_rn(xi, yv[k][0]));
+                } else {
+#pragma unroll
+                    for (int q = 0; q < W; ++q) cv[q] = add_rn(cv[q], mul_rn(xi, yv[k][q]));
+                }
+                st_stream<kGerStoreNT>(p, cv);
             }
-            st_stream(reinterpret_cast<V*>(a.C + i * a.ld + j0), cv);
         }
     } else {
-        const int rem = (int)(a.cols - j0);
-        for (int64_t i = i0; i < i1; ++i) {
-            const T xi = a.x[i];
-            for (int q = 0; q < rem; ++q) {
-                T* p = a.C + i * a.ld + j0 + q;
-                *p = add_rn(*p, mul_rn(xi, a.y[j0 + q]));
+        // Right edge: element by element over this lane's columns.
+        for (int k = 0; k < CH; ++k) {
+            const int64_t jk = j0 + (int64_t)k * NT * W;
+            const int64_t rem = min<int64_t>(W, a.cols - jk);
+            for (int64_t i = i0; i < i1; ++i) {
+                const T xi = a.x[i];
+                for (int64_t q = 0; q < rem; ++q) {
+                    T* p = a.C + i * a.ld + jk + q;
+                    *p = add_rn(*p, mul_rn(xi, a.y[jk + q]));
+                }
             }
         }
     }
@@ -95,11 +136,11 @@ static sb_status ger_typed(sb_handle* h, int64_t rows, int64_t cols, const T* x,
     constexpr int NT = 256;
     const bool al = aligned16(C) && ((ld * (int64_t)sizeof(T)) % 16 == 0);
     const int64_t W = al ? 16 / (int64_t)sizeof(T) : 1;
-    const int64_t cblocks = ceil_div(cols, NT * W);
-    // Aim for about 32 workgroups per compute unit over the whole launch,
-    // each streaming at least 64 rows.
-    const int64_t target = 256 * 32;
-    int64_t rb = std::max<int64_t>(64, ceil_div(rows, std::max<int64_t>(1, target / cblocks)));
+    const int64_t cblocks = ceil_div(cols, NT * W * (al ? kGerCols : 1));
+    // Aim for about 128 workgroups per compute unit over the whole launch,
+    // each streaming at least SB_GER_MIN_ROWS rows.
+    const int64_t target = SB_GER_BLOCKS;
+    int64_t rb = std::max<int64_t>(SB_GER_MIN_ROWS, ceil_div(rows, std::max<int64_t>(1, target / cblocks)));
     rb = std::min<int64_t>(rb, rows);
     GerArgs<T> a{rows, cols, ld, x, y, C, rb};
     const dim3 grid((unsigned)cblocks, (unsigned)ceil_div(rows, rb));

@@ -18,8 +18,31 @@
 
 #include "sb_device.hpp"
 #include "sb_internal.hpp"
+#include "sb_rowdot.hpp"
+
+// Build-time launch constants (overridable with -D for tuning sweeps).
+#ifndef SB_GEMVQ_UNROLL_BF16
+#define SB_GEMVQ_UNROLL_BF16 2
+#endif
+#ifndef SB_GEMVQ_UNROLL_E4M3
+#define SB_GEMVQ_UNROLL_E4M3 8
+#endif
+#ifndef SB_GEMVQ_ROWS_BF16
+#define SB_GEMVQ_ROWS_BF16 1
+#endif
+#ifndef SB_GEMVQ_ROWS_E4M3
+#define SB_GEMVQ_ROWS_E4M3 1
+#endif
+#ifndef SB_GEMVQ_LOAD_NT
+#define SB_GEMVQ_LOAD_NT 1
+#endif
+#ifndef SB_GEMVQ_WAVES_PER_CU
+#define SB_GEMVQ_WAVES_PER_CU 32
+#endif
 
 namespace sb {
+
+constexpr bool kGemvQNT = SB_GEMVQ_LOAD_NT;
 
 // ------------------------------------------------------------- encoding ---
 
@@ -116,44 +139,6 @@ __global__ __launch_bounds__(256) void quantize_rows_kernel(int64_t m, int64_t n
 
 // ------------------------------------------------------------- decoding ---
 
-template <bool BF16> struct Codes;
-template <> struct Codes<true> {
-    typedef uint16_t code_t;
-    static constexpr int PER16 = 8;  // values per 16-byte load
-    __device__ static float one(uint16_t c) { return __uint_as_float((uint32_t)c << 16); }
-    // 4 dwords -> 8 values, element order preserved
-    __device__ static void unpack(const v4u& w, float* f)
-    {
-        const uint32_t d[4] = {w[0], w[1], w[2], w[3]};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            f[2 * k] = __uint_as_float(d[k] << 16);
-            f[2 * k + 1] = __uint_as_float(d[k] & 0xFFFF0000u);
-        }
-    }
-};
-template <> struct Codes<false> {
-    typedef uint8_t code_t;
-    static constexpr int PER16 = 16;
-    __device__ static float one(uint8_t c)
-    {
-        return __builtin_amdgcn_cvt_f32_fp8((int)c, 0);
-    }
-    __device__ static void unpack(const v4u& w, float* f)
-    {
-        const uint32_t d[4] = {w[0], w[1], w[2], w[3]};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)d[k], false);
-            const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)d[k], true);
-            f[4 * k] = lo[0];
-            f[4 * k + 1] = lo[1];
-            f[4 * k + 2] = hi[0];
-            f[4 * k + 3] = hi[1];
-        }
-    }
-};
-
 struct GemvQArgs {
     int64_t m, n, ldq;
     const void* Aq;
@@ -164,13 +149,14 @@ struct GemvQArgs {
     int64_t KC, RB;
 };
 
-template <bool BF16, int G, int NT>
-__global__ __launch_bounds__(NT) void gemv_q_kernel(GemvQArgs a)
+// At least 4 waves per SIMD: without the bound the compiler hoists every
+// decode of the loads in flight and needs over 200 VGPRs (2 waves per SIMD).
+template <bool BF16, int G, int NT, int R>
+__global__ __launch_bounds__(NT, 4) void gemv_q_kernel(GemvQArgs a)
 {
     typedef Codes<BF16> C;
     typedef typename C::code_t code_t;
-    constexpr int P = C::PER16;
-    constexpr int U = 4;
+    constexpr int U = BF16 ? SB_GEMVQ_UNROLL_BF16 : SB_GEMVQ_UNROLL_E4M3;
     constexpr int NW = NT / kWave, GW = kWave / G;
     extern __shared__ __align__(16) unsigned char smem[];
     float* xs = reinterpret_cast<float*>(smem);
@@ -187,57 +173,25 @@ __global__ __launch_bounds__(NT) void gemv_q_kernel(GemvQArgs a)
     const int64_t r1 = min(a.m, r0 + a.RB);
     const code_t* Q = static_cast<const code_t*>(a.Aq);
 
-    for (int64_t row = r0 + w * GW + g; row < r1; row += NW * GW) {
-        const code_t* Qr = Q + row * a.ldq + k0;
-        int64_t head = ((16 - (reinterpret_cast<uintptr_t>(Qr) & 15)) & 15) / sizeof(code_t);
-        head = min(head, klen);
-        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int64_t e = l; e < head; e += G) acc[0] += C::one(Qr[e]) * xs[e];
-
-        const int64_t nv = (klen - head) / P;
-        const v4u* Qv = reinterpret_cast<const v4u*>(Qr + head);
-        const float* xb = xs + head;
-        const bool xal = ((head * 4) & 15) == 0;
-        int64_t v = l;
-        for (; v + (U - 1) * G < nv; v += U * G) {
-            v4u wv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) wv[u] = ld_stream(Qv + v + u * G);
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                float f[P];
-                C::unpack(wv[u], f);
-                const float* xe = xb + (v + u * G) * P;
-                if (xal) {
-#pragma unroll
-                    for (int q = 0; q < P; q += 4) {
-                        const v4f xv = *reinterpret_cast<const v4f*>(xe + q);
-                        acc[0] += f[q] * xv[0];
-                        acc[1] += f[q + 1] * xv[1];
-                        acc[2] += f[q + 2] * xv[2];
-                        acc[3] += f[q + 3] * xv[3];
-                    }
-                } else {
-#pragma unroll
-                    for (int q = 0; q < P; ++q) acc[q & 3] += f[q] * xe[q];
-                }
-            }
-        }
-        for (; v < nv; v += G) {
-            float f[P];
-            C::unpack(ld_stream(Qv + v), f);
-            const float* xe = xb + v * P;
-#pragma unroll
-            for (int q = 0; q < P; ++q) acc[q & 3] += f[q] * xe[q];
-        }
-        for (int64_t e = head + nv * P + l; e < klen; e += G) acc[1] += C::one(Qr[e]) * xs[e];
-
-        float t = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    auto finish = [&](int64_t row, float t) {
         t = group_sum<G>(t);
         if (l == 0) {
             if (a.partial) a.partial[s * a.m + row] = t;
             else a.c[row] = a.c[row] + a.scales[row] * t;
         }
+    };
+    int64_t row = r0 + (int64_t)(w * GW + g) * R;
+    for (; row + R <= r1; row += (int64_t)NW * GW * R) {
+        float t[R];
+        tile_dot<C, G, U, R, kGemvQNT>(Q + row * a.ldq + k0, a.ldq, klen, xs, l, t);
+#pragma unroll
+        for (int r = 0; r < R; ++r) finish(row + r, t[r]);
+    }
+    // rows of a last, partial tile
+    for (; row < r1; ++row) {
+        float t[1];
+        tile_dot<C, G, U, 1, kGemvQNT>(Q + row * a.ldq + k0, a.ldq, klen, xs, l, t);
+        finish(row, t[0]);
     }
 }
 
@@ -263,7 +217,7 @@ struct GemvQPlan {
     size_t lds, ws;
 };
 
-static GemvQPlan plan_gemv_q(sb_dtype q, int64_t m, int64_t n)
+static GemvQPlan plan_gemv_q(sb_dtype q, int64_t m, int64_t n, int R)
 {
     GemvQPlan p{};
     const int64_t P = q == SB_BF16 ? 8 : 16;
@@ -277,52 +231,53 @@ static GemvQPlan plan_gemv_q(sb_dtype q, int64_t m, int64_t n)
     p.lds = (size_t)round_up(p.KC * 4, 16);
     p.NT = p.lds > 80 * 1024 ? 1024 : (p.lds > 40 * 1024 ? 512 : 256);
     const int64_t wpb = p.NT / 64;
-    const int64_t bpc = std::max<int64_t>(1, std::min<int64_t>((160 * 1024) / (int64_t)p.lds, 32 / wpb));
+    const int64_t bpc = std::max<int64_t>(1, std::min<int64_t>((160 * 1024) / (int64_t)p.lds, SB_GEMVQ_WAVES_PER_CU / wpb));
     const int64_t nvec = ceil_div(p.KC, P);
     int G = 64;
-    while (G > 4 && nvec < (int64_t)G * 4) G >>= 1;
+    const int64_t U = q == SB_BF16 ? SB_GEMVQ_UNROLL_BF16 : SB_GEMVQ_UNROLL_E4M3;
+    while (G > 4 && nvec < (int64_t)G * U) G >>= 1;
     p.G = G;
-    const int64_t pass = wpb * (64 / G);
+    const int64_t pass = wpb * (64 / G) * R;
     const int64_t row_blocks = std::max<int64_t>(1, ceil_div(256 * bpc, p.nsplit));
     p.RB = round_up(std::max<int64_t>(1, ceil_div(m, row_blocks)), pass);
     p.ws = p.nsplit > 1 ? (size_t)(p.nsplit * m * 4) : 0;
     return p;
 }
 
-size_t gemv_q_ws_bytes(sb_dtype q, int64_t m, int64_t n) { return plan_gemv_q(q, m, n).ws; }
+size_t gemv_q_ws_bytes(sb_dtype q, int64_t m, int64_t n) { return plan_gemv_q(q, m, n, 1).ws; }
 
-template <bool BF16, int G, int NT>
+template <bool BF16, int G, int NT, int R>
 static void launch_q(const GemvQArgs& a, dim3 grid, size_t lds, hipStream_t st)
 {
     static const bool attr_set = [] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemv_q_kernel<BF16, G, NT>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemv_q_kernel<BF16, G, NT, R>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         return true;
     }();
     (void)attr_set;
-    hipLaunchKernelGGL((gemv_q_kernel<BF16, G, NT>), grid, dim3(NT), lds, st, a);
+    hipLaunchKernelGGL((gemv_q_kernel<BF16, G, NT, R>), grid, dim3(NT), lds, st, a);
 }
 
-template <bool BF16, int NT>
+template <bool BF16, int NT, int R>
 static bool dispatch_q_g(int G, const GemvQArgs& a, dim3 grid, size_t lds, hipStream_t st)
 {
     switch (G) {
-    case 4: launch_q<BF16, 4, NT>(a, grid, lds, st); return true;
-    case 8: launch_q<BF16, 8, NT>(a, grid, lds, st); return true;
-    case 16: launch_q<BF16, 16, NT>(a, grid, lds, st); return true;
-    case 32: launch_q<BF16, 32, NT>(a, grid, lds, st); return true;
-    case 64: launch_q<BF16, 64, NT>(a, grid, lds, st); return true;
+    case 4: launch_q<BF16, 4, NT, R>(a, grid, lds, st); return true;
+    case 8: launch_q<BF16, 8, NT, R>(a, grid, lds, st); return true;
+    case 16: launch_q<BF16, 16, NT, R>(a, grid, lds, st); return true;
+    case 32: launch_q<BF16, 32, NT, R>(a, grid, lds, st); return true;
+    case 64: launch_q<BF16, 64, NT, R>(a, grid, lds, st); return true;
     }
     return false;
 }
 
-template <bool BF16>
+template <bool BF16, int R>
 static bool dispatch_q(int NT, int G, const GemvQArgs& a, dim3 grid, size_t lds, hipStream_t st)
 {
     switch (NT) {
-    case 256: return dispatch_q_g<BF16, 256>(G, a, grid, lds, st);
-    case 512: return dispatch_q_g<BF16, 512>(G, a, grid, lds, st);
-    case 1024: return dispatch_q_g<BF16, 1024>(G, a, grid, lds, st);
+    case 256: return dispatch_q_g<BF16, 256, R>(G, a, grid, lds, st);
+    case 512: return dispatch_q_g<BF16, 512, R>(G, a, grid, lds, st);
+    case 1024: return dispatch_q_g<BF16, 1024, R>(G, a, grid, lds, st);
     }
     return false;
 }
@@ -331,13 +286,23 @@ sb_status run_gemv_q(sb_handle* h, sb_dtype q, int64_t m, int64_t n, const void*
                      const float* scales, const float* x, float* c)
 {
     if (m == 0 || n == 0) return SB_OK;
-    const GemvQPlan p = plan_gemv_q(q, m, n);
+    const int csize = q == SB_BF16 ? 2 : 1;
+    // Row tiles need every row of a tile at the same 16-byte alignment.
+    const bool rows_aligned = (ldq * csize) % 16 == 0;
+    constexpr int RB16 = SB_GEMVQ_ROWS_BF16, RE4 = SB_GEMVQ_ROWS_E4M3;
+    const int R = rows_aligned ? (q == SB_BF16 ? RB16 : RE4) : 1;
+    const GemvQPlan p = plan_gemv_q(q, m, n, R);
     if (p.ws > h->ws_bytes)
         return fail(h, SB_ENOMEM, "gemv_q needs %zu workspace bytes, handle has %zu", p.ws, h->ws_bytes);
     GemvQArgs a{m, n, ldq, Aq, scales, x, c, p.nsplit > 1 ? static_cast<float*>(h->ws) : nullptr, p.KC, p.RB};
     const dim3 grid((unsigned)ceil_div(m, p.RB), (unsigned)p.nsplit);
-    const bool ok = q == SB_BF16 ? dispatch_q<true>(p.NT, p.G, a, grid, p.lds, h->stream)
-                                 : dispatch_q<false>(p.NT, p.G, a, grid, p.lds, h->stream);
+    bool ok;
+    if (q == SB_BF16)
+        ok = R == 1 ? dispatch_q<true, 1>(p.NT, p.G, a, grid, p.lds, h->stream)
+                    : dispatch_q<true, RB16>(p.NT, p.G, a, grid, p.lds, h->stream);
+    else
+        ok = R == 1 ? dispatch_q<false, 1>(p.NT, p.G, a, grid, p.lds, h->stream)
+                    : dispatch_q<false, RE4>(p.NT, p.G, a, grid, p.lds, h->stream);
     if (!ok) return fail(h, SB_EINTERNAL, "no gemv_q instance for NT=%d G=%d", p.NT, p.G);
     sb_status st = check_launch(h, "gemv_q_kernel");
     if (st != SB_OK || p.nsplit == 1) return st;

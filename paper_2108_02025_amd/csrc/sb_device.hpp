@@ -21,11 +21,19 @@ constexpr int kWave = 64;
 
 // Loads of operands that are read exactly once (A, C, DOT's x and y) use the
 // non-temporal hint so they stream past L2 and MALL instead of evicting the
-// reused vector (x of GEMV).
-template <typename V>
-__device__ __forceinline__ V ld_stream(const V* p) { return __builtin_nontemporal_load(p); }
-template <typename V>
-__device__ __forceinline__ void st_stream(V* p, V v) { __builtin_nontemporal_store(v, p); }
+// reused vector (x of GEMV).  NT selects the hint at compile time.
+template <bool NT = true, typename V>
+__device__ __forceinline__ V ld_stream(const V* p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT = true, typename V>
+__device__ __forceinline__ void st_stream(V* p, V v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 
 // Separately rounded multiply / add / subtract.  Contraction into fused
 // multiply-add is switched off inside each helper, so the operation keeps

@@ -76,6 +76,11 @@ sb_status run_gemv_q(sb_handle* h, sb_dtype q, int64_t m, int64_t n, const void*
                      const float* scales, const float* x, float* c);
 size_t gemv_q_ws_bytes(sb_dtype q, int64_t m, int64_t n);
 
+// ---- measurement probes ---------------------------------------------------
+size_t probe_ws_bytes(size_t bytes);
+sb_status run_stream_read(sb_handle* h, const void* src, size_t bytes);
+sb_status run_stream_copy(sb_handle* h, const void* src, void* dst, size_t bytes);
+
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 }  // namespace sb

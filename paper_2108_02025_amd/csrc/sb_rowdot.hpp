@@ -1,0 +1,197 @@
+// Per-row dot products shared by the single-call GEMV kernels and the
+// batched kernel, so both run exactly the same arithmetic on a row.
+//
+// A group of G lanes (G a power of two, 4..64) owns a row segment of klen
+// elements; x for the segment sits in LDS.  Each lane streams 16-byte
+// vectors at lane stride, U of them in flight, and returns its partial sum;
+// the caller reduces the group.  The order of a lane's additions depends
+// only on (G, element width, row alignment), not on U.
+#pragma once
+
+#include <type_traits>
+
+#include "sb_device.hpp"
+
+namespace sb {
+
+// Plain binary64 / binary32 row segment.  ALIGNED: the row start is 16-byte
+// aligned (true for every row when A and ld*sizeof(T) are), so x can be read
+// from LDS as vectors; otherwise up to W-1 leading elements are peeled.
+template <typename T, int G, int U, bool ALIGNED, bool NTL>
+__device__ __forceinline__ T row_dot(const T* Ar, int64_t klen, const T* xs, int l)
+{
+    typedef typename Vec<T>::type V;
+    constexpr int W = Vec<T>::W;
+    int64_t head = 0;
+    if (!ALIGNED) {
+        head = ((16 - (reinterpret_cast<uintptr_t>(Ar) & 15)) & 15) / sizeof(T);
+        head = min(head, klen);
+    }
+    V acc = (V)0;
+    if (!ALIGNED && l < head) acc[0] = Ar[l] * xs[l];
+
+    const int64_t nv = (klen - head) / W;
+    const V* Av = reinterpret_cast<const V*>(Ar + head);
+    const T* xb = xs + head;
+    int64_t v = l;
+    for (; v + (U - 1) * G < nv; v += U * G) {
+        V av[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) av[u] = ld_stream<NTL>(Av + v + u * G);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = (v + u * G) * W;
+            if (ALIGNED) {
+                acc += av[u] * *reinterpret_cast<const V*>(xb + e);
+            } else {
+#pragma unroll
+                for (int q = 0; q < W; ++q) acc[q] += av[u][q] * xb[e + q];
+            }
+        }
+    }
+    for (; v < nv; v += G) {
+        const V av = ld_stream<NTL>(Av + v);
+        const int64_t e = v * W;
+#pragma unroll
+        for (int q = 0; q < W; ++q) acc[q] += av[q] * xb[e + q];
+    }
+    const int64_t t0 = head + nv * W;  // fewer than W elements remain
+    if (l < klen - t0) acc[1 % W] += Ar[t0 + l] * xs[t0 + l];
+
+    T t = acc[0];
+#pragma unroll
+    for (int q = 1; q < W; ++q) t += acc[q];
+    return t;
+}
+
+// ---- narrow storage: bfloat16 / OCP E4M3FN codes, binary32 arithmetic ----
+
+template <bool BF16> struct Codes;
+template <> struct Codes<true> {
+    typedef uint16_t code_t;
+    static constexpr int PER16 = 8;  // values per 16-byte load
+    __device__ static float one(uint16_t c) { return __uint_as_float((uint32_t)c << 16); }
+    // 4 dwords -> 8 values, element order preserved
+    __device__ static void unpack(const v4u& w, float* f)
+    {
+        const uint32_t d[4] = {w[0], w[1], w[2], w[3]};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            f[2 * k] = __uint_as_float(d[k] << 16);
+            f[2 * k + 1] = __uint_as_float(d[k] & 0xFFFF0000u);
+        }
+    }
+};
+template <> struct Codes<false> {
+    typedef uint8_t code_t;
+    static constexpr int PER16 = 16;
+    __device__ static float one(uint8_t c)
+    {
+        return __builtin_amdgcn_cvt_f32_fp8((int)c, 0);
+    }
+    __device__ static void unpack(const v4u& w, float* f)
+    {
+        const uint32_t d[4] = {w[0], w[1], w[2], w[3]};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)d[k], false);
+            const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)d[k], true);
+            f[4 * k] = lo[0];
+            f[4 * k + 1] = lo[1];
+            f[4 * k + 2] = hi[0];
+            f[4 * k + 3] = hi[1];
+        }
+    }
+};
+
+// Partial dot products of R consecutive rows (Q0 is the first, rows ldq
+// codes apart) with the staged x, for lane l of a group of G lanes.  All R
+// rows must share the same 16-byte alignment.  A lane's additions happen in
+// the same order for any U and R, so the result does not depend on them.
+template <class C, int G, int U, int R, bool NTL>
+__device__ __forceinline__ void tile_dot(const typename C::code_t* Q0, int64_t ldq, int64_t klen,
+                                         const float* xs, int l, float (&t)[R])
+{
+    typedef typename C::code_t code_t;
+    constexpr int P = C::PER16;
+    int64_t head = ((16 - (reinterpret_cast<uintptr_t>(Q0) & 15)) & 15) / sizeof(code_t);
+    head = min(head, klen);
+    float acc[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0f;
+    for (int64_t e = l; e < head; e += G) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r][0] += C::one(Q0[r * ldq + e]) * xs[e];
+    }
+    const int64_t nv = (klen - head) / P;
+    const float* xb = xs + head;
+    const bool xal = ((head * 4) & 15) == 0;
+    const v4u* Qv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) Qv[r] = reinterpret_cast<const v4u*>(Q0 + r * ldq + head);
+    int64_t v = l;
+    // Main loop: U loads per row in flight, then one straight-line step per
+    // load (the x-alignment choice is hoisted so each step is one block).
+    auto main_loop = [&](auto xal_tag) {
+        constexpr bool XAL = decltype(xal_tag)::value;
+        for (; v + (U - 1) * G < nv; v += U * G) {
+            v4u wv[U][R];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) wv[u][r] = ld_stream<NTL>(Qv[r] + v + u * G);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const float* xe = xb + (v + u * G) * P;
+                float xr[P];
+#pragma unroll
+                for (int q = 0; q < P; q += 4) {
+                    if constexpr (XAL) {
+                        const v4f xv = *reinterpret_cast<const v4f*>(xe + q);
+                        xr[q] = xv[0];
+                        xr[q + 1] = xv[1];
+                        xr[q + 2] = xv[2];
+                        xr[q + 3] = xv[3];
+                    } else {
+                        xr[q] = xe[q];
+                        xr[q + 1] = xe[q + 1];
+                        xr[q + 2] = xe[q + 2];
+                        xr[q + 3] = xe[q + 3];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    float f[P];
+                    C::unpack(wv[u][r], f);
+#pragma unroll
+                    for (int q = 0; q < P; ++q) acc[r][q & 3] += f[q] * xr[q];
+                }
+                // Keep each step's LDS reads and decodes inside the step:
+                // hoisted all together they need more than 200 VGPRs.  The
+                // global loads above are already in flight.
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    };
+    if (xal) main_loop(std::true_type{});
+    else main_loop(std::false_type{});
+    for (; v < nv; v += G) {
+        const float* xe = xb + v * P;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float f[P];
+            C::unpack(ld_stream<NTL>(Qv[r] + v), f);
+#pragma unroll
+            for (int q = 0; q < P; ++q) acc[r][q & 3] += f[q] * xe[q];
+        }
+    }
+    for (int64_t e = head + nv * P + l; e < klen; e += G) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r][1] += C::one(Q0[r * ldq + e]) * xs[e];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) t[r] = (acc[r][0] + acc[r][1]) + (acc[r][2] + acc[r][3]);
+}
+
+}  // namespace sb

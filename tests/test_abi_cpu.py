@@ -119,3 +119,66 @@ def test_handle_errors(L):
     assert b"workspace" in L.sb_last_error(None)
     assert L.sb_set_stream(None, None) == -1
     assert L.sb_handle_destroy(None) == 0
+
+
+def _desc(sbmod, dtype, m, n, A, c, x=X_, lda=None, scales=0, **cfg):
+    d = sbmod.sb_gemv_desc()
+    d.dtype, d.m, d.n, d.lda = dtype, m, n, lda or max(n, 1)
+    d.A, d.x, d.c, d.scales = A, x, c, scales or None
+    d.group, d.rows_per_tile, d.split = cfg.get("group", 0), cfg.get("rows_per_tile", 0), cfg.get("split", 0)
+    return d
+
+
+def test_batched_resolve_encode_on_host(L):
+    """Descriptor resolution and table encoding are pure host work."""
+    import struct
+
+    import paper_2108_02025_amd as sb
+    arr = (sb.sb_gemv_desc * 3)()
+    arr[0] = _desc(sb, 1, 1000, 8192, A_, C_)                       # binary32: x fits one 32 KiB chunk
+    arr[1] = _desc(sb, 0, 64, 10000, A_ + (1 << 30), C_ + (1 << 20))  # binary64: needs 3 chunks
+    arr[2] = _desc(sb, 2, 5, 7, A_ + (2 << 30), C_ + (2 << 20), scales=X_ + 4096, group=8, rows_per_tile=32)
+    out = (sb.sb_gemv_desc * 3)()
+    assert L.sb_gemv_batched_resolve(arr, 3, out) == 0
+    assert out[0].split == 1 and out[1].split == 3
+    assert (out[2].group, out[2].rows_per_tile, out[2].split) == (8, 32, 1)
+    for k in range(3):
+        assert out[k].group in (4, 8, 16, 32, 64) and out[k].rows_per_tile % (4 * 64 // out[k].group) == 0
+    img = ctypes.c_size_t(0)
+    total = L.sb_gemv_batched_table_bytes(arr, 3, ctypes.byref(img))
+    assert total >= img.value > 64 + 3 * 128
+    buf = (ctypes.c_ubyte * img.value)()
+    dev_table = 1 << 44
+    assert L.sb_gemv_batched_encode(arr, 3, ctypes.c_void_p(dev_table), buf, img.value) == 0
+    count, ntiles = struct.unpack_from("<qq", buf, 0)
+    tiles = []
+    for k in range(3):
+        rec = 64 + 128 * k
+        dtype, G, RT, S = struct.unpack_from("<iiii", buf, rec)
+        m, n, lda, KC, tile0, rtiles = struct.unpack_from("<qqqqqq", buf, rec + 16)
+        assert (dtype, G, RT, S) == (arr[k].dtype, out[k].group, out[k].rows_per_tile, out[k].split)
+        assert KC % 16 == 0 and KC * S >= n and rtiles == -(-m // RT)
+        tiles.append((tile0, rtiles * S))
+    assert count == 3 and tiles[0][0] == 0
+    assert tiles[1][0] == tiles[0][1] and tiles[2][0] == tiles[1][0] + tiles[1][1]
+    assert ntiles == sum(t for _, t in tiles)
+
+
+def test_batched_validation(L):
+    import paper_2108_02025_amd as sb
+    bad = [
+        _desc(sb, 1, 10, 10, A_, C_, group=3),                 # group not a power of two in 4..64
+        _desc(sb, 1, 10, 10, A_, C_, group=64, rows_per_tile=3),  # not a multiple of 4 rows
+        _desc(sb, 0, 10, 10000, A_, C_, split=1),              # binary64 chunk of 10000 > 4096 columns
+        _desc(sb, 1, 10, 10, A_, C_, lda=5),                   # lda < n
+        _desc(sb, 2, 10, 10, A_, C_),                          # codes without scales
+        _desc(sb, 7, 10, 10, A_, C_),                          # bad dtype
+    ]
+    for d in bad:
+        arr = (sb.sb_gemv_desc * 1)(d)
+        assert L.sb_gemv_batched_table_bytes(arr, 1, None) == (1 << 64) - 1
+    two = (sb.sb_gemv_desc * 2)(_desc(sb, 1, 10, 10, A_, C_), _desc(sb, 1, 10, 10, A_, C_ + 20))
+    assert L.sb_gemv_batched_resolve(two, 2, (sb.sb_gemv_desc * 2)()) == -1  # outputs overlap
+    assert b"overlap" in L.sb_last_error(None)
+    empty = (sb.sb_gemv_desc * 1)(_desc(sb, 1, 0, 10, 0, 0, x=0))
+    assert L.sb_gemv_batched_table_bytes(empty, 1, None) == 64 + 128

@@ -1,0 +1,173 @@
+"""Batched persistent GEMV on the GPU: every problem of a random mix against
+the oracle, the same problem alone vs in the mix (bitwise), explicit
+configurations with split-K, table reuse, and graph replay over new tables."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from gpu_util import U32, U64, assert_within, dev, gemv_bound, host
+
+pytestmark = pytest.mark.gpu
+
+Q = {"bf16": 2, "e4m3": 3}
+
+
+def make_problem(sb, rng, kind, m, n, cfg=None, seed=0):
+    """Device problem plus the host data the oracle needs."""
+    A, x, c0 = workloads.gemv_inputs(m, n, seed=seed, dtype=np.float64 if kind == "f64" else np.float32)
+    cfg = cfg or {}
+    if kind in ("f64", "f32"):
+        P = sb.GemvProblem(dev(A), dev(x), dev(c0), **cfg)
+        return P, dict(kind=kind, A=A, x=x, c0=c0)
+    q = Q[kind]
+    codes, s = oracle.quantize_rows(A, oracle.Q_BF16 if kind == "bf16" else oracle.Q_E4M3)
+    cd = dev(codes.view(np.int16) if kind == "bf16" else codes)
+    P = sb.GemvProblem(cd, dev(x), dev(c0), scales=dev(s), q=q, **cfg)
+    return P, dict(kind=kind, codes=codes, s=s, x=x, c0=c0)
+
+
+def oracle_check(P, H):
+    got = host(P.c).astype(np.float64)
+    if H["kind"] in ("f64", "f32"):
+        m, n = H["A"].shape
+        ref = oracle.gemv(H["A"], H["x"], H["c0"])
+        u = U64 if H["kind"] == "f64" else U32
+        assert_within(got, ref, gemv_bound(H["A"], H["x"], H["c0"], 0, n, u), H["kind"])
+    else:
+        qk = oracle.Q_BF16 if H["kind"] == "bf16" else oracle.Q_E4M3
+        ref = oracle.gemv_q(H["codes"], H["s"], H["x"], H["c0"], qk)
+        dec = np.vectorize(oracle.bf16_to_f32 if qk == oracle.Q_BF16 else oracle.e4m3_to_f32, otypes=[np.float64])
+        lut = dec(np.arange(1 << 16 if qk == oracle.Q_BF16 else 256))
+        mag = (np.abs(lut[H["codes"]]) * H["s"][:, None].astype(np.float64)) @ np.abs(H["x"].astype(np.float64))
+        n = H["codes"].shape[1]
+        bound = 2 * (n + 2) * U32 * (np.abs(H["c0"]) + mag) + 1e-30
+        assert_within(got, ref, bound, H["kind"])
+
+
+def fresh_copy(sb, P, H):
+    """The same problem with its own output vector reset to c0."""
+    return sb.GemvProblem(P.A, P.x, dev(H["c0"]), scales=P.scales, q=P.q, group=P.group,
+                          rows_per_tile=P.rows_per_tile, split=P.split)
+
+
+def test_batched_random_mix_alone_vs_mix(sb):
+    rng = np.random.default_rng(501)
+    kinds = ["f64", "f32", "bf16", "e4m3"]
+    probs, hosts = [], []
+    for i in range(40):
+        m = int(np.exp(rng.uniform(np.log(1), np.log(3000))))
+        n = int(np.exp(rng.uniform(np.log(1), np.log(9000))))
+        P, H = make_problem(sb, rng, kinds[i % 4], m, n, seed=1000 + i)
+        probs.append(P)
+        hosts.append(H)
+    sb.sb_gemv_batched(probs)
+    mix = [host(P.c).copy() for P in probs]
+    for P, H, got in zip(probs, hosts, mix):
+        oracle_check(P, H)
+        alone = fresh_copy(sb, P, H)
+        sb.sb_gemv_batched([alone])
+        assert np.array_equal(host(alone.c), got), "alone differs from mix"
+
+
+@pytest.mark.parametrize("cfg", [dict(group=4, rows_per_tile=64, split=1), dict(group=16, rows_per_tile=16, split=3),
+                                 dict(group=64, rows_per_tile=8, split=2), dict(group=32, rows_per_tile=0, split=5),
+                                 dict(group=8, rows_per_tile=32, split=0)])
+@pytest.mark.parametrize("kind", ["f64", "f32", "bf16", "e4m3"])
+def test_batched_configs(sb, cfg, kind):
+    rng = np.random.default_rng(7)
+    probs, hosts = [], []
+    for i, (m, n) in enumerate([(1, 5), (37, 1000), (300, 4099), (1025, 33), (64, 8192), (5, 20000)]):
+        max_kc = 4096 if kind == "f64" else 8192  # x chunk of a tile: 32 KiB of LDS
+        sp = cfg.get("split") or 0
+        if sp and -(-(-(-n // sp)) // 16) * 16 > max_kc:
+            continue  # this split leaves a chunk too wide for LDS (rejected by design)
+        P, H = make_problem(sb, rng, kind, m, n, cfg=cfg, seed=i)
+        probs.append(P)
+        hosts.append(H)
+    sb.sb_gemv_batched(probs)
+    for P, H in zip(probs, hosts):
+        oracle_check(P, H)
+    # the same problems again in reverse order with fresh outputs: same bits
+    again = [fresh_copy(sb, P, H) for P, H in zip(probs, hosts)][::-1]
+    sb.sb_gemv_batched(again)
+    for P, Q2 in zip(probs, again[::-1]):
+        assert torch.equal(P.c, Q2.c)
+
+
+def test_batched_integer_exact_and_table_reuse(sb):
+    """Integer data is exact; launching the same table twice adds A x twice
+    (split counters re-arm themselves)."""
+    rng = np.random.default_rng(3)
+    probs, refs = [], []
+    for i, (m, n) in enumerate([(100, 3000), (7, 9000), (513, 513)]):
+        A, x, c0 = workloads.gemv_inputs(m, n, seed=i, dist="int8")
+        P = sb.GemvProblem(dev(A), dev(x), dev(c0), split=3)
+        probs.append(P)
+        refs.append((A.astype(np.int64), x.astype(np.int64), c0))
+    table = sb.BatchTable(sb.sb_gemv_batched_table_bytes(probs)[0])
+    table.encode(probs)
+    table.run()
+    table.run()
+    for P, (A, x, c0) in zip(probs, refs):
+        assert np.array_equal(host(P.c), c0 + 2 * (A @ x))
+
+
+def test_batched_graph_replay(sb):
+    """A captured launch replayed over new tables written to the same
+    address gives the eager results, replay after replay."""
+    rng = np.random.default_rng(11)
+    batches = []
+    for b in range(3):
+        ps, hs = [], []
+        for i in range(6):
+            m, n = int(rng.integers(1, 900)), int(rng.integers(1, 5000))
+            P, H = make_problem(sb, rng, ["f32", "bf16"][i % 2], m, n, seed=100 * b + i)
+            ps.append(P)
+            hs.append(H)
+        batches.append((ps, hs))
+    cap = max(sb.sb_gemv_batched_table_bytes(ps)[0] for ps, _ in batches)
+    table = sb.BatchTable(cap)
+    eager = []
+    for ps, hs in batches:
+        fresh = [fresh_copy(sb, P, H) for P, H in zip(ps, hs)]
+        sb.sb_gemv_batched(fresh)
+        eager.append([host(P.c).copy() for P in fresh])
+    table.encode(batches[0][0])
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        table.run()                       # warm-up outside capture
+        torch.cuda.synchronize()
+        for P, H in zip(*batches[0]):
+            P.c.copy_(dev(H["c0"]))
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=s):
+            table.run()
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for (ps, hs), ref in zip(batches, eager):
+            for P, H in zip(ps, hs):
+                P.c.copy_(dev(H["c0"]))
+            table.encode(ps)
+            graph.replay()
+            torch.cuda.synchronize()
+            for P, r in zip(ps, ref):
+                assert np.array_equal(host(P.c), r), f"replay {rep}"
+
+
+def test_batched_rejects_bad_input(sb):
+    A = torch.zeros((10, 10), dtype=torch.float32, device="cuda")
+    x = torch.zeros(10, dtype=torch.float32, device="cuda")
+    c = torch.zeros(10, dtype=torch.float32, device="cuda")
+    with pytest.raises(sb.StreamBlasError):
+        sb.sb_gemv_batched_resolve([sb.GemvProblem(A, x, c, group=3)])
+    with pytest.raises(sb.StreamBlasError):
+        sb.sb_gemv_batched_resolve([sb.GemvProblem(A, x, c), sb.GemvProblem(A, x, c)])  # shared output
+    with pytest.raises(sb.StreamBlasError):
+        sb.sb_gemv_batched_resolve([sb.GemvProblem(A, x, c, group=64, rows_per_tile=3)])
+    r = sb.sb_gemv_batched_resolve([sb.GemvProblem(A, x, c)])
+    assert r[0]["split"] == 1 and r[0]["group"] in (4, 8, 16, 32, 64)

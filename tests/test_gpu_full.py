@@ -1,0 +1,221 @@
+"""GPU parity at the full workload sizes, in the launch configurations the
+benchmark times: binary64 GEMV N/T at 16384 x 16384, DOT at n = 2^28, GER at
+16384 x 16384, the skewed GEMV shapes in binary64 and binary32, and the
+precision forms (quantiser, quantised GEMV, compensated DOT).  Every output
+of every case is checked against the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from gpu_util import U32, U64, assert_within, dev, gamma, gemv_bound, host, normwise
+
+pytestmark = pytest.mark.gpu
+
+
+def gemv_case(sb, m, n, op, seed, dist, npd, lda=None):
+    A, x, c0 = workloads.gemv_inputs(m, n, seed=seed, dist=dist, op_t=bool(op), dtype=npd, lda=lda)
+    Av = A[:, :n]
+    ref = oracle.gemv(A.reshape(-1), x, c0, op=op, lda=A.shape[1], shape=(m, n))
+    Ad = dev(A)[:, :n]
+    cd = dev(c0)
+    sb.sb_gemv(Ad, dev(x), cd, op=op)
+    got = host(cd)
+    K = n if op == 0 else m
+    return got, ref, gemv_bound(Av, x, c0, op, K, U64 if npd == np.float64 else U32)
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_gemv_16384_f64(sb, op):
+    got, ref, bnd = gemv_case(sb, 16384, 16384, op, 201, "uniform", np.float64)
+    assert_within(got, ref, bnd, f"16384^2 op={op}")
+
+
+def test_gemv_16384_f64_integer(sb):
+    for op in (0, 1):
+        A, x, c0 = workloads.gemv_inputs(16384, 16384, seed=205, dist="int8", op_t=bool(op))
+        cd = dev(c0)
+        sb.sb_gemv(dev(A), dev(x), cd, op=op)
+        assert np.array_equal(host(cd), oracle.gemv(A, x, c0, op=op))
+
+
+SKEWED = [(262144, 256, 301), (256, 262144, 302), (65536, 4096, 303), (65537, 4093, 304)]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("m,n,seed", SKEWED)
+@pytest.mark.parametrize("op", [0, 1])
+def test_gemv_skewed(sb, dt, m, n, seed, op):
+    npd = np.float64 if dt == "f64" else np.float32
+    got, ref, bnd = gemv_case(sb, m, n, op, seed, "normal", npd)
+    assert_within(got, ref, bnd, f"{m}x{n} {dt} op={op}")
+    if dt == "f32":
+        assert normwise(got, ref) < 2.0 ** -16
+
+
+@pytest.mark.parametrize("m,n,seed", SKEWED)
+def test_gemv_skewed_integer_f32(sb, m, n, seed):
+    """binary32 integer data in [-7, 7]: partial sums stay below 2^24, so the
+    result is exact in every order."""
+    A, x, c0 = workloads.gemv_inputs(m, n, seed=seed, dist="int7", dtype=np.float32)
+    cd = dev(c0)
+    sb.sb_gemv(dev(A), dev(x), cd)
+    assert np.array_equal(host(cd).astype(np.float64), oracle.gemv(A, x, c0))
+
+
+def test_dot_2p28(sb):
+    n = 1 << 28
+    x, y, a0 = workloads.dot_inputs(n, seed=202)
+    ref = oracle.dot(x, y, a0[0])
+    ad = dev(a0)
+    sb.sb_dot(dev(x), dev(y), ad)
+    got = host(ad)[0]
+    mag = abs(a0[0]) + float(np.sum(np.abs(x * y)))
+    assert abs(got - ref) <= 2 * gamma(n + 1, U64) * mag
+    # x = y = 1: the sum is n exactly
+    ones = torch.ones(n, dtype=torch.float64, device="cuda")
+    ad = dev(np.zeros(1))
+    sb.sb_dot(ones, ones, ad)
+    assert host(ad)[0] == float(n)
+
+
+def test_ger_16384_bitwise(sb):
+    x, y, C0 = workloads.ger_inputs(16384, 16384, seed=203)
+    Cd = dev(C0)
+    sb.sb_ger(dev(x), dev(y), Cd)
+    got = host(Cd)
+    ref = oracle.ger(x, y, C0)
+    assert np.array_equal(got, ref)
+
+
+# ------------------------------------------------------- precision forms ----
+
+@pytest.fixture(scope="module")
+def a32_16384():
+    A, _, _ = workloads.gemv_inputs(16384, 16384, seed=201)
+    return A.astype(np.float32)
+
+
+@pytest.mark.parametrize("q", ["bf16", "e4m3"])
+def test_quantiser_bitwise_and_gemv_q(sb, a32_16384, q):
+    """GPU codes and scales equal the oracle's bit for bit on the 16384^2
+    matrix; the quantised GEMV lies within the binary32 bound of the
+    dequantised reference, and its normwise error against the binary64
+    product of the unquantised matrix is reported (<= 1e-2 required for
+    bfloat16)."""
+    qc = sb.SB_BF16 if q == "bf16" else sb.SB_FP8_E4M3
+    A32 = a32_16384
+    m, n = A32.shape
+    Ad = dev(A32)
+    Aq = torch.empty((m, n), dtype=torch.int16 if q == "bf16" else torch.uint8, device="cuda")
+    s = torch.empty(m, dtype=torch.float32, device="cuda")
+    sb.sb_quantize_rows(Ad, Aq, s, qc)
+    del Ad
+    codes_ref, s_ref = oracle.quantize_rows(A32, oracle.Q_BF16 if q == "bf16" else oracle.Q_E4M3)
+    codes = host(Aq).view(np.uint16 if q == "bf16" else np.uint8)
+    assert np.array_equal(host(s), s_ref)
+    assert np.array_equal(codes, codes_ref)
+    x = np.random.default_rng(401).standard_normal(n).astype(np.float32)
+    cd = torch.zeros(m, dtype=torch.float32, device="cuda")
+    sb.sb_gemv_q(Aq, s, dev(x), cd, qc)
+    got = host(cd).astype(np.float64)
+    r1 = oracle.gemv_q(codes_ref, s_ref, x, np.zeros(m), oracle.Q_BF16 if q == "bf16" else oracle.Q_E4M3)
+    mag = np.abs(A32.astype(np.float64)) @ np.abs(x.astype(np.float64))
+    # |s_i q_ij| <= (1 + 2^-3)|a_ij| + s_i 2^-9 for both formats (E4M3 subnormal quantum)
+    bound = 2 * gamma(n + 2, U32) * (1.125 * mag + s_ref.astype(np.float64) * np.abs(x).sum())
+    assert_within(got, r1, bound, f"gemv_q {q} vs dequantised reference")
+    r2 = oracle.gemv(A32, x, np.zeros(m))
+    err = normwise(got, r2)
+    print(f"gemv_q {q}: normwise error vs binary64 oracle on unquantised A = {err:.3e}")
+    if q == "bf16":
+        assert err <= 1e-2
+    else:
+        assert err <= 0.1
+
+
+@pytest.mark.parametrize("q", ["bf16", "e4m3"])
+def test_decode_every_code(sb, q):
+    """Every code decoded by the quantised GEMV's vector path: row i holds
+    code i at column i mod P among zero codes, x is all ones, s = 1."""
+    P = 8 if q == "bf16" else 16
+    ncodes = 1 << 16 if q == "bf16" else 256
+    codes = np.zeros((ncodes, P), dtype=np.uint16 if q == "bf16" else np.uint8)
+    codes[np.arange(ncodes), np.arange(ncodes) % P] = np.arange(ncodes)
+    Aq = dev(codes.view(np.int16) if q == "bf16" else codes)
+    cd = torch.zeros(ncodes, dtype=torch.float32, device="cuda")
+    sb.sb_gemv_q(Aq, torch.ones(ncodes, device="cuda"), torch.ones(P, device="cuda"), cd,
+                 sb.SB_BF16 if q == "bf16" else sb.SB_FP8_E4M3)
+    got = host(cd)
+    dec = oracle.bf16_to_f32 if q == "bf16" else oracle.e4m3_to_f32
+    ref = np.array([dec(c) for c in range(ncodes)], dtype=np.float32)
+    same = (got == ref) | (np.isnan(got) & np.isnan(ref))
+    assert same.all(), np.flatnonzero(~same)[:10]
+
+
+@pytest.mark.parametrize("q", ["bf16", "e4m3"])
+def test_gemv_q_integer_exact_and_shapes(sb, q):
+    """Unit scales, integer codes: exact.  Ragged shapes and a misaligned code
+    base exercise the scalar head and tail."""
+    qc = sb.SB_BF16 if q == "bf16" else sb.SB_FP8_E4M3
+    enc = oracle.bf16_from_f32 if q == "bf16" else oracle.e4m3_from_f32
+    cdt = np.uint16 if q == "bf16" else np.uint8
+    rng = np.random.default_rng(71)
+    for m, n in ((1, 1), (3, 17), (100, 1000), (513, 4099), (64, 70001)):
+        Aint = rng.integers(-8, 9, (m, n)).astype(np.float32)
+        xs = rng.integers(-8, 9, n).astype(np.float32)
+        table = {v: enc(float(v)) for v in range(-8, 9)}
+        codes = np.vectorize(lambda v: table[int(v)])(Aint).astype(cdt)
+        for off in (0, 1):
+            buf = np.zeros(m * n + 1, dtype=cdt)
+            buf[off:off + m * n] = codes.reshape(-1)
+            bd = dev(buf.view(np.int16) if q == "bf16" else buf)
+            Aq = bd[off:off + m * n].reshape(m, n)
+            cd = torch.zeros(m, dtype=torch.float32, device="cuda")
+            sb.sb_gemv_q(Aq, torch.ones(m, device="cuda"), dev(xs), cd, qc)
+            ref = (Aint.astype(np.int64) @ xs.astype(np.int64)).astype(np.float64)
+            assert np.array_equal(host(cd).astype(np.float64), ref), (m, n, off)
+
+
+def dot2_bound(s_exact, abs_sum, L):
+    """Ogita-Rump-Oishi bound for Dot2 with a reduction path of length L:
+    |res - s| <= u|s| + gamma_L^2 * sum|x_i y_i| (u = 2^-24)."""
+    g = gamma(L, U32)
+    return U32 * abs(s_exact) + g * g * abs_sum
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 1000, 65539, 1 << 20])
+def test_dot2_small(sb, n):
+    x, y, a0, _ = workloads.illcond_dot_inputs(max(n, 16), seed=n)
+    x, y = x[:n], y[:n]
+    a0 = np.float32(0.75)
+    ad = dev(np.array([a0], np.float32))
+    sb.sb_dot2_f32(dev(x), dev(y), ad)
+    got = float(host(ad)[0])
+    ex = oracle.dot_exact_f32(x, y, float(a0))
+    ab = oracle.dot_exact_f32(x, y, float(a0), absval=True)
+    assert abs(got - ex) <= dot2_bound(ex, ab, 200) + abs(ex) * U32
+
+
+def test_dot2_2p27_illconditioned(sb):
+    n = 1 << 27
+    x, y, a0, cond = workloads.illcond_dot_inputs(n, seed=402)
+    ex = oracle.dot_exact_f32(x, y)
+    ab = oracle.dot_exact_f32(x, y, absval=True)
+    xd, yd = dev(x), dev(y)
+    ad = torch.zeros(1, dtype=torch.float32, device="cuda")
+    sb.sb_dot2_f32(xd, yd, ad)
+    got = float(host(ad)[0])
+    rel2 = abs(got - ex) / abs(ex)
+    # reduction path: 64 products per lane chain, 2 + 6 + 2 merge levels in a
+    # workgroup, 8 partials per thread and 6 + 2 levels in the second stage,
+    # plus alpha: well below 200
+    assert abs(got - ex) <= dot2_bound(ex, ab, 200)
+    plain = torch.zeros(1, dtype=torch.float32, device="cuda")
+    sb.sb_dot(xd, yd, plain)
+    rel_plain = abs(float(host(plain)[0]) - ex) / abs(ex)
+    f64 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sb.sb_dot(xd.double(), yd.double(), f64)
+    rel64 = abs(float(host(f64)[0]) - ex) / abs(ex)
+    print(f"cond {cond:.3e}: rel error dot2_f32 {rel2:.3e}, plain f32 {rel_plain:.3e}, plain f64 {rel64:.3e}")
+    assert rel2 < rel_plain
