@@ -186,6 +186,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ops", default=None, help="comma-separated subset of operations")
     ap.add_argument("--no-probes", action="store_true", help="skip the HBM read/copy ceiling probes")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -252,6 +253,20 @@ def main():
                    "ops": names, "parallelism": "single GPU"},
         "roofline": roof, "ops": per, **extras,
     }
+    if not args.no_serve:
+        from paper_2108_02025_amd.serve import Server, make_trace
+        serving = {}
+        for label, budget in (("budget_4GiB", 4 << 30), ("budget_512MiB", 512 << 20)):
+            trace = make_trace(4096, rate=1e5, seed=501)
+            server = Server(budget_bytes=budget)
+            st = server.run(trace)
+            serving[label] = st.as_dict()
+            log(f"serving {label}: p50 {st.p50_ms:.2f} ms, p99 {st.p99_ms:.2f} ms, "
+                f"{st.achieved_rate:.0f} req/s, aggregate {st.aggregate_GBs:.1f} GB/s, "
+                f"device-busy {st.device_busy_GBs:.1f} GB/s, {st.batches} batches")
+            del server
+        out["serving"] = {"trace": "4096 requests, Poisson 1e5 req/s, m,n log-uniform [64,8192], "
+                                   "f32 / bf16-A 50:50, uniform[-1,1), c0 = 0", **serving}
     if not args.no_cpu:
         log("timing the CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(step_bytes)

@@ -231,6 +231,18 @@ sb_status sb_gemv_batched_run(sb_handle* handle, const void* dev_table, int32_t 
 sb_status sb_gemv_batched(sb_handle* handle, const sb_gemv_desc* descs, int32_t count);
 
 /*
+ * Operand generation (serving form: requests' operands are made on the
+ * device where they are used).  out[k] = 2u - 1 with u = (z >> 11) * 2^-53
+ * and z = SplitMix64(seed, counter0 + k) (Steele, Lea and Flood, OOPSLA
+ * 2014: z = seed + (c+1)*0x9E3779B97F4A7C15, then the xor-shift-multiply
+ * finaliser with 0xBF58476D1CE4E5B9 and 0x94D049BB133111EB).  dtype SB_F64
+ * stores the binary64 value, SB_F32 rounds it to nearest.  out must be
+ * aligned to the element size; count >= 0.
+ */
+sb_status sb_fill_uniform(sb_handle* handle, sb_dtype dtype, void* out, int64_t count, uint64_t seed,
+                          uint64_t counter0);
+
+/*
  * Measurement probes (not operations of the paper).  They stream a byte
  * range with the same 16-byte non-temporal accesses as the operation
  * kernels, giving the practical HBM ceiling the operations are measured

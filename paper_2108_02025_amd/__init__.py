@@ -26,7 +26,7 @@ __all__ = [
     "sb_version", "sb_status_string", "sb_workspace_bytes",
     "sb_gemv", "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32",
     "sb_stream_read", "sb_stream_copy", "sb_gemv_desc", "GemvProblem", "make_descs", "sb_gemv_batched",
-    "sb_gemv_batched_resolve", "sb_gemv_batched_table_bytes", "BatchTable",
+    "sb_gemv_batched_resolve", "sb_gemv_batched_table_bytes", "BatchTable", "sb_fill_uniform",
 ]
 
 SB_OK, SB_EINVAL, SB_ENOMEM, SB_EDEVICE, SB_EUNSUPPORTED, SB_EINTERNAL = 0, -1, -2, -3, -4, -5
@@ -89,9 +89,10 @@ def load():
     L.sb_gemv_batched_encode.argtypes = [ctypes.POINTER(sb_gemv_desc), I32, P, P, SZ]
     L.sb_gemv_batched_run.argtypes = [P, P, I32]
     L.sb_gemv_batched.argtypes = [P, ctypes.POINTER(sb_gemv_desc), I32]
+    L.sb_fill_uniform.argtypes = [P, I32, P, I64, ctypes.c_uint64, ctypes.c_uint64]
     L.sb_stream_read.argtypes = [P, P, SZ]
     L.sb_stream_copy.argtypes = [P, P, P, SZ]
-    for f in ("sb_gemv_batched_resolve", "sb_gemv_batched_encode", "sb_gemv_batched_run", "sb_gemv_batched",
+    for f in ("sb_fill_uniform", "sb_gemv_batched_resolve", "sb_gemv_batched_encode", "sb_gemv_batched_run", "sb_gemv_batched",
               "sb_stream_read", "sb_stream_copy", "sb_handle_create", "sb_handle_destroy", "sb_set_stream", "sb_set_workspace", "sb_gemv",
               "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32"):
         getattr(L, f).restype = I32
@@ -448,3 +449,14 @@ class BatchTable:
     def run(self, grid: int = 0) -> None:
         self.h.prepare(0)
         self.h.check(load().sb_gemv_batched_run(self.h.h, ctypes.c_void_p(self.dev.data_ptr()), grid))
+
+
+def sb_fill_uniform(out: torch.Tensor, seed: int, counter0: int = 0) -> torch.Tensor:
+    """Fill a contiguous float64/float32 device tensor with SplitMix64 uniforms in [-1, 1)."""
+    if not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous device tensor")
+    dt = _dtype(out)
+    h = handle_for(out)
+    h.prepare(0)
+    h.check(load().sb_fill_uniform(h.h, dt, _ptr(out), out.numel(), seed & ((1 << 64) - 1), counter0))
+    return out

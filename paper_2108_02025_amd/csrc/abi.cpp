@@ -319,6 +319,19 @@ sb_status sb_dot2_f32(sb_handle* handle, int64_t n, const float* x, const float*
     SB_GUARD_END
 }
 
+sb_status sb_fill_uniform(sb_handle* handle, sb_dtype dtype, void* out, int64_t count, uint64_t seed,
+                          uint64_t counter0)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_fill_uniform: NULL handle");
+    if (dtype != SB_F64 && dtype != SB_F32) return fail(handle, SB_EINVAL, "sb_fill_uniform: dtype must be F64 or F32");
+    if (count < 0 || count > kMaxBytes / 8) return fail(handle, SB_EINVAL, "sb_fill_uniform: bad count");
+    if (count > 0 && (!out || misaligned(out, esize_of(dtype))))
+        return fail(handle, SB_EINVAL, "sb_fill_uniform: NULL or misaligned output");
+    SB_GUARD_BEGIN
+    return sb::run_fill_uniform(handle, dtype, out, count, seed, counter0);
+    SB_GUARD_END
+}
+
 static sb_status probe_check(sb_handle* handle, const char* what, const void* src, const void* dst, size_t bytes)
 {
     if (!handle) return fail(nullptr, SB_EINVAL, "%s: NULL handle", what);

@@ -76,6 +76,9 @@ sb_status run_gemv_q(sb_handle* h, sb_dtype q, int64_t m, int64_t n, const void*
                      const float* scales, const float* x, float* c);
 size_t gemv_q_ws_bytes(sb_dtype q, int64_t m, int64_t n);
 
+// ---- operand generation ---------------------------------------------------
+sb_status run_fill_uniform(sb_handle* h, sb_dtype dt, void* out, int64_t count, uint64_t seed, uint64_t counter0);
+
 // ---- measurement probes ---------------------------------------------------
 size_t probe_ws_bytes(size_t bytes);
 sb_status run_stream_read(sb_handle* h, const void* src, size_t bytes);
