@@ -255,10 +255,12 @@ def main():
     }
     if not args.no_serve:
         from paper_2108_02025_amd.serve import Server, make_trace
-        serving = {}
+        from paper_2108_02025_amd.tuner import TuningTable
+        tuning = TuningTable.load()
+        serving = {"tuned": tuning is not None}
         for label, budget in (("budget_4GiB", 4 << 30), ("budget_512MiB", 512 << 20)):
             trace = make_trace(4096, rate=1e5, seed=501)
-            server = Server(budget_bytes=budget)
+            server = Server(budget_bytes=budget, tuning=tuning)
             st = server.run(trace)
             serving[label] = st.as_dict()
             log(f"serving {label}: p50 {st.p50_ms:.2f} ms, p99 {st.p99_ms:.2f} ms, "

@@ -186,7 +186,8 @@ sb_status sb_dot2_f32(sb_handle* handle, int64_t n, const float* x, const float*
  *          scales as written by sb_quantize_rows; x and c are binary32 and
  *          c_i += s_i * sum_j q_ij x_j.
  *   group  lanes cooperating on a row: 4, 8, 16, 32 or 64 (0: automatic).
- *   rows_per_tile  a multiple of 4 * (64 / group) (0: automatic).
+ *   rows_per_tile  a multiple of 4 * (64 / group) (0: automatic, about
+ *          256 KiB of A per tile; the tile height never changes a row's result).
  *   split  column chunks; each chunk's x must fit 32 KiB of LDS (0: automatic).
  * Outputs of different problems must not overlap.  Problems with m = 0 or
  * n = 0 are skipped.
@@ -241,6 +242,30 @@ sb_status sb_gemv_batched(sb_handle* handle, const sb_gemv_desc* descs, int32_t 
  */
 sb_status sb_fill_uniform(sb_handle* handle, sb_dtype dtype, void* out, int64_t count, uint64_t seed,
                           uint64_t counter0);
+
+/*
+ * Batched operand generation for GEMV requests (serving form).  For each
+ * descriptor: A (m x n row-major, lda elements) gets element (i, j) from
+ * counter i*n + j, x gets element j from counter m*n + j (values as
+ * sb_fill_uniform with the descriptor's seed), c is set to zero.  dtype
+ * SB_F32 stores binary32 A; SB_BF16 stores the bfloat16 codes and per-row
+ * scales that sb_quantize_rows would make from that binary32 A (bit for
+ * bit; with n = 0 every scale is 1).  One launch on the handle's stream; the descriptors are copied into
+ * the workspace first (sb_generate_batched_bytes bytes).
+ */
+typedef struct {
+    int32_t dtype;
+    int32_t reserved;
+    int64_t m, n, lda;
+    uint64_t seed;
+    void* A;
+    float* scales;
+    float* x;
+    float* c;
+} sb_gen_desc;
+
+size_t sb_generate_batched_bytes(int32_t count);
+sb_status sb_generate_batched(sb_handle* handle, const sb_gen_desc* descs, int32_t count);
 
 /*
  * Measurement probes (not operations of the paper).  They stream a byte

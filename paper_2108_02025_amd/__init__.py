@@ -90,9 +90,12 @@ def load():
     L.sb_gemv_batched_run.argtypes = [P, P, I32]
     L.sb_gemv_batched.argtypes = [P, ctypes.POINTER(sb_gemv_desc), I32]
     L.sb_fill_uniform.argtypes = [P, I32, P, I64, ctypes.c_uint64, ctypes.c_uint64]
+    L.sb_generate_batched_bytes.argtypes = [I32]
+    L.sb_generate_batched_bytes.restype = SZ
+    L.sb_generate_batched.argtypes = [P, P, I32]
     L.sb_stream_read.argtypes = [P, P, SZ]
     L.sb_stream_copy.argtypes = [P, P, P, SZ]
-    for f in ("sb_fill_uniform", "sb_gemv_batched_resolve", "sb_gemv_batched_encode", "sb_gemv_batched_run", "sb_gemv_batched",
+    for f in ("sb_fill_uniform", "sb_generate_batched", "sb_gemv_batched_resolve", "sb_gemv_batched_encode", "sb_gemv_batched_run", "sb_gemv_batched",
               "sb_stream_read", "sb_stream_copy", "sb_handle_create", "sb_handle_destroy", "sb_set_stream", "sb_set_workspace", "sb_gemv",
               "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32"):
         getattr(L, f).restype = I32
@@ -432,13 +435,23 @@ class BatchTable:
         return sb_gemv_batched_table_bytes(problems)[0] <= self.capacity
 
     def encode(self, problems) -> None:
-        descs = make_descs(problems)
-        total, img = sb_gemv_batched_table_bytes(problems)
+        self.encode_descs(make_descs(problems), len(problems))
+
+    def encode_descs(self, descs, count: int) -> None:
+        """Encode `count` sb_gemv_desc structs at `descs` (a ctypes array or
+        a pointer to structs laid out like sb_gemv_desc)."""
+        if not isinstance(descs, ctypes.Array):
+            descs = ctypes.cast(descs, ctypes.POINTER(sb_gemv_desc))
+        img_c = ctypes.c_size_t(0)
+        total = load().sb_gemv_batched_table_bytes(descs, count, ctypes.byref(img_c))
+        if total == (1 << 64) - 1:
+            raise StreamBlasError(SB_EINVAL, "invalid batched descriptors")
+        img = int(img_c.value)
         if total > self.capacity:
             raise StreamBlasError(SB_ENOMEM, f"batch table needs {total} bytes, capacity {self.capacity}")
         if self._copied is not None:
             self._copied.synchronize()  # the pinned image may still be in flight
-        st = load().sb_gemv_batched_encode(descs, len(problems), ctypes.c_void_p(self.dev.data_ptr()),
+        st = load().sb_gemv_batched_encode(descs, count, ctypes.c_void_p(self.dev.data_ptr()),
                                            ctypes.c_void_p(self.host.data_ptr()), img)
         if st != SB_OK:
             raise StreamBlasError(st, load().sb_last_error(None).decode())

@@ -36,20 +36,35 @@ namespace sb {
 constexpr int kBatNT = 256;
 constexpr int kBatWaves = kBatNT / kWave;
 constexpr int64_t kBatLds = 32 * 1024;     // x chunk bytes per tile
-constexpr int kBatGrid = 1024;             // default persistent grid: 4 workgroups per CU
 constexpr int64_t kBatTileBytes = 256 * 1024;  // automatic tile size target (bytes of A)
-constexpr int kBatUnrollPlain = 8, kBatUnrollBf16 = 2, kBatUnrollE4m3 = 4;
+#ifndef SB_BAT_UNROLL_PLAIN
+#define SB_BAT_UNROLL_PLAIN 8
+#endif
+#ifndef SB_BAT_UNROLL_BF16
+#define SB_BAT_UNROLL_BF16 8
+#endif
+#ifndef SB_BAT_UNROLL_E4M3
+#define SB_BAT_UNROLL_E4M3 4
+#endif
+#ifndef SB_BAT_GRID
+#define SB_BAT_GRID 1024
+#endif
+constexpr int kBatUnrollPlain = SB_BAT_UNROLL_PLAIN, kBatUnrollBf16 = SB_BAT_UNROLL_BF16,
+              kBatUnrollE4m3 = SB_BAT_UNROLL_E4M3;
+constexpr int kBatGrid = SB_BAT_GRID;  // default persistent grid: 4 workgroups per CU
 
 struct BatHeader {
     int64_t count;
     int64_t ntiles;
-    int64_t pad[6];
+    int64_t total_cost;  // sum of tile costs, KiB units
+    int64_t pad[5];
 };
 
 struct BatProblem {
     int32_t dtype, G, RT, S;
     int64_t m, n, lda, KC;
     int64_t tile0, rtiles;
+    int64_t cost0, tile_cost;  // cost before this problem's first tile, and per tile (KiB units)
     const void* A;
     const float* scales;
     const void* x;
@@ -60,11 +75,30 @@ struct BatProblem {
     int64_t pad2;
 };
 static_assert(sizeof(BatHeader) == 64, "header layout");
-static_assert(sizeof(BatProblem) == 128, "problem record layout");
+static_assert(sizeof(BatProblem) == 144, "problem record layout");
+
+// The first tile whose start cost is at least C (tile start costs increase
+// strictly: each tile costs at least the fixed per-tile overhead).
+__device__ __forceinline__ int64_t first_tile_at_cost(const BatProblem* probs, int64_t count, int64_t ntiles,
+                                                      int64_t total, int64_t C)
+{
+    if (C >= total) return ntiles;
+    int64_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (probs[mid].cost0 <= C) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatProblem& p = probs[lo];
+    const int64_t tiles = p.rtiles * p.S;
+    int64_t local = p.tile_cost > 0 ? (C - p.cost0 + p.tile_cost - 1) / p.tile_cost : 0;
+    if (local > tiles) local = tiles;
+    return p.tile0 + local;
+}
 
 // Rows [r0, r1) of one tile, per-row results to c or to the split partials.
 // Not inlined: each (dtype, group, alignment) variant gets its own register
-// allocation instead of the kernel carrying all thirty at once.
+// allocation (inlined together they spill at the 128-VGPR bound).
 template <int DT, int G, bool AL>
 __device__ __attribute__((noinline)) void bat_rows(const BatProblem& p, int64_t s, int64_t r0, int64_t r1, int64_t k0,
                                          int64_t klen, const unsigned char* xs_raw)
@@ -132,38 +166,50 @@ __global__ __launch_bounds__(kBatNT, 4) void gemv_batched_kernel(const unsigned 
     __shared__ int last_flag;
     const BatHeader* hdr = reinterpret_cast<const BatHeader*>(table);
     const BatProblem* probs = reinterpret_cast<const BatProblem*>(table + sizeof(BatHeader));
-    const int64_t count = hdr->count, ntiles = hdr->ntiles;
+    const int64_t count = hdr->count, ntiles = hdr->ntiles, total = hdr->total_cost;
     int64_t cached_p = -1, cached_s = -1;
-    // Workgroup b takes the contiguous tile range [b*T/grid, (b+1)*T/grid),
-    // so consecutive tiles of one problem reuse the staged x chunk.
-    const int64_t t_begin = (int64_t)blockIdx.x * ntiles / gridDim.x;
-    const int64_t t_end = ((int64_t)blockIdx.x + 1) * ntiles / gridDim.x;
+    // Workgroup b takes the tiles whose start cost lies in
+    // [b*C/grid, (b+1)*C/grid): contiguous tile ranges of equal bytes, so
+    // consecutive tiles of one problem also reuse the staged x chunk.
+    const int64_t t_begin = first_tile_at_cost(probs, count, ntiles, total, (int64_t)blockIdx.x * total / gridDim.x);
+    const int64_t t_end = first_tile_at_cost(probs, count, ntiles, total,
+                                             ((int64_t)blockIdx.x + 1) * total / gridDim.x);
 
-    for (int64_t t = t_begin; t < t_end; ++t) {
-        // The problem owning tile t: the last record with tile0 <= t.
+    if (t_begin >= t_end) return;
+    // One search for the problem owning the first tile; later tiles of the
+    // contiguous range advance through the records in order.
+    int64_t pi = 0;
+    {
         int64_t lo = 0, hi = count - 1;
         while (lo < hi) {
             const int64_t mid = (lo + hi + 1) >> 1;
-            if (probs[mid].tile0 <= t) lo = mid;
+            if (probs[mid].tile0 <= t_begin) lo = mid;
             else hi = mid - 1;
         }
-        const BatProblem p = probs[lo];
+        pi = lo;
+    }
+    BatProblem p = probs[pi];
+    for (int64_t t = t_begin; t < t_end; ++t) {
+        while (t >= p.tile0 + p.rtiles * p.S) p = probs[++pi];  // skips problems without tiles
         const int64_t local = t - p.tile0;
         const int64_t s = local % p.S, rt = local / p.S;
         const int64_t r0 = rt * p.RT, r1 = min(p.m, r0 + p.RT);
         const int64_t k0 = s * p.KC, klen = min(p.n, k0 + p.KC) - k0;
 
-        if (lo != cached_p || s != cached_s) {
+        if (pi != cached_p || s != cached_s) {
             __syncthreads();  // every row of the previous tile has read x
-            if (p.dtype == SB_F64) {
-                const double* xg = static_cast<const double*>(p.x) + k0;
-                for (int64_t e = threadIdx.x; e < klen; e += kBatNT) reinterpret_cast<double*>(xs)[e] = xg[e];
+            const int xs_size = p.dtype == SB_F64 ? 8 : 4;
+            const unsigned char* xg = static_cast<const unsigned char*>(p.x) + k0 * xs_size;
+            const int64_t nbytes = klen * xs_size;
+            if (((reinterpret_cast<uintptr_t>(xg) | (uintptr_t)nbytes) & 15) == 0) {
+                for (int64_t e = threadIdx.x; e < nbytes / 16; e += kBatNT)
+                    reinterpret_cast<v4u*>(xs)[e] = reinterpret_cast<const v4u*>(xg)[e];
             } else {
-                const float* xg = static_cast<const float*>(p.x) + k0;
-                for (int64_t e = threadIdx.x; e < klen; e += kBatNT) reinterpret_cast<float*>(xs)[e] = xg[e];
+                for (int64_t e = threadIdx.x; e < nbytes / 4; e += kBatNT)
+                    reinterpret_cast<uint32_t*>(xs)[e] = reinterpret_cast<const uint32_t*>(xg)[e];
             }
             __syncthreads();
-            cached_p = lo;
+            cached_p = pi;
             cached_s = s;
         }
 
@@ -210,7 +256,8 @@ static int esize(int32_t dt) { return dt == SB_F64 ? 8 : dt == SB_F32 ? 4 : dt =
 static int xsize(int32_t dt) { return dt == SB_F64 ? 8 : 4; }
 
 // Fill the automatic fields of one descriptor; false if it cannot be run.
-static bool resolve(const sb_gemv_desc& in, sb_gemv_desc& out, int64_t* KC, char* why, size_t whylen)
+static bool resolve(const sb_gemv_desc& in, sb_gemv_desc& out, int64_t* KC, int64_t tile_bytes, char* why,
+                    size_t whylen)
 {
     out = in;
     const int es = esize(in.dtype), xs = xsize(in.dtype);
@@ -242,7 +289,7 @@ static bool resolve(const sb_gemv_desc& in, sb_gemv_desc& out, int64_t* KC, char
     int64_t RT = in.rows_per_tile;
     if (RT == 0) {
         const int64_t row_bytes = std::max<int64_t>(1, std::min<int64_t>(kc, in.n)) * es;
-        RT = std::max<int64_t>(pass, (kBatTileBytes / row_bytes) / pass * pass);
+        RT = std::max<int64_t>(pass, (tile_bytes / row_bytes) / pass * pass);
         RT = std::min<int64_t>(RT, round_up(std::max<int64_t>(in.m, 1), pass));
     } else if (RT % pass) {
         snprintf(why, whylen, "rows_per_tile %lld is not a multiple of %lld", (long long)RT, (long long)pass);
@@ -276,6 +323,10 @@ static sb_status layout(const sb_gemv_desc* d, int32_t count, BatLayout& L, char
     L.counter_off.resize(count);
     L.partial_off.resize(count);
     size_t off = sizeof(BatHeader) + (size_t)count * sizeof(BatProblem);
+    // Automatic tile height: about 256 KiB of A per tile (measured better
+    // than smaller, better balanced tiles: the per-tile set-up costs more than
+    // the imbalance).  The rows of a tile never change a row's arithmetic.
+    const int64_t tile_bytes = kBatTileBytes;
     for (int32_t i = 0; i < count; ++i) {
         const sb_gemv_desc& in = d[i];
         if (in.dtype < SB_F64 || in.dtype > SB_FP8_E4M3 || in.m < 0 || in.n < 0 || in.lda < std::max<int64_t>(1, in.n)) {
@@ -297,7 +348,7 @@ static sb_status layout(const sb_gemv_desc* d, int32_t count, BatLayout& L, char
             return SB_EINVAL;
         }
         char sub[160];
-        if (!resolve(in, L.res[i], &L.kc[i], sub, sizeof sub)) {
+        if (!resolve(in, L.res[i], &L.kc[i], tile_bytes, sub, sizeof sub)) {
             snprintf(why, whylen, "descriptor %d: %s", i, sub);
             return SB_EINVAL;
         }
@@ -347,7 +398,7 @@ static void encode(const sb_gemv_desc* d, int32_t count, const BatLayout& L, uns
     hdr->count = count;
     hdr->ntiles = L.ntiles;
     BatProblem* P = reinterpret_cast<BatProblem*>(image + sizeof(BatHeader));
-    int64_t tile0 = 0;
+    int64_t tile0 = 0, cost = 0;
     for (int32_t i = 0; i < count; ++i) {
         const sb_gemv_desc& r = L.res[i];
         BatProblem& p = P[i];
@@ -361,6 +412,11 @@ static void encode(const sb_gemv_desc* d, int32_t count, const BatLayout& L, uns
         p.KC = L.kc[i];
         p.tile0 = tile0;
         p.rtiles = L.rtiles[i];
+        // tile cost: its bytes of A plus a fixed 4 KiB for staging and set-up
+        const int64_t a_bytes = (int64_t)r.rows_per_tile * std::min<int64_t>(L.kc[i], d[i].n) * esize(r.dtype);
+        p.tile_cost = L.tiles[i] > 0 ? (a_bytes + 4096 + 1023) / 1024 : 0;
+        p.cost0 = cost;
+        cost += p.tile_cost * L.tiles[i];
         p.A = d[i].A;
         p.scales = d[i].scales;
         p.x = d[i].x;
@@ -371,6 +427,7 @@ static void encode(const sb_gemv_desc* d, int32_t count, const BatLayout& L, uns
         p.aligned = (r.dtype == SB_F64 || r.dtype == SB_F32) && aligned16(d[i].A) && (d[i].lda * es) % 16 == 0;
         tile0 += L.tiles[i];
     }
+    hdr->total_cost = cost;
 }
 
 }  // namespace sb

@@ -11,8 +11,13 @@
 // path; any element can be regenerated on its own from (seed, counter).
 #include <algorithm>
 
+#include <string.h>
+
+#include <vector>
+
 #include "sb_device.hpp"
 #include "sb_internal.hpp"
+#include "sb_quant.hpp"
 
 namespace sb {
 
@@ -47,4 +52,141 @@ sb_status run_fill_uniform(sb_handle* h, sb_dtype dt, void* out, int64_t count, 
     return check_launch(h, "fill_uniform_kernel");
 }
 
+// ---- batched materialisation of GEMV requests -----------------------------
+//
+// One launch makes the operands of many requests: every row of every A is a
+// work item (binary32 rows are generated in place; bfloat16 rows are
+// generated twice, once for the row's amax and once for the codes, exactly
+// as sb_fill_uniform followed by sb_quantize_rows would produce them), plus
+// one item per request for x (counters m*n ... m*n + n - 1) and the zeroed c.
+
+struct GenHeader {
+    int64_t count, nitems, pad[6];
+};
+struct GenRec {
+    int32_t dtype, pad;
+    int64_t m, n, lda;
+    uint64_t seed;
+    void* A;
+    float* scales;
+    float* x;
+    float* c;
+    int64_t item0;
+};
+static_assert(sizeof(GenHeader) == 64 && sizeof(GenRec) == 80, "generator table layout");
+
+__global__ __launch_bounds__(256) void generate_kernel(const unsigned char* table)
+{
+    __shared__ float red[4];
+    __shared__ float s_sh;
+    const GenHeader* hdr = reinterpret_cast<const GenHeader*>(table);
+    const GenRec* recs = reinterpret_cast<const GenRec*>(table + sizeof(GenHeader));
+    const int64_t count = hdr->count, nitems = hdr->nitems;
+    for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+        int64_t lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (recs[mid].item0 <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const GenRec r = recs[lo];
+        const int64_t row = item - r.item0;
+        // bfloat16 rows exist even when n = 0: their scale is 1, as the
+        // quantiser gives a row whose largest magnitude is 0
+        if (row < ((r.n > 0 || r.dtype == SB_BF16) ? r.m : 0)) {
+            const uint64_t c0 = (uint64_t)(row * r.n);
+            if (r.dtype == SB_F32) {
+                float* Ar = static_cast<float*>(r.A) + row * r.lda;
+                for (int64_t j = threadIdx.x; j < r.n; j += 256) Ar[j] = (float)splitmix_uniform(r.seed, c0 + j);
+            } else {
+                float amax = 0.0f;
+                for (int64_t j = threadIdx.x; j < r.n; j += 256) {
+                    const float v = fabsf((float)splitmix_uniform(r.seed, c0 + j));
+                    if (v == v && v > amax) amax = v;
+                }
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
+                if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = amax;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    s_sh = row_scale(true, fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+                    r.scales[row] = s_sh;
+                }
+                __syncthreads();
+                const float s = s_sh;
+                uint16_t* Qr = static_cast<uint16_t*>(r.A) + row * r.lda;
+                for (int64_t j = threadIdx.x; j < r.n; j += 256)
+                    Qr[j] = bf16_encode((float)splitmix_uniform(r.seed, c0 + j) / s);
+                __syncthreads();  // s_sh and red are reused by the next item
+            }
+        } else {
+            const uint64_t c0 = (uint64_t)(r.m * r.n);
+            for (int64_t j = threadIdx.x; j < r.n; j += 256) r.x[j] = (float)splitmix_uniform(r.seed, c0 + j);
+            for (int64_t i = threadIdx.x; i < r.m; i += 256) r.c[i] = 0.0f;
+        }
+    }
+}
+
 }  // namespace sb
+
+using sb::fail;
+
+extern "C" {
+
+size_t sb_generate_batched_bytes(int32_t count)
+{
+    return count < 0 ? (size_t)-1 : sizeof(sb::GenHeader) + (size_t)count * sizeof(sb::GenRec);
+}
+
+sb_status sb_generate_batched(sb_handle* handle, const sb_gen_desc* descs, int32_t count)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_generate_batched: NULL handle");
+    if (count < 0 || (count > 0 && !descs)) return fail(handle, SB_EINVAL, "sb_generate_batched: bad descriptors");
+    try {
+        std::vector<unsigned char> image(sb_generate_batched_bytes(count));
+        memset(image.data(), 0, image.size());
+        auto* hdr = reinterpret_cast<sb::GenHeader*>(image.data());
+        auto* recs = reinterpret_cast<sb::GenRec*>(image.data() + sizeof(sb::GenHeader));
+        int64_t items = 0;
+        for (int32_t k = 0; k < count; ++k) {
+            const sb_gen_desc& d = descs[k];
+            if ((d.dtype != SB_F32 && d.dtype != SB_BF16) || d.m < 0 || d.n < 0 || d.lda < (d.n > 1 ? d.n : 1) ||
+                d.m > ((int64_t)1 << 31) || d.n > ((int64_t)1 << 31))
+                return fail(handle, SB_EINVAL, "sb_generate_batched: descriptor %d: bad dtype, size or lda", k);
+            const int es = d.dtype == SB_F32 ? 4 : 2;
+            if ((d.m > 0 && d.n > 0 && !d.A) || (d.m > 0 && d.dtype == SB_BF16 && !d.scales) || (d.n > 0 && !d.x) ||
+                (d.m > 0 && !d.c) || (uintptr_t)d.A % es || (uintptr_t)d.x % 4 || (uintptr_t)d.c % 4 ||
+                (uintptr_t)d.scales % 4)
+                return fail(handle, SB_EINVAL, "sb_generate_batched: descriptor %d: NULL or misaligned pointer", k);
+            sb::GenRec& r = recs[k];
+            r.dtype = d.dtype;
+            r.m = d.m;
+            r.n = d.n;
+            r.lda = d.lda;
+            r.seed = d.seed;
+            r.A = d.A;
+            r.scales = d.scales;
+            r.x = d.x;
+            r.c = d.c;
+            r.item0 = items;
+            items += ((d.n > 0 || d.dtype == SB_BF16) ? d.m : 0) + 1;  // the rows of A, then x and c
+            (void)es;
+        }
+        hdr->count = count;
+        hdr->nitems = items;
+        if (items == 0) return SB_OK;
+        if (image.size() > handle->ws_bytes || !sb::aligned16(handle->ws))
+            return fail(handle, SB_ENOMEM, "sb_generate_batched needs %zu workspace bytes, handle has %zu",
+                        image.size(), handle->ws_bytes);
+        const hipError_t e = hipMemcpyAsync(handle->ws, image.data(), image.size(), hipMemcpyHostToDevice, handle->stream);
+        if (e != hipSuccess) return fail(handle, SB_EDEVICE, "sb_generate_batched: copy: %s", hipGetErrorString(e));
+        const int64_t grid = std::min<int64_t>(items, 4096);
+        hipLaunchKernelGGL(sb::generate_kernel, dim3((unsigned)grid), dim3(256), 0, handle->stream,
+                           static_cast<const unsigned char*>(handle->ws));
+        return sb::check_launch(handle, "generate_kernel");
+    } catch (...) {
+        return fail(handle, SB_EINTERNAL, "sb_generate_batched: unexpected C++ exception");
+    }
+}
+
+}  // extern "C"

@@ -31,6 +31,7 @@ arrival).
 from __future__ import annotations
 
 import collections
+import ctypes
 import dataclasses
 import math
 import time
@@ -192,6 +193,14 @@ class Stats:
         return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in dataclasses.asdict(self).items()}
 
 
+GEMV_DESC = np.dtype([("dtype", "<i4"), ("group", "<i4"), ("rows_per_tile", "<i4"), ("split", "<i4"),
+                      ("m", "<i8"), ("n", "<i8"), ("lda", "<i8"),
+                      ("A", "<u8"), ("scales", "<u8"), ("x", "<u8"), ("c", "<u8")])
+GEN_DESC = np.dtype([("dtype", "<i4"), ("reserved", "<i4"), ("m", "<i8"), ("n", "<i8"), ("lda", "<i8"),
+                     ("seed", "<u8"), ("A", "<u8"), ("scales", "<u8"), ("x", "<u8"), ("c", "<u8")])
+assert GEMV_DESC.itemsize == 72 and GEN_DESC.itemsize == 72
+
+
 class Server:
     """See the module docstring.  `tuning` maps (kind, m, n) to a
     configuration dict for the batched kernel (or None for automatic)."""
@@ -199,10 +208,12 @@ class Server:
     def __init__(self, budget_bytes: int = 4 << 30, max_batch: int = 512, max_inflight: int = 2,
                  use_graphs: bool = True, tuning=None, sample_every: int = 16, table_bytes: int = 96 << 20,
                  device=None):
+        from . import Handle
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
         self.budget = int(budget_bytes)
         self.buf = torch.empty(self.budget, dtype=torch.uint8, device=self.device)
+        self.base = self.buf.data_ptr()
         self.stage = torch.empty(8192 * 8192, dtype=torch.float32, device=self.device)
         self.max_batch = max_batch
         self.max_inflight = max_inflight
@@ -211,6 +222,7 @@ class Server:
         self.sample_every = sample_every
         self.exec_stream = torch.cuda.Stream(device=self.device)
         self.gen_stream = torch.cuda.Stream(device=self.device)
+        self.gen_handle = Handle(self.device.index)
         self.tables = [BatchTable(table_bytes, self.device) for _ in range(max_inflight)]
         self.graphs: list[torch.cuda.CUDAGraph | None] = [None] * max_inflight
 
@@ -227,13 +239,12 @@ class Server:
     def _config(self, r: Request):
         return self.tuning(r.kind, r.m, r.n) if self.tuning else None
 
-    def warm_up(self, trace: list[Request]) -> None:
+    def warm_up(self) -> None:
         """Capture the graphs with a tiny batch so capture is off the clock."""
         if not self.use_graphs:
             return
-        r = Request(-1, 0.0, "f32", 64, 64, 12345)
         with torch.cuda.stream(self.exec_stream):
-            P = materialise(self.buf, 0, r.kind, r.m, r.n, r.seed, self.stage)
+            P = materialise(self.buf, 0, "f32", 64, 64, 12345, self.stage)
             for k in range(len(self.tables)):
                 self.tables[k].encode([P])
                 self.tables[k].run()  # eager launch before capture
@@ -242,17 +253,42 @@ class Server:
                 self._graph_for(k)
         torch.cuda.synchronize()
 
+    def _generate(self, gen: np.ndarray) -> None:
+        from . import load
+        L = load()
+        h = self.gen_handle
+        h.prepare(int(L.sb_generate_batched_bytes(len(gen))))
+        h.check(L.sb_generate_batched(h.h, ctypes.c_void_p(gen.ctypes.data), len(gen)))
+
     def run(self, trace: list[Request]) -> Stats:
-        n_req = len(trace)
+        N = len(trace)
+        arrival = np.array([r.arrival for r in trace])
+        m = np.array([r.m for r in trace], dtype=np.int64)
+        n = np.array([r.n for r in trace], dtype=np.int64)
+        bf16 = np.array([r.kind == "bf16" for r in trace])
+        seed = np.array([r.seed for r in trace], dtype=np.uint64)
+        es = np.where(bf16, 2, 4)
+        a_bytes = (es * m * n + ALIGN - 1) // ALIGN * ALIGN
+        s_bytes = np.where(bf16, (4 * m + ALIGN - 1) // ALIGN * ALIGN, 0)
+        x_bytes = (4 * n + ALIGN - 1) // ALIGN * ALIGN
+        dev_bytes = a_bytes + s_bytes + x_bytes + (4 * m + ALIGN - 1) // ALIGN * ALIGN
+        cfg = np.zeros((N, 3), dtype=np.int32)
+        if self.tuning:
+            for i, r in enumerate(trace):
+                c = self.tuning(r.kind, r.m, r.n) or {}
+                cfg[i] = (c.get("group", 0), c.get("rows_per_tile", 0), c.get("split", 0))
+        offset = np.full(N, -1, dtype=np.int64)
+        t_admit = np.full(N, np.nan)
+        t_launch = np.full(N, np.nan)
+        t_done = np.full(N, np.nan)
+        sampled = np.flatnonzero(np.arange(N) % self.sample_every == 0)
+        result_at = np.full(N, -1, dtype=np.int64)
+        result_at[sampled] = np.concatenate([[0], np.cumsum(m[sampled])[:-1]]) if len(sampled) else []
+        self.results = torch.empty(max(1, int(m[sampled].sum())), dtype=torch.float32, device=self.device)
+
         pool = Pool(self.budget)
-        sampled = [r for r in trace if r.id % self.sample_every == 0]
-        self.results = torch.empty(max(1, sum(r.m for r in sampled)), dtype=torch.float32, device=self.device)
-        pos = 0
-        for r in sampled:
-            r.result_at = pos
-            pos += r.m
-        queue: collections.deque[Request] = collections.deque()
-        ready: list[Request] = []
+        queue: collections.deque[int] = collections.deque()
+        ready: list[int] = []
         inflight: collections.deque = collections.deque()
         free_tables = collections.deque(range(len(self.tables)))
         gen_event = None
@@ -260,71 +296,93 @@ class Server:
         nxt = 0
         batch_id = 0
         busy_events = []
-        self.warm_up(trace)
+        self.warm_up()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        while done + rejected < n_req:
+        while done + rejected < N:
             now = time.perf_counter() - t0
-            while nxt < n_req and trace[nxt].arrival <= now:
-                queue.append(trace[nxt])
-                nxt += 1
+            upto = int(np.searchsorted(arrival, now, side="right"))
+            if upto > nxt:
+                queue.extend(range(nxt, upto))
+                nxt = upto
             # admission: FIFO, by device memory
+            admitted = []
             while queue:
-                r = queue[0]
-                if r.device_bytes > self.budget:
+                i = queue[0]
+                if dev_bytes[i] > self.budget:
                     queue.popleft()
                     rejected += 1
-                    r.t_done = math.inf
+                    t_done[i] = np.inf
                     continue
-                off = pool.alloc(r.device_bytes)
+                off = pool.alloc(int(dev_bytes[i]))
                 if off is None:
                     break
                 queue.popleft()
-                r.offset = off
-                r.t_admit = time.perf_counter() - t0
+                offset[i] = off
+                admitted.append(i)
+            if admitted:
+                ids = np.array(admitted)
+                t_admit[ids] = time.perf_counter() - t0
+                base = self.base + offset[ids]
+                gen = np.zeros(len(ids), dtype=GEN_DESC)
+                gen["dtype"] = np.where(bf16[ids], 2, 1)
+                gen["m"], gen["n"], gen["lda"], gen["seed"] = m[ids], n[ids], n[ids], seed[ids]
+                gen["A"] = base
+                gen["scales"] = np.where(bf16[ids], base + a_bytes[ids], 0)
+                gen["x"] = base + a_bytes[ids] + s_bytes[ids]
+                gen["c"] = base + a_bytes[ids] + s_bytes[ids] + x_bytes[ids]
                 with torch.cuda.stream(self.gen_stream):
-                    r.problem = materialise(self.buf, off, r.kind, r.m, r.n, r.seed, self.stage, self._config(r))
+                    self._generate(gen)
                     gen_event = torch.cuda.Event()
                     gen_event.record()
-                ready.append(r)
+                ready.extend(admitted)
             # continuous batching: launch whatever is ready when a table is free
             if ready and free_tables:
                 k = free_tables.popleft()
-                batch, ready = ready[: self.max_batch], ready[self.max_batch:]
+                ids = np.array(ready[: self.max_batch])
+                ready = ready[self.max_batch:]
+                base = self.base + offset[ids]
+                d = np.zeros(len(ids), dtype=GEMV_DESC)
+                d["dtype"] = np.where(bf16[ids], 2, 1)
+                d["group"], d["rows_per_tile"], d["split"] = cfg[ids, 0], cfg[ids, 1], cfg[ids, 2]
+                d["m"], d["n"], d["lda"] = m[ids], n[ids], n[ids]
+                d["A"] = base
+                d["scales"] = np.where(bf16[ids], base + a_bytes[ids], 0)
+                d["x"] = base + a_bytes[ids] + s_bytes[ids]
+                d["c"] = base + a_bytes[ids] + s_bytes[ids] + x_bytes[ids]
                 with torch.cuda.stream(self.exec_stream):
                     self.exec_stream.wait_event(gen_event)
                     start = torch.cuda.Event(enable_timing=True)
                     end = torch.cuda.Event(enable_timing=True)
-                    self.tables[k].encode([r.problem for r in batch])
+                    self.tables[k].encode_descs(d.ctypes.data, len(ids))
                     start.record()
                     if self.use_graphs:
                         self._graph_for(k).replay()
                     else:
                         self.tables[k].run()
                     end.record()
-                    for r in batch:
-                        if r.result_at >= 0:
-                            self.results[r.result_at:r.result_at + r.m].copy_(r.problem.c)
+                    for i in ids[result_at[ids] >= 0]:
+                        c_off = int(offset[i] + a_bytes[i] + s_bytes[i] + x_bytes[i])
+                        self.results[result_at[i]:result_at[i] + m[i]].copy_(
+                            self.buf[c_off:c_off + 4 * int(m[i])].view(torch.float32))
                     fin = torch.cuda.Event()
                     fin.record()
-                t = time.perf_counter() - t0
-                for r in batch:
-                    r.t_launch = t
-                    r.batch = batch_id
-                inflight.append((fin, batch, k, start, end))
+                t_launch[ids] = time.perf_counter() - t0
+                inflight.append((fin, ids, k))
                 busy_events.append((start, end))
                 batch_id += 1
             # completions
             while inflight and inflight[0][0].query():
-                fin, batch, k, _, _ = inflight.popleft()
-                t = time.perf_counter() - t0
-                for r in batch:
-                    r.t_done = t
-                    pool.free(r.offset, r.device_bytes)
-                    r.problem = None
-                done += len(batch)
+                fin, ids, k = inflight.popleft()
+                t_done[ids] = time.perf_counter() - t0
+                for i in ids:
+                    pool.free(int(offset[i]), int(dev_bytes[i]))
+                done += len(ids)
                 free_tables.append(k)
         torch.cuda.synchronize()
+        for i, r in enumerate(trace):
+            r.t_admit, r.t_launch, r.t_done = float(t_admit[i]), float(t_launch[i]), float(t_done[i])
+            r.offset, r.result_at = int(offset[i]), int(result_at[i])
         return self._stats(trace, busy_events, batch_id, rejected)
 
     def _stats(self, trace, busy_events, nbatches, rejected) -> Stats:
@@ -348,8 +406,9 @@ class Server:
         return self.results[r.result_at:r.result_at + r.m]
 
     def rerun_alone(self, r: Request) -> torch.Tensor:
-        """Regenerate one request's operands and run it alone (same
-        configuration); returns its output."""
+        """Regenerate one request's operands with the separate fill and
+        quantise calls and run it alone (same configuration); returns its
+        output."""
         buf = torch.empty(r.device_bytes, dtype=torch.uint8, device=self.device)
         P = materialise(buf, 0, r.kind, r.m, r.n, r.seed, self.stage, self._config(r))
         sb_gemv_batched([P])

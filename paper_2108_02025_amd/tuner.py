@@ -1,0 +1,177 @@
+"""Autotuner for the batched GEMV kernel.
+
+For every bucket (kind, round(log2 m), round(log2 n)) with kind binary32 or
+bfloat16-A and m, n in [64, 8192], the tuner builds a batch of identical
+problems of the bucket's shape (operands generated on the device), times
+each candidate configuration
+
+    group          lanes per row (rows per wave = 64 / group): the powers of
+                   two 4..64 that leave each lane at least one 16-byte load
+    split          column chunks (tile width n / split; split-K): 1, plus 2
+                   and 4 for short, wide shapes
+
+(the tile height stays automatic: it is sized from the whole batch, which
+the tuner cannot know, and never changes a row's arithmetic)
+with HIP events (median of several launches over the same table) and keeps
+the fastest.  The table is saved as JSON keyed by GPU architecture and
+library version; `TuningTable` maps any (kind, m, n) to its bucket's
+configuration.  A problem's configuration depends only on its own shape, so
+tuning never breaks the alone-vs-mix equality of results.
+
+    python -m paper_2108_02025_amd.tuner [--out FILE] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+
+import numpy as np
+import torch
+
+from . import SB_BF16, BatchTable, GemvProblem, sb_gemv_batched_table_bytes, sb_version
+from .serve import GEN_DESC, device_bytes
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_TABLE = os.path.join(HERE, "tuning_gfx950.json")
+LOG2 = range(6, 14)  # 64 .. 8192
+
+
+def bucket(kind: str, m: int, n: int) -> str:
+    lm = min(max(int(round(math.log2(max(m, 1)))), LOG2[0]), LOG2[-1])
+    ln = min(max(int(round(math.log2(max(n, 1)))), LOG2[0]), LOG2[-1])
+    return f"{kind}/{lm}/{ln}"
+
+
+def candidates(kind: str, m: int, n: int) -> list[dict]:
+    per16 = 4 if kind == "f32" else 8          # elements per 16-byte load
+    out = []
+    for g in (4, 8, 16, 32, 64):
+        if g > 4 and (n + per16 - 1) // per16 < g:
+            continue
+        splits = [1]
+        if n >= 2048 and m <= 1024:
+            splits += [2, 4]
+        for sp in splits:
+            out.append({"group": g, "rows_per_tile": 0, "split": sp})
+    return out
+
+
+def _make_batch(kind: str, m: int, n: int, count: int, device):
+    """`count` problems of one shape with operands made on the device."""
+    from . import Handle, load
+    per = device_bytes(kind, m, n)
+    buf = torch.empty(per * count, dtype=torch.uint8, device=device)
+    base = buf.data_ptr()
+    es = 4 if kind == "f32" else 2
+    up = lambda v: (v + 255) // 256 * 256  # noqa: E731
+    a, s_, x = up(es * m * n), up(4 * m) if kind == "bf16" else 0, up(4 * n)
+    gen = np.zeros(count, dtype=GEN_DESC)
+    offs = base + per * np.arange(count, dtype=np.uint64)
+    gen["dtype"] = 2 if kind == "bf16" else 1
+    gen["m"], gen["n"], gen["lda"], gen["seed"] = m, n, n, 777 + np.arange(count)
+    gen["A"], gen["x"], gen["c"] = offs, offs + a + s_, offs + a + s_ + x
+    gen["scales"] = offs + a if kind == "bf16" else 0
+    L = load()
+    h = Handle(device.index)
+    h.prepare(int(L.sb_generate_batched_bytes(count)))
+    import ctypes
+    h.check(L.sb_generate_batched(h.h, ctypes.c_void_p(gen.ctypes.data), count))
+    views = []
+    for k in range(count):
+        o = per * k
+        A = buf[o:o + es * m * n].view(torch.float32 if kind == "f32" else torch.int16).view(m, n)
+        sc = buf[o + a:o + a + 4 * m].view(torch.float32) if kind == "bf16" else None
+        xv = buf[o + a + s_:o + a + s_ + 4 * n].view(torch.float32)
+        cv = buf[o + a + s_ + x:o + a + s_ + x + 4 * m].view(torch.float32)
+        views.append((A, sc, xv, cv))
+    return buf, views
+
+
+def time_config(kind, m, n, cfg, views, table: BatchTable, reps=7) -> float:
+    probs = [GemvProblem(A, xv, cv, scales=sc, q=SB_BF16 if kind == "bf16" else None, **cfg)
+             for A, sc, xv, cv in views]
+    if sb_gemv_batched_table_bytes(probs)[0] > table.capacity:
+        return math.inf
+    table.encode(probs)
+    table.run()
+    evs = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        table.run()
+        b.record()
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    return sorted(x.elapsed_time(y) for x, y in evs)[reps // 2] * 1e3
+
+
+def tune(kinds=("f32", "bf16"), buckets=None, batch_bytes=96 << 20, max_count=64, log=print) -> dict:
+    dev = torch.device("cuda", torch.cuda.current_device())
+    bt = BatchTable(64 << 20, dev)
+    table = {}
+    for kind in kinds:
+        for lm in LOG2:
+            for ln in LOG2:
+                key = f"{kind}/{lm}/{ln}"
+                if buckets and key not in buckets:
+                    continue
+                m, n = 1 << lm, 1 << ln
+                count = max(1, min(max_count, batch_bytes // device_bytes(kind, m, n)))
+                buf, views = _make_batch(kind, m, n, count, dev)
+                best = None
+                for cfg in candidates(kind, m, n):
+                    us = time_config(kind, m, n, cfg, views, bt)
+                    if best is None or us < best[0]:
+                        best = (us, cfg)
+                auto_us = time_config(kind, m, n, {"group": 0, "rows_per_tile": 0, "split": 0}, views, bt)
+                es = 4 if kind == "f32" else 2
+                gbs = count * (es * m * n) / best[0] / 1e3
+                table[key] = {**best[1], "us": round(best[0], 2), "auto_us": round(auto_us, 2),
+                              "GBs": round(gbs, 1), "count": int(count)}
+                log(f"{key}: {best[1]} {best[0]:.1f} us (automatic {auto_us:.1f} us), {gbs:.0f} GB/s")
+                del buf, views
+    return {"arch": "gfx950", "library_version": sb_version(), "buckets": table}
+
+
+class TuningTable:
+    """Callable (kind, m, n) -> configuration dict, from a saved table."""
+
+    def __init__(self, data: dict):
+        self.buckets = data["buckets"]
+
+    @classmethod
+    def load(cls, path: str = DEFAULT_TABLE) -> "TuningTable | None":
+        if not os.path.exists(path):
+            return None
+        with open(path) as f:
+            data = json.load(f)
+        if data.get("arch") != "gfx950" or data.get("library_version") != sb_version():
+            return None
+        return cls(data)
+
+    def __call__(self, kind: str, m: int, n: int) -> dict | None:
+        e = self.buckets.get(bucket(kind, m, n))
+        if e is None:
+            return None
+        return {"group": e["group"], "rows_per_tile": e["rows_per_tile"], "split": e["split"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_TABLE)
+    ap.add_argument("--quick", action="store_true", help="tune a few buckets only")
+    args = ap.parse_args()
+    buckets = None
+    if args.quick:
+        buckets = {"f32/13/13", "bf16/13/13", "f32/6/13", "bf16/13/6", "f32/10/10"}
+    data = tune(buckets=buckets)
+    with open(args.out, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    print(f"wrote {args.out} ({len(data['buckets'])} buckets)")
+
+
+if __name__ == "__main__":
+    main()

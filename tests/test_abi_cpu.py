@@ -146,20 +146,22 @@ def test_batched_resolve_encode_on_host(L):
         assert out[k].group in (4, 8, 16, 32, 64) and out[k].rows_per_tile % (4 * 64 // out[k].group) == 0
     img = ctypes.c_size_t(0)
     total = L.sb_gemv_batched_table_bytes(arr, 3, ctypes.byref(img))
-    assert total >= img.value > 64 + 3 * 128
+    assert total >= img.value > 64 + 3 * 144
     buf = (ctypes.c_ubyte * img.value)()
     dev_table = 1 << 44
     assert L.sb_gemv_batched_encode(arr, 3, ctypes.c_void_p(dev_table), buf, img.value) == 0
-    count, ntiles = struct.unpack_from("<qq", buf, 0)
-    tiles = []
+    count, ntiles, total_cost = struct.unpack_from("<qqq", buf, 0)
+    tiles, cost = [], 0
     for k in range(3):
-        rec = 64 + 128 * k
+        rec = 64 + 144 * k
         dtype, G, RT, S = struct.unpack_from("<iiii", buf, rec)
-        m, n, lda, KC, tile0, rtiles = struct.unpack_from("<qqqqqq", buf, rec + 16)
+        m, n, lda, KC, tile0, rtiles, cost0, tile_cost = struct.unpack_from("<qqqqqqqq", buf, rec + 16)
         assert (dtype, G, RT, S) == (arr[k].dtype, out[k].group, out[k].rows_per_tile, out[k].split)
         assert KC % 16 == 0 and KC * S >= n and rtiles == -(-m // RT)
+        assert cost0 == cost and tile_cost >= 4       # every tile carries the 4 KiB set-up cost
+        cost += tile_cost * rtiles * S
         tiles.append((tile0, rtiles * S))
-    assert count == 3 and tiles[0][0] == 0
+    assert count == 3 and tiles[0][0] == 0 and total_cost == cost
     assert tiles[1][0] == tiles[0][1] and tiles[2][0] == tiles[1][0] + tiles[1][1]
     assert ntiles == sum(t for _, t in tiles)
 
@@ -181,4 +183,4 @@ def test_batched_validation(L):
     assert L.sb_gemv_batched_resolve(two, 2, (sb.sb_gemv_desc * 2)()) == -1  # outputs overlap
     assert b"overlap" in L.sb_last_error(None)
     empty = (sb.sb_gemv_desc * 1)(_desc(sb, 1, 0, 10, 0, 0, x=0))
-    assert L.sb_gemv_batched_table_bytes(empty, 1, None) == 64 + 128
+    assert L.sb_gemv_batched_table_bytes(empty, 1, None) == 256  # 64 + 144, rounded up to 64

@@ -90,3 +90,53 @@ def test_serve_graphs_off_same_bits(sb):
         server.run(trace)
         outs.append(host(server.results).copy())
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_generate_batched_matches_fill_and_quantise(sb):
+    """One sb_generate_batched launch makes the same operands, bit for bit,
+    as sb_fill_uniform followed by sb_quantize_rows."""
+    import ctypes
+
+    from paper_2108_02025_amd.serve import GEN_DESC, Request, device_bytes, materialise
+    shapes = [("f32", 5, 7), ("bf16", 64, 8192), ("bf16", 300, 1000), ("f32", 1000, 300), ("bf16", 3, 0),
+              ("f32", 0, 5), ("bf16", 1, 1)]
+    stage = torch.empty(8192 * 8192, dtype=torch.float32, device="cuda")
+    gen = np.zeros(len(shapes), dtype=GEN_DESC)
+    bufs, refs = [], []
+    for k, (kind, m, n) in enumerate(shapes):
+        r = Request(k, 0.0, kind, m, n, 1000 + k)
+        b = torch.full((device_bytes(kind, m, n),), 0x5A, dtype=torch.uint8, device="cuda")
+        ref = torch.full_like(b, 0x5A)
+        materialise(ref, 0, kind, m, n, r.seed, stage)
+        es = 4 if kind == "f32" else 2
+        up = lambda v: (v + 255) // 256 * 256  # noqa: E731
+        a, s_, x = up(es * m * n), up(4 * m) if kind == "bf16" else 0, up(4 * n)
+        base = b.data_ptr()
+        gen[k] = (2 if kind == "bf16" else 1, 0, m, n, max(n, 1), r.seed, base,
+                  base + a if kind == "bf16" else 0, base + a + s_, base + a + s_ + x)
+        bufs.append(b)
+        refs.append(ref)
+    L = sb.load()
+    h = sb.Handle()
+    h.prepare(int(L.sb_generate_batched_bytes(len(shapes))))
+    h.check(L.sb_generate_batched(h.h, ctypes.c_void_p(gen.ctypes.data), len(shapes)))
+    torch.cuda.synchronize()
+    for (kind, m, n), b, ref in zip(shapes, bufs, refs):
+        assert torch.equal(b, ref), (kind, m, n)
+
+
+def test_tuner_quick_and_tuned_serving(sb, tmp_path):
+    from paper_2108_02025_amd import tuner
+    from paper_2108_02025_amd.serve import Server, make_trace
+    data = tuner.tune(buckets={"f32/8/11", "bf16/11/8"}, batch_bytes=8 << 20, log=lambda s: None)
+    assert set(data["buckets"]) == {"f32/8/11", "bf16/11/8"}
+    for e in data["buckets"].values():
+        assert e["us"] <= e["auto_us"] * 1.5 and e["group"] in (4, 8, 16, 32, 64)
+    tt = tuner.TuningTable(data)
+    assert tt("f32", 256, 2048) == {k: data["buckets"]["f32/8/11"][k] for k in ("group", "rows_per_tile", "split")}
+    assert tt("f32", 64, 64) is None
+    trace = make_trace(200, rate=2e4, seed=9, lo=128, hi=4096)
+    server = Server(budget_bytes=512 << 20, tuning=tt, sample_every=4)
+    st = server.run(trace)
+    assert st.n == 200
+    assert check_sampled(sb, server, trace) == 50
