@@ -29,6 +29,42 @@ import sys
 import time
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC = os.path.join(HERE, "profiles", "hbm_traffic.json")
+
+# Source files whose contents determine each operation's kernels; measured
+# traffic is reported only while their hash matches the one recorded with it.
+KERNEL_SOURCES = {
+    "gemv_n_f64": ["gemv.hip", "sb_rowdot.hpp", "sb_device.hpp"],
+    "gemv_t_f64": ["gemv.hip", "sb_device.hpp"],
+    "dot_f64": ["dot.hip", "sb_device.hpp"],
+    "ger_f64": ["ger.hip", "sb_device.hpp"],
+    "gemv_q_bf16": ["quant.hip", "sb_rowdot.hpp", "sb_quant.hpp", "sb_device.hpp"],
+    "gemv_q_e4m3": ["quant.hip", "sb_rowdot.hpp", "sb_quant.hpp", "sb_device.hpp"],
+    "dot2_f32": ["dot.hip", "sb_device.hpp"],
+}
+
+
+def source_hash(op: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[op]:
+        with open(os.path.join(HERE, "paper_2108_02025_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(op: str):
+    """HBM bytes per call from the committed counter measurement, or None
+    when there is none or the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC) or op not in KERNEL_SOURCES:
+        return None
+    with open(TRAFFIC) as f:
+        d = json.load(f)
+    e = d.get("ops", {}).get(op)
+    if not e or e.get("source_sha256") != source_hash(op):
+        return None
+    return e["traffic_bytes"]
 
 
 def log(msg):
@@ -225,7 +261,11 @@ def main():
     value = sum(step_bytes.values()) / (ms_step * 1e-3) / 1e9
     dom = max(per, key=lambda k: per[k]["us"])
     roof = {"bound": "hbm", "kernel": dom, "achieved": per[dom]["GB/s"], "peak": PEAK_HBM_GBS,
-            "unit": "GB/s", "frac": round(per[dom]["GB/s"] / PEAK_HBM_GBS, 4), "traffic": None}
+            "unit": "GB/s", "frac": round(per[dom]["GB/s"] / PEAK_HBM_GBS, 4), "traffic": measured_traffic(dom)}
+    for name in per:
+        t = measured_traffic(name)
+        if t is not None:
+            per[name]["traffic_bytes"] = t
     extras = {}
     if not args.no_probes:
         probes = build_probes(sb, torch, dev)

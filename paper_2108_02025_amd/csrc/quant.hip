@@ -28,6 +28,9 @@
 #ifndef SB_GEMVQ_UNROLL_E4M3
 #define SB_GEMVQ_UNROLL_E4M3 8
 #endif
+#ifndef SB_GEMVQ_MIN_WAVES
+#define SB_GEMVQ_MIN_WAVES 4
+#endif
 #ifndef SB_GEMVQ_ROWS_BF16
 #define SB_GEMVQ_ROWS_BF16 1
 #endif
@@ -90,10 +93,10 @@ struct GemvQArgs {
     int64_t KC, RB;
 };
 
-// At least 4 waves per SIMD: without the bound the compiler hoists every
-// decode of the loads in flight and needs over 200 VGPRs (2 waves per SIMD).
+// A lower bound on waves per SIMD caps the registers the compiler may use
+// for the loads in flight and their decodes.
 template <bool BF16, int G, int NT, int R>
-__global__ __launch_bounds__(NT, 4) void gemv_q_kernel(GemvQArgs a)
+__global__ __launch_bounds__(NT, SB_GEMVQ_MIN_WAVES) void gemv_q_kernel(GemvQArgs a)
 {
     typedef Codes<BF16> C;
     typedef typename C::code_t code_t;
