@@ -214,6 +214,35 @@ def cpu_baseline(step_bytes):
     }
 
 
+def small_problems(sb, torch, dev):
+    """Per-call GPU time of small problems (50 back-to-back calls replayed
+    from one graph, median of 5), with the library's default cutoffs."""
+    from paper_2108_02025_amd.cutoffs import per_call_us
+    g = torch.Generator(device=dev)
+    g.manual_seed(11)
+
+    def uni(shape, dtype=torch.float64):
+        return torch.rand(shape, generator=g, device=dev, dtype=dtype) * 2 - 1
+
+    res = {}
+    for m, n in ((1024, 1024), (150, 4096)):
+        A, x, c, xt, ct = uni((m, n)), uni(n), uni(m), uni(m), uni(n)
+        nb = 8 * (m * n + n + 2 * m)
+        for name, fn in ((f"gemv_n_f64_{m}x{n}", lambda: sb.sb_gemv(A, x, c)),
+                         (f"gemv_t_f64_{m}x{n}", lambda: sb.sb_gemv(A, xt, ct, op=1))):
+            us = per_call_us(fn)
+            res[name] = {"us": round(us, 2), "GB/s": round(nb / us / 1e3, 1)}
+    for n in (4096, 16384, 1 << 20):
+        x, y, a = uni(n), uni(n), uni(1)
+        us = per_call_us(lambda: sb.sb_dot(x, y, a))
+        res[f"dot_f64_{n}"] = {"us": round(us, 2), "GB/s": round(16 * n / us / 1e3, 1)}
+    x, y, a = uni(16384, torch.float32), uni(16384, torch.float32), uni(1, torch.float32)
+    us = per_call_us(lambda: sb.sb_dot2_f32(x, y, a))
+    res["dot2_f32_16384"] = {"us": round(us, 2), "GB/s": round(8 * 16384 / us / 1e3, 1)}
+    log("small problems: " + ", ".join(f"{k} {v['us']} us" for k, v in res.items()))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +252,7 @@ def main():
     ap.add_argument("--ops", default=None, help="comma-separated subset of operations")
     ap.add_argument("--no-probes", action="store_true", help="skip the HBM read/copy ceiling probes")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
+    ap.add_argument("--no-small", action="store_true", help="skip the small-problem latencies")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -293,6 +323,8 @@ def main():
                    "ops": names, "parallelism": "single GPU"},
         "roofline": roof, "ops": per, **extras,
     }
+    if not args.no_small:
+        out["small"] = small_problems(sb, torch, dev)
     if not args.no_serve:
         from paper_2108_02025_amd.serve import Server, make_trace
         from paper_2108_02025_amd.tuner import TuningTable

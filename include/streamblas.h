@@ -87,6 +87,29 @@ sb_status sb_set_workspace(sb_handle* handle, void* workspace, size_t ws_bytes);
 const char* sb_last_error(const sb_handle* handle);
 
 /*
+ * Small-problem cutoffs (section 4.3: below a size found by experiment, the
+ * dot product runs without a parallel split; section 4 also advises fewer
+ * parallel parts for small problems).  Each handle starts with the defaults
+ * measured on MI355X; callers may re-measure and override them.
+ *   SB_CUTOFF_DOT_SMALL_BYTES     sb_dot and sb_dot2_f32 with at most this
+ *                                 many operand bytes (x and y together) run
+ *                                 as one workgroup in a single launch that
+ *                                 also adds alpha, with no workspace;
+ *                                 above it, the two-stage form.
+ *   SB_CUTOFF_GEMV_T_SMALL_SPLITS a column-axpy GEMV (row-major T,
+ *                                 column-major N) whose row split would have
+ *                                 2 .. this many parts runs unsplit with 16
+ *                                 waves per column block in a single launch.
+ * value must be >= 0 (0 disables the small path); SB_EINVAL otherwise.  A
+ * cutoff changes the summation order (still deterministic for a given
+ * shape and handle) and the workspace a call needs.
+ */
+typedef enum { SB_CUTOFF_DOT_SMALL_BYTES = 0, SB_CUTOFF_GEMV_T_SMALL_SPLITS = 1 } sb_cutoff;
+sb_status sb_set_cutoff(sb_handle* handle, sb_cutoff which, int64_t value);
+/* *value receives the handle's cutoff, or the default when handle is NULL. */
+sb_status sb_get_cutoff(const sb_handle* handle, sb_cutoff which, int64_t* value);
+
+/*
  * Workspace bytes that one call of the given kind and shape needs with this
  * handle's current tuning (0 if none).  For SB_KIND_DOT and SB_KIND_DOT2 the
  * length is n (m is ignored); for SB_KIND_GER the result is always 0.
@@ -120,7 +143,9 @@ sb_status sb_gemv(sb_handle* handle, sb_dtype dtype, sb_layout layout, sb_op op,
  * alpha points to ONE device scalar of that type.  The products are summed
  * in a fixed two-stage order (per-workgroup partial sums in the workspace,
  * then one workgroup combines them in index order) and the initial alpha is
- * added last.  n = 0 leaves alpha unchanged.  Deterministic for a given n.
+ * added last; below SB_CUTOFF_DOT_SMALL_BYTES one workgroup does all of it
+ * in a single launch (Algorithm 3's small-problem form).  n = 0 leaves
+ * alpha unchanged.  Deterministic for a given n and cutoff.
  */
 sb_status sb_dot(sb_handle* handle, sb_dtype dtype, int64_t n, const void* x,
                  const void* y, void* alpha);

@@ -27,6 +27,7 @@ __all__ = [
     "sb_gemv", "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32",
     "sb_stream_read", "sb_stream_copy", "sb_gemv_desc", "GemvProblem", "make_descs", "sb_gemv_batched",
     "sb_gemv_batched_resolve", "sb_gemv_batched_table_bytes", "BatchTable", "sb_fill_uniform",
+    "SB_CUTOFF_DOT_SMALL_BYTES", "SB_CUTOFF_GEMV_T_SMALL_SPLITS", "sb_set_cutoff", "sb_get_cutoff",
 ]
 
 SB_OK, SB_EINVAL, SB_ENOMEM, SB_EDEVICE, SB_EUNSUPPORTED, SB_EINTERNAL = 0, -1, -2, -3, -4, -5
@@ -34,6 +35,7 @@ SB_F64, SB_F32, SB_BF16, SB_FP8_E4M3 = 0, 1, 2, 3
 SB_ROW_MAJOR, SB_COL_MAJOR = 0, 1
 SB_N, SB_T = 0, 1
 SB_KIND_GEMV, SB_KIND_DOT, SB_KIND_GER, SB_KIND_GEMV_Q, SB_KIND_DOT2, SB_KIND_PROBE_READ = 0, 1, 2, 3, 4, 5
+SB_CUTOFF_DOT_SMALL_BYTES, SB_CUTOFF_GEMV_T_SMALL_SPLITS = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libstreamblas.so")
@@ -75,6 +77,8 @@ def load():
     L.sb_set_workspace.argtypes = [P, P, SZ]
     L.sb_last_error.argtypes = [P]
     L.sb_last_error.restype = ctypes.c_char_p
+    L.sb_set_cutoff.argtypes = [P, I32, I64]
+    L.sb_get_cutoff.argtypes = [P, I32, ctypes.POINTER(I64)]
     L.sb_workspace_bytes.argtypes = [P, I32, I32, I32, I32, I64, I64]
     L.sb_workspace_bytes.restype = SZ
     L.sb_gemv.argtypes = [P, I32, I32, I32, I64, I64, P, I64, P, P]
@@ -96,7 +100,7 @@ def load():
     L.sb_stream_read.argtypes = [P, P, SZ]
     L.sb_stream_copy.argtypes = [P, P, P, SZ]
     for f in ("sb_fill_uniform", "sb_generate_batched", "sb_gemv_batched_resolve", "sb_gemv_batched_encode", "sb_gemv_batched_run", "sb_gemv_batched",
-              "sb_stream_read", "sb_stream_copy", "sb_handle_create", "sb_handle_destroy", "sb_set_stream", "sb_set_workspace", "sb_gemv",
+              "sb_stream_read", "sb_stream_copy", "sb_handle_create", "sb_handle_destroy", "sb_set_stream", "sb_set_workspace", "sb_set_cutoff", "sb_get_cutoff", "sb_gemv",
               "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32"):
         getattr(L, f).restype = I32
     _lib = L
@@ -149,6 +153,23 @@ class Handle:
 
 
 _handles: dict[int, Handle] = {}
+
+
+def sb_get_cutoff(which: int, handle: Handle | None = None) -> int:
+    """A handle's small-problem cutoff, or the library default (handle None)."""
+    v = ctypes.c_int64()
+    st = load().sb_get_cutoff(handle.h if handle else None, which, ctypes.byref(v))
+    if st != SB_OK:
+        raise StreamBlasError(st, load().sb_last_error(None).decode())
+    return int(v.value)
+
+
+def sb_set_cutoff(which: int, value: int, handle: Handle | None = None) -> None:
+    """Set a small-problem cutoff on `handle` (default: the current device's)."""
+    if handle is None:
+        idx = torch.cuda.current_device()
+        handle = _handles.get(idx) or _handles.setdefault(idx, Handle(idx))
+    handle.check(load().sb_set_cutoff(handle.h, which, value))
 
 
 def handle_for(t: torch.Tensor) -> Handle:

@@ -112,6 +112,8 @@ sb_status sb_handle_create(void* workspace, size_t ws_bytes, void* stream, sb_ha
     h->ws = workspace;
     h->ws_bytes = workspace ? ws_bytes : 0;
     h->stream = static_cast<hipStream_t>(stream);
+    h->dot_small_bytes = sb::kDefaultDotSmallBytes;
+    h->gemv_t_small_splits = sb::kDefaultGemvTSmallSplits;
     h->err[0] = '\0';
     *out = h;
     return SB_OK;
@@ -139,12 +141,38 @@ sb_status sb_set_workspace(sb_handle* handle, void* workspace, size_t ws_bytes)
     return SB_OK;
 }
 
+sb_status sb_set_cutoff(sb_handle* handle, sb_cutoff which, int64_t value)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_set_cutoff: NULL handle");
+    if (value < 0) return fail(handle, SB_EINVAL, "sb_set_cutoff: negative value %lld", (long long)value);
+    switch (which) {
+    case SB_CUTOFF_DOT_SMALL_BYTES: handle->dot_small_bytes = value; return SB_OK;
+    case SB_CUTOFF_GEMV_T_SMALL_SPLITS: handle->gemv_t_small_splits = value; return SB_OK;
+    }
+    return fail(handle, SB_EINVAL, "sb_set_cutoff: unknown cutoff %d", (int)which);
+}
+
+sb_status sb_get_cutoff(const sb_handle* handle, sb_cutoff which, int64_t* value)
+{
+    if (!value) return fail(nullptr, SB_EINVAL, "sb_get_cutoff: value is NULL");
+    switch (which) {
+    case SB_CUTOFF_DOT_SMALL_BYTES:
+        *value = handle ? handle->dot_small_bytes : sb::kDefaultDotSmallBytes;
+        return SB_OK;
+    case SB_CUTOFF_GEMV_T_SMALL_SPLITS:
+        *value = handle ? handle->gemv_t_small_splits : sb::kDefaultGemvTSmallSplits;
+        return SB_OK;
+    }
+    return fail(nullptr, SB_EINVAL, "sb_get_cutoff: unknown cutoff %d", (int)which);
+}
+
 const char* sb_last_error(const sb_handle* handle) { return handle ? handle->err : g_err; }
 
 size_t sb_workspace_bytes(const sb_handle* handle, sb_kind kind, sb_dtype dtype, sb_layout layout,
                           sb_op op, int64_t m, int64_t n)
 {
-    (void)handle;
+    const int64_t dot_small = handle ? handle->dot_small_bytes : sb::kDefaultDotSmallBytes;
+    const int64_t t_small = handle ? handle->gemv_t_small_splits : sb::kDefaultGemvTSmallSplits;
     const size_t bad = (size_t)-1;
     if (m < 0 || n < 0) return bad;
     switch (kind) {
@@ -155,13 +183,13 @@ size_t sb_workspace_bytes(const sb_handle* handle, sb_kind kind, sb_dtype dtype,
         const int es = esize_of(dtype);
         const int64_t rows = layout == SB_ROW_MAJOR ? m : n, cols = layout == SB_ROW_MAJOR ? n : m;
         const bool row_dot = (layout == SB_ROW_MAJOR) == (op == SB_N);
-        return row_dot ? sb::plan_gemv_n(es, rows, cols).ws : sb::plan_gemv_t(es, rows, cols).ws;
+        return row_dot ? sb::plan_gemv_n(es, rows, cols).ws : sb::plan_gemv_t(es, rows, cols, t_small).ws;
     }
     case SB_KIND_DOT:
         if (dtype != SB_F64 && dtype != SB_F32) return bad;
-        return n == 0 ? 0 : sb::plan_dot(esize_of(dtype), n, 1).ws;
+        return n == 0 ? 0 : sb::plan_dot(esize_of(dtype), n, 1, dot_small).ws;
     case SB_KIND_DOT2:
-        return n == 0 ? 0 : sb::plan_dot(4, n, 2).ws;
+        return n == 0 ? 0 : sb::plan_dot(4, n, 2, dot_small).ws;
     case SB_KIND_GEMV_Q:
         if (dtype != SB_BF16 && dtype != SB_FP8_E4M3) return bad;
         return (m == 0 || n == 0) ? 0 : sb::gemv_q_ws_bytes(dtype, m, n);

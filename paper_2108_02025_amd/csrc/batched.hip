@@ -152,8 +152,7 @@ __device__ __forceinline__ void bat_finish(const BatProblem& p, int64_t r0, int6
     const T* part = static_cast<const T*>(p.partial);
     T* c = static_cast<T*>(p.c);
     for (int64_t row = r0 + threadIdx.x; row < r1; row += kBatNT) {
-        T t = part[row];
-        for (int64_t s = 1; s < p.S; ++s) t += part[s * p.m + row];
+        const T t = ordered_split_sum(part + row, (int64_t)p.S, p.m);
         if (p.dtype == SB_BF16 || p.dtype == SB_FP8_E4M3) c[row] = c[row] + p.scales[row] * t;
         else c[row] = c[row] + t;
     }

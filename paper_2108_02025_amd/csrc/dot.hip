@@ -10,6 +10,8 @@
 // waves in order) and writes one partial sum; a second kernel with one
 // workgroup adds the G partial sums in index order and finally adds the
 // initial alpha.  The order depends only on n, so results are reproducible.
+// Below a cutoff in operand bytes one workgroup does everything in a single
+// launch (the small-problem form of section 4.3).
 #include <algorithm>
 
 #include "sb_device.hpp"
@@ -27,8 +29,18 @@ namespace sb {
 #ifndef SB_DOT_BLOCKS
 #define SB_DOT_BLOCKS 1024
 #endif
+#ifndef SB_DOT_SMALL_BYTES
+#define SB_DOT_SMALL_BYTES (256 * 1024)
+#endif
 constexpr int kUnrollDot = SB_DOT_UNROLL;
 constexpr bool kDotNT = SB_DOT_LOAD_NT;
+constexpr int kSmallNT = 1024;   // threads of the single-workgroup path
+constexpr int kUnrollSmall = 4;
+// Default operand bytes (x and y together) at or below which the
+// single-workgroup path runs.  Measured per call under graph replay on
+// MI355X: one workgroup is faster up to 256 KiB (binary64 n = 16384: 3.6 us
+// against 4.4 us for two launches) and slower from 512 KiB on.
+const int64_t kDefaultDotSmallBytes = SB_DOT_SMALL_BYTES;
 
 template <typename T>
 struct DotArgs {
@@ -39,19 +51,18 @@ struct DotArgs {
     int64_t chunk;
 };
 
-template <typename T, int NT, bool ALIGNED>
-__global__ __launch_bounds__(NT) void dot_stage1_kernel(DotArgs<T> a)
+// Sum of x[b0, b1) . y[b0, b1) over one workgroup: 16-byte loads, U in
+// flight per lane and operand, per-lane accumulators, then the workgroup
+// reduction.  The result is valid in thread 0.
+template <typename T, int NT, int U, bool ALIGNED, bool NTL>
+__device__ __forceinline__ T dot_range(const T* x, const T* y, int64_t b0, int64_t b1, T* red)
 {
     constexpr int W = ALIGNED ? Vec<T>::W : 1;
     typedef typename std::conditional<ALIGNED, typename Vec<T>::type, T>::type V;
-    constexpr int U = kUnrollDot;
-    __shared__ T red[NT / kWave];
 
-    const int64_t b0 = (int64_t)blockIdx.x * a.chunk;
-    const int64_t b1 = min(a.n, b0 + a.chunk);
     const int64_t nv = (b1 - b0) / W;
-    const V* xv = reinterpret_cast<const V*>(a.x + b0);
-    const V* yv = reinterpret_cast<const V*>(a.y + b0);
+    const V* xv = reinterpret_cast<const V*>(x + b0);
+    const V* yv = reinterpret_cast<const V*>(y + b0);
 
     V acc = (V)0;
     int64_t v = threadIdx.x;
@@ -59,13 +70,13 @@ __global__ __launch_bounds__(NT) void dot_stage1_kernel(DotArgs<T> a)
         V xa[U], ya[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            xa[u] = ld_stream<kDotNT>(xv + v + u * NT);
-            ya[u] = ld_stream<kDotNT>(yv + v + u * NT);
+            xa[u] = ld_stream<NTL>(xv + v + u * NT);
+            ya[u] = ld_stream<NTL>(yv + v + u * NT);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) acc += xa[u] * ya[u];
     }
-    for (; v < nv; v += NT) acc += ld_stream<kDotNT>(xv + v) * ld_stream<kDotNT>(yv + v);
+    for (; v < nv; v += NT) acc += ld_stream<NTL>(xv + v) * ld_stream<NTL>(yv + v);
 
     T t;
     if constexpr (W == 1) {
@@ -76,10 +87,30 @@ __global__ __launch_bounds__(NT) void dot_stage1_kernel(DotArgs<T> a)
         for (int q = 1; q < W; ++q) t += acc[q];
     }
     const int64_t t0 = b0 + nv * W;  // fewer than W elements remain
-    if (threadIdx.x < b1 - t0) t += a.x[t0 + threadIdx.x] * a.y[t0 + threadIdx.x];
+    if (threadIdx.x < b1 - t0) t += x[t0 + threadIdx.x] * y[t0 + threadIdx.x];
+    return block_sum<NT>(t, red);
+}
 
-    t = block_sum<NT>(t, red);
+template <typename T, int NT, bool ALIGNED>
+__global__ __launch_bounds__(NT) void dot_stage1_kernel(DotArgs<T> a)
+{
+    __shared__ T red[NT / kWave];
+    const int64_t b0 = (int64_t)blockIdx.x * a.chunk;
+    const int64_t b1 = min(a.n, b0 + a.chunk);
+    const T t = dot_range<T, NT, kUnrollDot, ALIGNED, kDotNT>(a.x, a.y, b0, b1, red);
     if (threadIdx.x == 0) a.partial[blockIdx.x] = t;
+}
+
+// Small problems (section 4.3's Algorithm 3: no parallel split below a
+// cutoff): one workgroup reads both vectors and adds the initial alpha
+// itself, so the whole operation is one launch with no workspace.  Plain
+// loads: operands this small are often still in the caches.
+template <typename T, bool ALIGNED>
+__global__ __launch_bounds__(kSmallNT) void dot_small_kernel(int64_t n, const T* x, const T* y, T* alpha)
+{
+    __shared__ T red[kSmallNT / kWave];
+    const T t = dot_range<T, kSmallNT, kUnrollSmall, ALIGNED, false>(x, y, 0, n, red);
+    if (threadIdx.x == 0) alpha[0] = alpha[0] + t;
 }
 
 // alpha = alpha + (sum of partial[0..nparts) in a fixed order).
@@ -162,17 +193,15 @@ __device__ __forceinline__ Pair pair_block_sum(Pair p, Pair* lds)
     return t;
 }
 
-template <int NT, bool ALIGNED>
-__global__ __launch_bounds__(NT) void dot2_stage1_kernel(int64_t n, const float* x, const float* y,
-                                                         float* partial, int64_t chunk)
+// Compensated sum of x[b0, b1) . y[b0, b1) over one workgroup (the pair is
+// valid in thread 0).
+template <int NT, int U, bool ALIGNED, bool NTL>
+__device__ __forceinline__ Pair dot2_range(const float* x, const float* y, int64_t b0, int64_t b1,
+                                           Pair* red)
 {
     constexpr int W = ALIGNED ? 4 : 1;
     typedef typename std::conditional<ALIGNED, v4f, float>::type V;
-    constexpr int U = kUnrollDot;
-    __shared__ Pair red[NT / kWave];
 
-    const int64_t b0 = (int64_t)blockIdx.x * chunk;
-    const int64_t b1 = min(n, b0 + chunk);
     const int64_t nv = (b1 - b0) / W;
     const V* xv = reinterpret_cast<const V*>(x + b0);
     const V* yv = reinterpret_cast<const V*>(y + b0);
@@ -185,8 +214,8 @@ __global__ __launch_bounds__(NT) void dot2_stage1_kernel(int64_t n, const float*
         V xa[U], ya[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            xa[u] = ld_stream<kDotNT>(xv + v + u * NT);
-            ya[u] = ld_stream<kDotNT>(yv + v + u * NT);
+            xa[u] = ld_stream<NTL>(xv + v + u * NT);
+            ya[u] = ld_stream<NTL>(yv + v + u * NT);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -199,7 +228,7 @@ __global__ __launch_bounds__(NT) void dot2_stage1_kernel(int64_t n, const float*
         }
     }
     for (; v < nv; v += NT) {
-        const V xa = ld_stream<kDotNT>(xv + v), ya = ld_stream<kDotNT>(yv + v);
+        const V xa = ld_stream<NTL>(xv + v), ya = ld_stream<NTL>(yv + v);
         if constexpr (W == 1) {
             pair_fma(acc[0], xa, ya);
         } else {
@@ -213,11 +242,39 @@ __global__ __launch_bounds__(NT) void dot2_stage1_kernel(int64_t n, const float*
     Pair p = acc[0];
 #pragma unroll
     for (int q = 1; q < W; ++q) p = pair_merge(p, acc[q]);
-    p = pair_block_sum<NT>(p, red);
+    return pair_block_sum<NT>(p, red);
+}
+
+// alpha joins last: (s', t) = TwoSum(alpha, s), alpha = s' + (c + t).
+__device__ __forceinline__ void pair_finish(float* alpha, Pair p)
+{
+    float s, t;
+    two_sum(alpha[0], p.s, s, t);
+    alpha[0] = add_rn(s, add_rn(p.c, t));
+}
+
+template <int NT, bool ALIGNED>
+__global__ __launch_bounds__(NT) void dot2_stage1_kernel(int64_t n, const float* x, const float* y,
+                                                         float* partial, int64_t chunk)
+{
+    __shared__ Pair red[NT / kWave];
+    const int64_t b0 = (int64_t)blockIdx.x * chunk;
+    const int64_t b1 = min(n, b0 + chunk);
+    const Pair p = dot2_range<NT, kUnrollDot, ALIGNED, kDotNT>(x, y, b0, b1, red);
     if (threadIdx.x == 0) {
         partial[2 * blockIdx.x] = p.s;
         partial[2 * blockIdx.x + 1] = p.c;
     }
+}
+
+// The single-workgroup form for small problems (see dot_small_kernel).
+template <bool ALIGNED>
+__global__ __launch_bounds__(kSmallNT) void dot2_small_kernel(int64_t n, const float* x, const float* y,
+                                                             float* alpha)
+{
+    __shared__ Pair red[kSmallNT / kWave];
+    const Pair p = dot2_range<kSmallNT, kUnrollSmall, ALIGNED, false>(x, y, 0, n, red);
+    if (threadIdx.x == 0) pair_finish(alpha, p);
 }
 
 __global__ __launch_bounds__(256) void dot2_stage2_kernel(int64_t nparts, const float* partial,
@@ -228,11 +285,7 @@ __global__ __launch_bounds__(256) void dot2_stage2_kernel(int64_t nparts, const 
     for (int64_t i = threadIdx.x; i < nparts; i += 256)
         p = pair_merge(p, Pair{partial[2 * i], partial[2 * i + 1]});
     p = pair_block_sum<256>(p, red);
-    if (threadIdx.x == 0) {
-        float s, t;
-        two_sum(alpha[0], p.s, s, t);
-        alpha[0] = add_rn(s, add_rn(p.c, t));
-    }
+    if (threadIdx.x == 0) pair_finish(alpha, p);
 }
 
 // ---------------------------------------------------------------- plans ---
@@ -241,9 +294,17 @@ static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 constexpr int64_t kMaxDotBlocks = SB_DOT_BLOCKS;  // default: 4 workgroups per compute unit
 
-DotPlan plan_dot(int esize, int64_t n, int partial_values)
+DotPlan plan_dot(int esize, int64_t n, int partial_values, int64_t small_bytes)
 {
     DotPlan p{};
+    if (n * esize * 2 <= small_bytes) {
+        p.small = true;
+        p.NT = kSmallNT;
+        p.nblocks = 1;
+        p.chunk = n;
+        p.ws = 0;
+        return p;
+    }
     p.NT = 256;
     const int64_t step = (int64_t)p.NT * (16 / esize);  // elements per workgroup pass
     const int64_t want = ceil_div(n, step * kUnrollDot);
@@ -257,12 +318,17 @@ DotPlan plan_dot(int esize, int64_t n, int partial_values)
 template <typename T>
 static sb_status dot_typed(sb_handle* h, int64_t n, const T* x, const T* y, T* alpha)
 {
-    const DotPlan p = plan_dot(sizeof(T), n, 1);
+    const DotPlan p = plan_dot(sizeof(T), n, 1, h->dot_small_bytes);
     if (p.ws > h->ws_bytes)
         return fail(h, SB_ENOMEM, "dot needs %zu workspace bytes, handle has %zu", p.ws, h->ws_bytes);
+    const bool al = aligned16(x) && aligned16(y);
+    if (p.small) {
+        if (al) hipLaunchKernelGGL((dot_small_kernel<T, true>), dim3(1), dim3(kSmallNT), 0, h->stream, n, x, y, alpha);
+        else hipLaunchKernelGGL((dot_small_kernel<T, false>), dim3(1), dim3(kSmallNT), 0, h->stream, n, x, y, alpha);
+        return check_launch(h, "dot_small_kernel");
+    }
     T* part = static_cast<T*>(h->ws);
     DotArgs<T> a{n, x, y, part, p.chunk};
-    const bool al = aligned16(x) && aligned16(y);
     if (al) hipLaunchKernelGGL((dot_stage1_kernel<T, 256, true>), dim3((unsigned)p.nblocks), dim3(256), 0, h->stream, a);
     else hipLaunchKernelGGL((dot_stage1_kernel<T, 256, false>), dim3((unsigned)p.nblocks), dim3(256), 0, h->stream, a);
     sb_status st = check_launch(h, "dot_stage1_kernel");
@@ -285,9 +351,16 @@ sb_status run_dot(sb_handle* h, sb_dtype dt, int64_t n, const void* x, const voi
 sb_status run_dot2(sb_handle* h, int64_t n, const float* x, const float* y, float* alpha)
 {
     if (n == 0) return SB_OK;
-    const DotPlan p = plan_dot(sizeof(float), n, 2);
+    const DotPlan p = plan_dot(sizeof(float), n, 2, h->dot_small_bytes);
     if (p.ws > h->ws_bytes)
         return fail(h, SB_ENOMEM, "dot2 needs %zu workspace bytes, handle has %zu", p.ws, h->ws_bytes);
+    if (p.small) {
+        if (aligned16(x) && aligned16(y))
+            hipLaunchKernelGGL((dot2_small_kernel<true>), dim3(1), dim3(kSmallNT), 0, h->stream, n, x, y, alpha);
+        else
+            hipLaunchKernelGGL((dot2_small_kernel<false>), dim3(1), dim3(kSmallNT), 0, h->stream, n, x, y, alpha);
+        return check_launch(h, "dot2_small_kernel");
+    }
     float* part = static_cast<float*>(h->ws);
     if (aligned16(x) && aligned16(y))
         hipLaunchKernelGGL((dot2_stage1_kernel<256, true>), dim3((unsigned)p.nblocks), dim3(256), 0,

@@ -47,6 +47,9 @@ namespace sb {
 #ifndef SB_GEMV_N_WAVES_PER_CU
 #define SB_GEMV_N_WAVES_PER_CU 32
 #endif
+#ifndef SB_GEMV_T_SMALL_SPLITS
+#define SB_GEMV_T_SMALL_SPLITS 2
+#endif
 constexpr int kUnrollN = SB_GEMV_N_UNROLL;  // 16-byte loads in flight per lane and row
 constexpr int kUnrollT = SB_GEMV_T_UNROLL;  // rows in flight per wave
 constexpr bool kGemvNT = SB_GEMV_LOAD_NT;
@@ -100,9 +103,7 @@ __global__ __launch_bounds__(256) void split_finish_kernel(int64_t len, int64_t 
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= len) return;
-    T t = partial[i];
-    for (int64_t s = 1; s < nsplit; ++s) t += partial[s * len + i];
-    out[i] = out[i] + t;
+    out[i] = out[i] + ordered_split_sum(partial + i, nsplit, len);
 }
 
 template <typename T>
@@ -228,7 +229,14 @@ GemvNPlan plan_gemv_n(int esize, int64_t rows, int64_t cols)
     return p;
 }
 
-GemvTPlan plan_gemv_t(int esize, int64_t rows, int64_t cols)
+// Default largest row split replaced by the unsplit single-launch form.
+// Measured per call under graph replay on MI355X: a 2-way split (128..191
+// rows) is slower than 16 waves per column block (binary64 128 x 1024:
+// 4.9 us against 4.0 us), a 3-way split about as fast, 4 ways and more
+// faster (one compute unit then streams too many bytes).
+const int64_t kDefaultGemvTSmallSplits = SB_GEMV_T_SMALL_SPLITS;
+
+GemvTPlan plan_gemv_t(int esize, int64_t rows, int64_t cols, int64_t small_splits)
 {
     GemvTPlan p{};
     p.NT = 256;
@@ -239,6 +247,17 @@ GemvTPlan plan_gemv_t(int esize, int64_t rows, int64_t cols)
     ns = std::min<int64_t>(ns, 512);
     ns = std::min<int64_t>(ns, std::max<int64_t>(1, rows / 64));
     ns = std::max<int64_t>(ns, 1);
+    if (ns >= 2 && ns <= small_splits) {
+        // Few rows (section 4's advice for small problems: fewer parallel
+        // parts): one workgroup of 16 waves per column block has at least
+        // the waves of a split of up to four ways, and needs no second
+        // kernel and no workspace, so the call is a single launch.
+        p.NT = 1024;
+        p.RS = rows;
+        p.nsplit = 1;
+        p.ws = 0;
+        return p;
+    }
     p.RS = ceil_div(rows, ns);
     p.nsplit = ceil_div(rows, p.RS);
     p.ws = p.nsplit > 1 ? (size_t)(p.nsplit * cols * esize) : 0;
@@ -307,15 +326,20 @@ template <typename T>
 static sb_status gemv_t_typed(sb_handle* h, int64_t rows, int64_t cols, const T* A, int64_t ld,
                               const T* x, T* c)
 {
-    const GemvTPlan p = plan_gemv_t(sizeof(T), rows, cols);
+    const GemvTPlan p = plan_gemv_t(sizeof(T), rows, cols, h->gemv_t_small_splits);
     if (p.ws > h->ws_bytes)
         return fail(h, SB_ENOMEM, "gemv needs %zu workspace bytes, handle has %zu", p.ws, h->ws_bytes);
     GemvTArgs<T> a{rows, cols, ld, A, x, c, p.nsplit > 1 ? static_cast<T*>(h->ws) : nullptr, p.RS};
     const bool al = aligned16(A) && ((ld * (int64_t)sizeof(T)) % 16 == 0);
     const int64_t CW = 64 * (al ? 16 / (int64_t)sizeof(T) : 1);
     const dim3 grid((unsigned)ceil_div(cols, CW), (unsigned)p.nsplit);
-    if (al) hipLaunchKernelGGL((gemv_t_kernel<T, 256, true>), grid, dim3(256), 0, h->stream, a);
-    else hipLaunchKernelGGL((gemv_t_kernel<T, 256, false>), grid, dim3(256), 0, h->stream, a);
+    if (p.NT == 1024) {
+        if (al) hipLaunchKernelGGL((gemv_t_kernel<T, 1024, true>), grid, dim3(1024), 0, h->stream, a);
+        else hipLaunchKernelGGL((gemv_t_kernel<T, 1024, false>), grid, dim3(1024), 0, h->stream, a);
+    } else {
+        if (al) hipLaunchKernelGGL((gemv_t_kernel<T, 256, true>), grid, dim3(256), 0, h->stream, a);
+        else hipLaunchKernelGGL((gemv_t_kernel<T, 256, false>), grid, dim3(256), 0, h->stream, a);
+    }
     sb_status st = check_launch(h, "gemv_t_kernel");
     if (st != SB_OK || p.nsplit == 1) return st;
     hipLaunchKernelGGL(split_finish_kernel<T>, dim3((unsigned)ceil_div(cols, 256)), dim3(256), 0,

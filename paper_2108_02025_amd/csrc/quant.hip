@@ -145,9 +145,7 @@ __global__ __launch_bounds__(256) void gemv_q_finish_kernel(int64_t m, int64_t n
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= m) return;
-    float t = partial[i];
-    for (int64_t s = 1; s < nsplit; ++s) t += partial[s * m + i];
-    c[i] = c[i] + scales[i] * t;
+    c[i] = c[i] + scales[i] * ordered_split_sum(partial + i, nsplit, m);
 }
 
 // ---------------------------------------------------------------- plans ---

@@ -12,6 +12,8 @@ struct sb_handle {
     void* ws;
     size_t ws_bytes;
     hipStream_t stream;
+    int64_t dot_small_bytes;      // SB_CUTOFF_DOT_SMALL_BYTES
+    int64_t gemv_t_small_splits;  // SB_CUTOFF_GEMV_T_SMALL_SPLITS
     char err[512];
 };
 
@@ -42,12 +44,14 @@ struct GemvNPlan {
 GemvNPlan plan_gemv_n(int esize, int64_t rows, int64_t cols);
 
 struct GemvTPlan {
-    int NT;         // threads per workgroup (waves split the rows of a split)
+    int NT;         // threads per workgroup (waves split the rows of a split): 256, or
+                    // 1024 for a small matrix done without a row split in one launch
     int64_t nsplit; // number of row splits
     int64_t RS;     // rows per split
     size_t ws;
 };
-GemvTPlan plan_gemv_t(int esize, int64_t rows, int64_t cols);
+GemvTPlan plan_gemv_t(int esize, int64_t rows, int64_t cols, int64_t small_splits);
+extern const int64_t kDefaultGemvTSmallSplits;
 
 sb_status run_gemv_n(sb_handle* h, sb_dtype dt, int64_t rows, int64_t cols, const void* M,
                      int64_t ld, const void* v, void* out);
@@ -56,12 +60,14 @@ sb_status run_gemv_t(sb_handle* h, sb_dtype dt, int64_t rows, int64_t cols, cons
 
 // ---- DOT ------------------------------------------------------------------
 struct DotPlan {
+    bool small;     // one workgroup, one launch, no workspace
     int NT;
     int64_t nblocks;
     int64_t chunk;  // elements per workgroup, multiple of NT*4
     size_t ws;
 };
-DotPlan plan_dot(int esize, int64_t n, int partial_values);
+DotPlan plan_dot(int esize, int64_t n, int partial_values, int64_t small_bytes);
+extern const int64_t kDefaultDotSmallBytes;
 sb_status run_dot(sb_handle* h, sb_dtype dt, int64_t n, const void* x, const void* y, void* alpha);
 sb_status run_dot2(sb_handle* h, int64_t n, const float* x, const float* y, float* alpha);
 

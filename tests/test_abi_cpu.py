@@ -95,6 +95,37 @@ def test_workspace_sizing_and_enomem(L, h):
     assert L.sb_dot2_f32(h, 1 << 20, X_, A_, C_) == -2
 
 
+def test_small_problem_plans(L, h):
+    """Below the cutoffs DOT, Dot2 and GEMV-T run as one launch without
+    workspace; just above they use the two-stage form.  Cutoffs are per
+    handle and settable."""
+    ws = L.sb_workspace_bytes
+    v = ctypes.c_int64()
+    assert L.sb_get_cutoff(None, 0, ctypes.byref(v)) == 0 and v.value == 256 * 1024
+    assert L.sb_get_cutoff(None, 1, ctypes.byref(v)) == 0 and v.value == 2
+    cut64, cut32 = 16384, 32768                       # 256 KiB of x and y together
+    assert ws(None, 1, 0, 0, 0, 1, cut64) == 0 and ws(None, 1, 0, 0, 0, 1, cut64 + 1) > 0
+    assert ws(None, 1, 1, 0, 0, 1, cut32) == 0 and ws(None, 1, 1, 0, 0, 1, cut32 + 1) > 0
+    assert ws(None, 4, 1, 0, 0, 1, cut32) == 0 and ws(None, 4, 1, 0, 0, 1, cut32 + 1) > 0
+    # row-major T, 16384 columns (128 column blocks of binary64): a 2-way row
+    # split (128 <= rows < 192) is replaced by one workgroup of 16 waves per
+    # column block
+    assert ws(None, 0, 0, 0, 1, 127, 16384) == 0     # no split anyway
+    assert ws(None, 0, 0, 0, 1, 128, 16384) == 0
+    assert ws(None, 0, 0, 0, 1, 191, 16384) == 0
+    assert ws(None, 0, 0, 0, 1, 192, 16384) == 3 * 16384 * 8
+    assert ws(None, 0, 0, 1, 0, 16384, 150) == 0     # column-major N: the same kernel
+    assert ws(None, 0, 0, 0, 1, 1024, 1024) == 16 * 1024 * 8
+    # per-handle overrides
+    assert L.sb_set_cutoff(h, 0, 0) == 0 and ws(h, 1, 0, 0, 0, 1, 100) > 0
+    assert L.sb_set_cutoff(h, 0, 1 << 30) == 0 and ws(h, 1, 0, 0, 0, 1, 1 << 20) == 0
+    assert L.sb_get_cutoff(h, 0, ctypes.byref(v)) == 0 and v.value == 1 << 30
+    assert L.sb_set_cutoff(h, 1, 0) == 0 and ws(h, 0, 0, 0, 1, 150, 16384) == 2 * 16384 * 8
+    assert L.sb_set_cutoff(h, 1, 16) == 0 and ws(h, 0, 0, 0, 1, 1024, 1024) == 0
+    assert L.sb_set_cutoff(h, 1, -1) == -1 and L.sb_set_cutoff(h, 7, 1) == -1
+    assert L.sb_set_cutoff(None, 0, 1) == -1 and L.sb_get_cutoff(h, 0, None) == -1
+
+
 def test_dot_ger_quant_validation(L, h):
     assert L.sb_dot(h, 0, -1, X_, A_, C_) == -1
     assert L.sb_dot(h, 0, 10, X_, A_, None) == -1
