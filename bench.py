@@ -37,6 +37,7 @@ TRAFFIC = os.path.join(HERE, "profiles", "hbm_traffic.json")
 KERNEL_SOURCES = {
     "gemv_n_f64": ["gemv.hip", "sb_rowdot.hpp", "sb_device.hpp"],
     "gemv_t_f64": ["gemv.hip", "sb_device.hpp"],
+    "gemv2_f64": ["gemv2.hip", "sb_device.hpp"],
     "dot_f64": ["dot.hip", "sb_device.hpp"],
     "ger_f64": ["ger.hip", "sb_device.hpp"],
     "gemv_q_bf16": ["quant.hip", "sb_rowdot.hpp", "sb_quant.hpp", "sb_device.hpp"],
@@ -87,7 +88,7 @@ def build_ops(sb, torch, dev, sel):
     ops = []
     want = (lambda name: sel is None or name in sel)
     A = None
-    if any(want(k) for k in ("gemv_n_f64", "gemv_t_f64", "gemv_q_bf16", "gemv_q_e4m3")):
+    if any(want(k) for k in ("gemv_n_f64", "gemv_t_f64", "gemv2_f64", "gemv_q_bf16", "gemv_q_e4m3")):
         log("drawing A 16384x16384 binary64")
         A = uni((M, N), 201)
     if want("gemv_n_f64"):
@@ -96,6 +97,10 @@ def build_ops(sb, torch, dev, sel):
     if want("gemv_t_f64"):
         xt, ct = uni((M,), 2013), uni((N,), 2014)
         ops.append(("gemv_t_f64", 8 * (M * N + M + 2 * N), 2 * M * N, lambda: sb.sb_gemv(A, xt, ct, op=sb.SB_T)))
+    if want("gemv2_f64"):
+        x2, y2, c2, d2 = uni((N,), 2015), uni((M,), 2016), uni((M,), 2017), uni((N,), 2018)
+        ops.append(("gemv2_f64", 8 * (M * N + N + M + 2 * M + 2 * N), 4 * M * N,
+                    lambda: sb.sb_gemv2(A, x2, y2, c2, d2)))
     if want("dot_f64"):
         log("drawing DOT vectors n=2^28")
         dx, dy, da = uni((nd,), 2021), uni((nd,), 2022), uni((1,), 2023)
@@ -308,6 +313,9 @@ def main():
             ref = ceil["probe_copy"] if name == "ger_f64" else ceil["probe_read"]
             per[name]["frac_ceiling"] = round(per[name]["GB/s"] / ref, 4)
         log(f"probes: read {ceil['probe_read']} GB/s, copy {ceil['probe_copy']} GB/s")
+    if all(k in per for k in ("gemv_n_f64", "gemv_t_f64", "gemv2_f64")):
+        extras["gemv2_speedup_over_two_calls"] = round(
+            (per["gemv_n_f64"]["us"] + per["gemv_t_f64"]["us"]) / per["gemv2_f64"]["us"], 3)
     if "gemv_n_f64" in per and "gemv_q_bf16" in per:
         extras["bf16_over_f64_flops"] = round(per["gemv_q_bf16"]["TFLOP/s"] / per["gemv_n_f64"]["TFLOP/s"], 3)
     if "gemv_n_f64" in per and "gemv_q_e4m3" in per:
@@ -318,7 +326,7 @@ def main():
         "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+f32", "data": "synthetic",
-        "config": {"workload": "fp64 gemv N/T 16384x16384, dot n=2^28, ger 16384x16384; "
+        "config": {"workload": "fp64 gemv N/T and two-sided 16384x16384, dot n=2^28, ger 16384x16384; "
                                "bf16-A and e4m3-A gemv 16384x16384 (f32 x, c); dot2 f32 n=2^27 cond 1e8",
                    "ops": names, "parallelism": "single GPU"},
         "roofline": roof, "ops": per, **extras,

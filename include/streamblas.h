@@ -53,7 +53,7 @@ typedef enum { SB_N = 0, SB_T = 1 } sb_op;
 
 /* Operation kinds, for sb_workspace_bytes. */
 typedef enum { SB_KIND_GEMV = 0, SB_KIND_DOT = 1, SB_KIND_GER = 2, SB_KIND_GEMV_Q = 3,
-               SB_KIND_DOT2 = 4, SB_KIND_PROBE_READ = 5 } sb_kind;
+               SB_KIND_DOT2 = 4, SB_KIND_PROBE_READ = 5, SB_KIND_GEMV2 = 6 } sb_kind;
 
 typedef struct sb_handle sb_handle;
 
@@ -112,7 +112,8 @@ sb_status sb_get_cutoff(const sb_handle* handle, sb_cutoff which, int64_t* value
 /*
  * Workspace bytes that one call of the given kind and shape needs with this
  * handle's current tuning (0 if none).  For SB_KIND_DOT and SB_KIND_DOT2 the
- * length is n (m is ignored); for SB_KIND_GER the result is always 0.
+ * length is n (m is ignored); for SB_KIND_GER the result is always 0; for
+ * SB_KIND_GEMV2 op is ignored.
  * Returns (size_t)-1 for invalid arguments.
  */
 size_t sb_workspace_bytes(const sb_handle* handle, sb_kind kind, sb_dtype dtype,
@@ -136,6 +137,28 @@ size_t sb_workspace_bytes(const sb_handle* handle, sb_kind kind, sb_dtype dtype,
 sb_status sb_gemv(sb_handle* handle, sb_dtype dtype, sb_layout layout, sb_op op,
                   int64_t m, int64_t n, const void* A, int64_t lda,
                   const void* x, void* c);
+
+/*
+ * Two-sided GEMV: c += A x and d += A^T y in one pass over A.  An extension
+ * of the section 3.1 GEMV definition for callers that need both products of
+ * one matrix (as in bidiagonalisation, or the BLAS Technical Forum's fused
+ * GEMVT): the paper finds these operations bound by memory traffic
+ * (sections 4.2 and 4.3), and reading A once instead of twice halves it.
+ *   dtype  SB_F64 or SB_F32 for A, x, y, c and d.
+ *   A      m x n in `layout` with leading dimension lda (as in sb_gemv).
+ *   x      n entries; c: m entries, c_i += sum_j A_ij x_j.
+ *   y      m entries; d: n entries, d_j += sum_i A_ij y_i.
+ * Each output is the sum of its products with the initial value added last,
+ * each sum in a fixed order that depends only on (dtype, layout, m, n, lda
+ * alignment): deterministic, but not the same order as sb_gemv, so the bits
+ * may differ from two sb_gemv calls within the same error bound.  x and y
+ * may alias each other; c and d must not overlap A, x, y or each other
+ * (SB_EINVAL).  If m or n is 0 nothing is launched and both outputs are
+ * unchanged (an empty sum adds nothing).  Needs sb_workspace_bytes of kind
+ * SB_KIND_GEMV2 in the handle's workspace (SB_ENOMEM otherwise).
+ */
+sb_status sb_gemv2(sb_handle* handle, sb_dtype dtype, sb_layout layout, int64_t m, int64_t n,
+                   const void* A, int64_t lda, const void* x, const void* y, void* c, void* d);
 
 /*
  * DOT: *alpha += x . y   (section 3.1, Definition (DOT); section 4.3,

@@ -118,6 +118,13 @@ def gemv(A, x, c0, op: int = OP_N, layout: int = ROW_MAJOR, lda: int | None = No
     return c
 
 
+def gemv2(A, x, y, c0, d0, layout: int = ROW_MAJOR) -> tuple[np.ndarray, np.ndarray]:
+    """Two-sided GEMV: (c0 + A x, d0 + A^T y), each by the GEMV definition
+    (section 3.1) on its own; the fused form reads A once but computes the
+    same two sums."""
+    return gemv(A, x, c0, op=OP_N, layout=layout), gemv(A, y, d0, op=OP_T, layout=layout)
+
+
 def gemv_entries(A, x, idx, c0_at_idx, op: int = OP_N, layout: int = ROW_MAJOR,
                  lda: int | None = None, shape: tuple[int, int] | None = None) -> np.ndarray:
     """The GEMV definition evaluated only for the output indices ``idx``."""

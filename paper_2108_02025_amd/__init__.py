@@ -21,7 +21,7 @@ import torch
 
 __all__ = [
     "SB_F64", "SB_F32", "SB_BF16", "SB_FP8_E4M3", "SB_ROW_MAJOR", "SB_COL_MAJOR", "SB_N", "SB_T",
-    "SB_KIND_GEMV", "SB_KIND_DOT", "SB_KIND_GER", "SB_KIND_GEMV_Q", "SB_KIND_DOT2",
+    "SB_KIND_GEMV", "SB_KIND_DOT", "SB_KIND_GER", "SB_KIND_GEMV_Q", "SB_KIND_DOT2", "SB_KIND_GEMV2", "sb_gemv2",
     "StreamBlasError", "load", "lib_path", "Handle", "handle_for",
     "sb_version", "sb_status_string", "sb_workspace_bytes",
     "sb_gemv", "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32",
@@ -35,6 +35,7 @@ SB_F64, SB_F32, SB_BF16, SB_FP8_E4M3 = 0, 1, 2, 3
 SB_ROW_MAJOR, SB_COL_MAJOR = 0, 1
 SB_N, SB_T = 0, 1
 SB_KIND_GEMV, SB_KIND_DOT, SB_KIND_GER, SB_KIND_GEMV_Q, SB_KIND_DOT2, SB_KIND_PROBE_READ = 0, 1, 2, 3, 4, 5
+SB_KIND_GEMV2 = 6
 SB_CUTOFF_DOT_SMALL_BYTES, SB_CUTOFF_GEMV_T_SMALL_SPLITS = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -83,6 +84,7 @@ def load():
     L.sb_workspace_bytes.restype = SZ
     L.sb_gemv.argtypes = [P, I32, I32, I32, I64, I64, P, I64, P, P]
     L.sb_dot.argtypes = [P, I32, I64, P, P, P]
+    L.sb_gemv2.argtypes = [P, I32, I32, I64, I64, P, I64, P, P, P, P]
     L.sb_ger.argtypes = [P, I32, I32, I64, I64, P, P, P, I64]
     L.sb_quantize_rows.argtypes = [P, I32, I64, I64, P, I64, P, I64, P]
     L.sb_gemv_q.argtypes = [P, I32, I64, I64, P, I64, P, P, P]
@@ -100,7 +102,7 @@ def load():
     L.sb_stream_read.argtypes = [P, P, SZ]
     L.sb_stream_copy.argtypes = [P, P, P, SZ]
     for f in ("sb_fill_uniform", "sb_generate_batched", "sb_gemv_batched_resolve", "sb_gemv_batched_encode", "sb_gemv_batched_run", "sb_gemv_batched",
-              "sb_stream_read", "sb_stream_copy", "sb_handle_create", "sb_handle_destroy", "sb_set_stream", "sb_set_workspace", "sb_set_cutoff", "sb_get_cutoff", "sb_gemv",
+              "sb_stream_read", "sb_stream_copy", "sb_handle_create", "sb_handle_destroy", "sb_set_stream", "sb_set_workspace", "sb_set_cutoff", "sb_get_cutoff", "sb_gemv", "sb_gemv2",
               "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32"):
         getattr(L, f).restype = I32
     _lib = L
@@ -238,6 +240,24 @@ def sb_gemv(A: torch.Tensor, x: torch.Tensor, c: torch.Tensor, op: int = SB_N) -
     h.prepare(sb_workspace_bytes(SB_KIND_GEMV, dt, layout, op, m, n, h))
     h.check(load().sb_gemv(h.h, dt, layout, op, m, n, _ptr(A), ld, _ptr(x), _ptr(c)))
     return c
+
+
+def sb_gemv2(A: torch.Tensor, x: torch.Tensor, y: torch.Tensor, c: torch.Tensor, d: torch.Tensor):
+    """c += A x and d += A^T y in place, reading A once (row- or column-major
+    A from its strides)."""
+    _device_check(A, x, y, c, d)
+    _vec(x), _vec(y), _vec(c), _vec(d)
+    dt = _dtype(A)
+    if any(t.dtype != A.dtype for t in (x, y, c, d)):
+        raise TypeError("A, x, y, c and d must share a dtype")
+    layout, ld = _matrix_layout(A)
+    m, n = A.shape
+    if x.numel() != n or c.numel() != m or y.numel() != m or d.numel() != n:
+        raise ValueError(f"A is {m}x{n}: need x, d of {n} and y, c of {m} entries")
+    h = handle_for(A)
+    h.prepare(sb_workspace_bytes(SB_KIND_GEMV2, dt, layout, 0, m, n, h))
+    h.check(load().sb_gemv2(h.h, dt, layout, m, n, _ptr(A), ld, _ptr(x), _ptr(y), _ptr(c), _ptr(d)))
+    return c, d
 
 
 def sb_dot(x: torch.Tensor, y: torch.Tensor, alpha: torch.Tensor) -> torch.Tensor:

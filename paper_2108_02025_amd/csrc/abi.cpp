@@ -185,6 +185,13 @@ size_t sb_workspace_bytes(const sb_handle* handle, sb_kind kind, sb_dtype dtype,
         const bool row_dot = (layout == SB_ROW_MAJOR) == (op == SB_N);
         return row_dot ? sb::plan_gemv_n(es, rows, cols).ws : sb::plan_gemv_t(es, rows, cols, t_small).ws;
     }
+    case SB_KIND_GEMV2: {
+        if (dtype != SB_F64 && dtype != SB_F32) return bad;
+        if (layout != SB_ROW_MAJOR && layout != SB_COL_MAJOR) return bad;
+        if (m == 0 || n == 0) return 0;
+        const int64_t rows = layout == SB_ROW_MAJOR ? m : n, cols = layout == SB_ROW_MAJOR ? n : m;
+        return sb::plan_gemv2(esize_of(dtype), rows, cols).ws;
+    }
     case SB_KIND_DOT:
         if (dtype != SB_F64 && dtype != SB_F32) return bad;
         return n == 0 ? 0 : sb::plan_dot(esize_of(dtype), n, 1, dot_small).ws;
@@ -233,6 +240,38 @@ sb_status sb_gemv(sb_handle* handle, sb_dtype dtype, sb_layout layout, sb_op op,
     const bool row_dot = (layout == SB_ROW_MAJOR) == (op == SB_N);
     return row_dot ? sb::run_gemv_n(handle, dtype, rows, cols, A, lda, x, c)
                    : sb::run_gemv_t(handle, dtype, rows, cols, A, lda, x, c);
+    SB_GUARD_END
+}
+
+sb_status sb_gemv2(sb_handle* handle, sb_dtype dtype, sb_layout layout, int64_t m, int64_t n, const void* A,
+                   int64_t lda, const void* x, const void* y, void* c, void* d)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_gemv2: NULL handle");
+    SB_GUARD_BEGIN
+    if (dtype == SB_BF16 || dtype == SB_FP8_E4M3) return fail(handle, SB_EUNSUPPORTED, "sb_gemv2: narrow dtype");
+    if (dtype != SB_F64 && dtype != SB_F32) return fail(handle, SB_EINVAL, "sb_gemv2: bad dtype %d", (int)dtype);
+    if (layout != SB_ROW_MAJOR && layout != SB_COL_MAJOR) return fail(handle, SB_EINVAL, "sb_gemv2: bad layout %d", (int)layout);
+    if (m < 0 || n < 0) return fail(handle, SB_EINVAL, "sb_gemv2: negative size m=%lld n=%lld", (long long)m, (long long)n);
+    const int64_t rows = layout == SB_ROW_MAJOR ? m : n, cols = layout == SB_ROW_MAJOR ? n : m;
+    if (lda < (cols > 1 ? cols : 1))
+        return fail(handle, SB_EINVAL, "sb_gemv2: lda=%lld below %lld", (long long)lda, (long long)(cols > 1 ? cols : 1));
+    const int es = esize_of(dtype);
+    const int64_t a_el = span_elems(rows, cols, lda);
+    int64_t a_bytes;
+    if (a_el < 0 || !mul_ok(a_el, es, &a_bytes) || a_bytes > kMaxBytes)
+        return fail(handle, SB_EINVAL, "sb_gemv2: matrix extent overflows");
+    if (m == 0 || n == 0) return SB_OK;
+    if (!A || !x || !y || !c || !d) return fail(handle, SB_EINVAL, "sb_gemv2: NULL pointer with non-zero extent");
+    if (misaligned(A, es) || misaligned(x, es) || misaligned(y, es) || misaligned(c, es) || misaligned(d, es))
+        return fail(handle, SB_EINVAL, "sb_gemv2: pointer not aligned to the element size");
+    const Range ra = range_of(A, a_el, es), rx = range_of(x, n, es), ry = range_of(y, m, es);
+    const Range rc = range_of(c, m, es), rd = range_of(d, n, es);
+    if (overlap(rc, ra) || overlap(rc, rx) || overlap(rc, ry) || overlap(rd, ra) || overlap(rd, rx) ||
+        overlap(rd, ry) || overlap(rc, rd))
+        return fail(handle, SB_EINVAL, "sb_gemv2: c or d overlaps A, x, y or the other output");
+    // On the row-major view: row-dot gives c (row-major) or d (column-major).
+    if (layout == SB_ROW_MAJOR) return sb::run_gemv2(handle, dtype, rows, cols, A, lda, x, y, c, d);
+    return sb::run_gemv2(handle, dtype, rows, cols, A, lda, y, x, d, c);
     SB_GUARD_END
 }
 

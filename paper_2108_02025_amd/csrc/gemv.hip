@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void split_finish_kernel(int64_t len, int64_t 
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= len) return;
-    out[i] = out[i] + ordered_split_sum(partial + i, nsplit, len);
+    out[i] = out[i] + ordered_split_sum<16>(partial + i, nsplit, len);
 }
 
 template <typename T>
@@ -309,6 +309,9 @@ static sb_status gemv_n_typed(sb_handle* h, int64_t rows, int64_t cols, const T*
     const GemvNPlan p = plan_gemv_n(sizeof(T), rows, cols);
     if (p.ws > h->ws_bytes)
         return fail(h, SB_ENOMEM, "gemv needs %zu workspace bytes, handle has %zu", p.ws, h->ws_bytes);
+    if (p.nsplit > 65535)
+        return fail(h, SB_EUNSUPPORTED, "gemv: rows of %lld elements need %lld column splits (at most 65535)",
+                    (long long)cols, (long long)p.nsplit);
     GemvNArgs<T> a{rows, cols, ld, A, x, c, p.nsplit > 1 ? static_cast<T*>(h->ws) : nullptr, p.KC, p.RB};
     const bool al = aligned16(A) && ((ld * (int64_t)sizeof(T)) % 16 == 0);
     const dim3 grid((unsigned)ceil_div(rows, p.RB), (unsigned)p.nsplit);

@@ -236,6 +236,9 @@ sb_status run_gemv_q(sb_handle* h, sb_dtype q, int64_t m, int64_t n, const void*
     const GemvQPlan p = plan_gemv_q(q, m, n, R);
     if (p.ws > h->ws_bytes)
         return fail(h, SB_ENOMEM, "gemv_q needs %zu workspace bytes, handle has %zu", p.ws, h->ws_bytes);
+    if (p.nsplit > 65535)
+        return fail(h, SB_EUNSUPPORTED, "gemv_q: rows of %lld codes need %lld column splits (at most 65535)",
+                    (long long)n, (long long)p.nsplit);
     GemvQArgs a{m, n, ldq, Aq, scales, x, c, p.nsplit > 1 ? static_cast<float*>(h->ws) : nullptr, p.KC, p.RB};
     const dim3 grid((unsigned)ceil_div(m, p.RB), (unsigned)p.nsplit);
     bool ok;

@@ -58,6 +58,22 @@ sb_status run_gemv_n(sb_handle* h, sb_dtype dt, int64_t rows, int64_t cols, cons
 sb_status run_gemv_t(sb_handle* h, sb_dtype dt, int64_t rows, int64_t cols, const void* M,
                      int64_t ld, const void* v, void* out);
 
+// ---- two-sided GEMV -------------------------------------------------------
+// out_r[i] += sum_j M[i, j] vc[j] and out_c[j] += sum_i M[i, j] vr[i] in one
+// pass over a row-major rows x cols view M.
+struct Gemv2Plan {
+    int NW;             // waves per workgroup (each 64 lanes x 16 bytes of columns)
+    int64_t ncb;        // column bands (partial row sums when > 1)
+    int64_t nsplit;     // row bands (partial column sums when > 1)
+    int64_t RS;         // rows per band
+    size_t lds;         // dynamic LDS bytes
+    size_t ws_c_offset; // workspace offset of the partial column sums
+    size_t ws;          // workspace bytes
+};
+Gemv2Plan plan_gemv2(int esize, int64_t rows, int64_t cols);
+sb_status run_gemv2(sb_handle* h, sb_dtype dt, int64_t rows, int64_t cols, const void* M, int64_t ld,
+                    const void* vc, const void* vr, void* out_r, void* out_c);
+
 // ---- DOT ------------------------------------------------------------------
 struct DotPlan {
     bool small;     // one workgroup, one launch, no workspace

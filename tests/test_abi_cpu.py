@@ -126,6 +126,29 @@ def test_small_problem_plans(L, h):
     assert L.sb_set_cutoff(None, 0, 1) == -1 and L.sb_get_cutoff(h, 0, None) == -1
 
 
+def test_gemv2_validation_and_workspace(L, h):
+    Y_, D_ = FAKE + (3 << 36), FAKE + (4 << 36)
+
+    def g2(dt=0, layout=0, m=10, n=12, A=A_, lda=12, x=X_, y=Y_, c=C_, d=D_):
+        return L.sb_gemv2(h, dt, layout, m, n, A, lda, x, y, c, d)
+    assert L.sb_gemv2(None, 0, 0, 1, 1, A_, 1, X_, Y_, C_, D_) == -1
+    assert g2(dt=2) == -4 and g2(dt=5) == -1 and g2(layout=3) == -1
+    assert g2(m=-1) == -1 and g2(lda=11) == -1 and g2(layout=1, lda=9) == -1
+    assert g2(A=None) == -1 and g2(y=None) == -1 and g2(d=None) == -1
+    assert g2(d=A_ + 8) == -1                      # d inside A
+    assert g2(c=D_ + 16) == -1                     # c overlaps d
+    assert g2(c=Y_) == -1 and g2(d=X_ + 8) == -1   # outputs overlap inputs
+    assert g2(m=4096, n=4096, lda=4096, y=X_) == -2   # x and y may alias; no workspace here
+    assert g2(m=0, A=None, x=None, y=None, c=None, d=None) == 0
+    assert g2(n=0, lda=1, A=None, x=None, y=None, c=None, d=None) == 0
+    ws = L.sb_workspace_bytes
+    # 16384 x 16384 binary64: 8 column bands of 2048 and 32 row bands of 512
+    assert ws(None, 6, 0, 0, 0, 16384, 16384) == 8 * 16384 * 8 + 32 * 16384 * 8
+    assert ws(None, 6, 0, 1, 0, 16384, 16384) == ws(None, 6, 0, 0, 0, 16384, 16384)
+    assert ws(None, 6, 0, 0, 0, 64, 64) == 0       # one band each way: direct update
+    assert ws(None, 6, 2, 0, 0, 64, 64) == (1 << 64) - 1
+
+
 def test_dot_ger_quant_validation(L, h):
     assert L.sb_dot(h, 0, -1, X_, A_, C_) == -1
     assert L.sb_dot(h, 0, 10, X_, A_, None) == -1
