@@ -26,6 +26,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 ROW_MAJOR, COL_MAJOR = 0, 1
 OP_N, OP_T = 0, 1
 Q_BF16, Q_E4M3 = 2, 3
+Q_MXFP8, Q_MXFP4 = 4, 5
 
 _CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared", "-Wall"]
 
@@ -71,6 +72,16 @@ def lib():
         L.orc_gemv_q.restype = I32
         L.orc_dot_exact_f32.argtypes = [I64, P, P, F, I32]
         L.orc_dot_exact_f32.restype = D
+        L.orc_e8m0_to_f64.argtypes = [ctypes.c_uint8]
+        L.orc_e8m0_to_f64.restype = D
+        L.orc_e2m1_to_f64.argtypes = [ctypes.c_uint8]
+        L.orc_e2m1_to_f64.restype = D
+        L.orc_e2m1_from_f64.argtypes = [D]
+        L.orc_e2m1_from_f64.restype = ctypes.c_uint8
+        L.orc_quantize_mx.argtypes = [I32, I64, I64, P, I64, P, I64, P, I64]
+        L.orc_quantize_mx.restype = I32
+        L.orc_gemv_mx.argtypes = [I32, I64, I64, P, I64, P, I64, P, P]
+        L.orc_gemv_mx.restype = I32
         L.orc_sum_exact_f64.argtypes = [I64, P]
         L.orc_sum_exact_f64.restype = D
         _lib = L
@@ -199,6 +210,50 @@ def gemv_q(codes, scales, x, c0, q: int) -> np.ndarray:
     x = np.ascontiguousarray(x, dtype=np.float32)
     c = _f64(c0).copy()
     rc = lib().orc_gemv_q(q, m, n, _p(codes), max(n, 1), _p(scales), _p(x), _p(c))
+    assert rc == 0, rc
+    return c
+
+
+def e8m0_to_f64(code: int) -> float:
+    return float(lib().orc_e8m0_to_f64(int(code)))
+
+
+def e2m1_to_f64(code: int) -> float:
+    return float(lib().orc_e2m1_to_f64(int(code)))
+
+
+def e2m1_from_f64(v: float) -> int:
+    return int(lib().orc_e2m1_from_f64(float(v)))
+
+
+def mx_row_bytes(q: int, n: int) -> int:
+    """Bytes of one row of MX element codes (MXFP8: n, MXFP4: ceil(n/2))."""
+    return n if q == Q_MXFP8 else (n + 1) // 2
+
+
+def quantize_mx(A, q: int):
+    """MX quantisation (blocks of 32 along each row) of a binary32 matrix;
+    returns (codes m x row bytes, E8M0 scales m x ceil(n/32))."""
+    A = np.ascontiguousarray(A, dtype=np.float32)
+    m, n = A.shape
+    rb, nb = mx_row_bytes(q, n), (n + 31) // 32
+    codes = np.zeros((m, max(rb, 1)), dtype=np.uint8)
+    scales = np.zeros((m, max(nb, 1)), dtype=np.uint8)
+    rc = lib().orc_quantize_mx(q, m, n, _p(A), max(n, 1), _p(codes), codes.shape[1], _p(scales), scales.shape[1])
+    assert rc == 0, rc
+    return codes[:, :rb], scales[:, :nb]
+
+
+def gemv_mx(codes, scales, x, c0, q: int, n: int) -> np.ndarray:
+    """c0 + (X * P) x in binary64 on the decoded MX blocks of an m x n matrix."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    scales = np.ascontiguousarray(scales, dtype=np.uint8)
+    m = codes.shape[0]
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    assert x.shape[0] == n
+    c = _f64(c0).copy()
+    rc = lib().orc_gemv_mx(q, m, n, _p(codes), max(codes.shape[1], 1), _p(scales), max(scales.shape[1], 1),
+                           _p(x), _p(c))
     assert rc == 0, rc
     return c
 

@@ -216,11 +216,11 @@ float orc_e4m3_to_f32(uint8_t code)
 }
 
 /* Round to E4M3FN, nearest-even, saturating magnitudes above 448 to 448. */
-uint8_t orc_e4m3_from_f32(float f)
+static uint8_t e4m3_from_f64(double d, int negative)
 {
-    uint8_t sign = (f32_bits(f) >> 31) ? 0x80 : 0x00;
-    if (isnan(f)) return (uint8_t)(sign | 0x7F);
-    double v = fabs((double)f);
+    uint8_t sign = negative ? 0x80 : 0x00;
+    if (isnan(d)) return (uint8_t)(sign | 0x7F);
+    double v = fabs(d);
     if (v >= 448.0) return (uint8_t)(sign | 0x7E);
     if (v < 0x1p-6) {
         /* Subnormal range, quantum 2^-9; k = 8 lands exactly on 2^-6, whose
@@ -237,6 +237,8 @@ uint8_t orc_e4m3_from_f32(float f)
     if (field > 15 || (field == 15 && k - 8.0 > 6.0)) return (uint8_t)(sign | 0x7E);
     return (uint8_t)(sign | (uint8_t)(field << 3) | (uint8_t)(k - 8.0));
 }
+
+uint8_t orc_e4m3_from_f32(float f) { return e4m3_from_f64((double)f, (int)(f32_bits(f) >> 31)); }
 
 /*
  * Per-row scaled quantisation (precision form; the paper is silent on it).
@@ -411,4 +413,131 @@ double orc_sum_exact_f64(int64_t n, const double* v)
     double r = lacc_round(a);
     free(a);
     return r;
+}
+
+/*
+ * Microscaling (OCP Microscaling Formats specification v1.0): each row is
+ * cut into blocks of 32 consecutive elements (the last block of a row may
+ * be shorter); a block stores one shared scale X in E8M0 (X = 2^(code-127),
+ * code 255 is NaN) and its elements P_j in E4M3 (MXFP8) or E2M1 (MXFP4);
+ * element j decodes to X * P_j.
+ *
+ * E2M1: sign, 2 exponent bits (bias 1), 1 mantissa bit, no infinities or
+ * NaN; the eight magnitudes are 0, 0.5, 1, 1.5, 2, 3, 4, 6.
+ */
+double orc_e8m0_to_f64(uint8_t code) { return code == 255 ? NAN : ldexp(1.0, (int)code - 127); }
+
+double orc_e2m1_to_f64(uint8_t code)
+{
+    const int s = (code >> 3) & 1, e = (code >> 1) & 3, mbit = code & 1;
+    const double mag = e == 0 ? 0.5 * mbit : ldexp(1.0 + 0.5 * mbit, e - 1);
+    return s ? -mag : mag;
+}
+
+/* Round to the nearest of the eight magnitudes; a tie goes to the code with
+ * an even last bit; beyond 6 the magnitude saturates to 6.  The sign is
+ * kept (so -0.0 and small negatives give the code 8, negative zero). */
+uint8_t orc_e2m1_from_f64(double v)
+{
+    const int neg = signbit(v) ? 1 : 0;
+    const double a = fabs(v);
+    int best = 0;
+    double bestd = INFINITY;
+    for (int c = 0; c < 8; ++c) {
+        const double d = fabs(a - orc_e2m1_to_f64((uint8_t)c));
+        if (d < bestd || (d == bestd && (c & 1) == 0)) {
+            best = c;
+            bestd = d;
+        }
+    }
+    if (a > 6.0) best = 7;
+    return (uint8_t)((neg << 3) | best);
+}
+
+/*
+ * MX quantisation of a row-major m x n binary32 matrix, blocks of 32 along
+ * each row (scale rule of the specification's conversion section):
+ *   a block with a non-finite element: X code 255 (NaN), element codes 0;
+ *   a block of zeros: X code 0, element codes of signed zero;
+ *   otherwise E = floor(log2 amax) and code = clamp(E - emax + 127, 0, 254)
+ *   with emax = 8 (E4M3, largest normal 448 = 1.75 * 2^8) or 2 (E2M1,
+ *   largest 6 = 1.5 * 2^2); P_j = encode(a_j / X), a_j / X exact in binary64,
+ *   rounded to nearest even and saturated.
+ * q = 4 selects MXFP8 (E4M3 codes, one byte each, row stride ldq bytes);
+ * q = 5 selects MXFP4 (E2M1 codes, element 2k in the low nibble and 2k+1 in
+ * the high nibble of byte k of the row; an unused high nibble is 0).
+ * Scales: S[i * lds + b] for block b of row i.
+ */
+int32_t orc_quantize_mx(int32_t q, int64_t m, int64_t n, const float* A, int64_t lda,
+                        uint8_t* Q, int64_t ldq, uint8_t* S, int64_t lds)
+{
+    if (q != 4 && q != 5) return -1;
+    const int emax = q == 4 ? 8 : 2;
+    const int64_t nb = (n + 31) / 32;
+    for (int64_t i = 0; i < m; ++i) {
+        if (q == 5)
+            for (int64_t k = 0; k < (n + 1) / 2; ++k) Q[i * ldq + k] = 0;
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t j0 = 32 * b, j1 = j0 + 32 < n ? j0 + 32 : n;
+            int finite = 1;
+            double amax = 0.0;
+            for (int64_t j = j0; j < j1; ++j) {
+                const double a = (double)A[i * lda + j];
+                if (!isfinite(a)) finite = 0;
+                else if (fabs(a) > amax) amax = fabs(a);
+            }
+            int code;
+            if (!finite) {
+                code = 255;
+            } else if (amax == 0.0) {
+                code = 0;
+            } else {
+                int ex;
+                frexp(amax, &ex);              /* amax in [2^(ex-1), 2^ex) */
+                code = (ex - 1) - emax + 127;
+                if (code < 0) code = 0;
+                if (code > 254) code = 254;
+            }
+            S[i * lds + b] = (uint8_t)code;
+            for (int64_t j = j0; j < j1; ++j) {
+                const double a = (double)A[i * lda + j];
+                uint8_t c = 0;
+                if (code != 255) {
+                    const double v = ldexp(a, 127 - code);
+                    c = q == 4 ? e4m3_from_f64(v, signbit(v) ? 1 : 0) : orc_e2m1_from_f64(v);
+                }
+                if (q == 4) Q[i * ldq + j] = c;
+                else Q[i * ldq + j / 2] |= (uint8_t)(c << (4 * (j & 1)));
+            }
+        }
+    }
+    return 0;
+}
+
+static double mx_element(int32_t q, const uint8_t* Qrow, int64_t j)
+{
+    if (q == 4) return (double)orc_e4m3_to_f32(Qrow[j]);
+    return orc_e2m1_to_f64((uint8_t)((Qrow[j / 2] >> (4 * (j & 1))) & 15));
+}
+
+/*
+ * Dequantised MX GEMV reference: c_i += sum_j X_i,j/32 * P_ij * x_j in
+ * binary64, ascending j from +0.0, the initial c_i added last.  Each
+ * product has at most 4 + 24 significant bits times a power of two, so it
+ * is exact and only the sum rounds.
+ */
+int32_t orc_gemv_mx(int32_t q, int64_t m, int64_t n, const uint8_t* Q, int64_t ldq, const uint8_t* S,
+                    int64_t lds, const float* x, double* c)
+{
+    if (q != 4 && q != 5) return -1;
+    for (int64_t i = 0; i < m; ++i) {
+        double t = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double X = orc_e8m0_to_f64(S[i * lds + j / 32]);
+            const double p = X * mx_element(q, Q + i * ldq, j);
+            t += p * (double)x[j];
+        }
+        c[i] = c[i] + t;
+    }
+    return 0;
 }

@@ -504,3 +504,101 @@ def test_generators_deterministic():
     assert all(np.array_equal(p, q) for p, q in zip(a, b))
     A, _, _ = workloads.gemv_inputs(4, 6, seed=1, lda=9)
     assert A.shape == (4, 9) and np.isnan(A[:, 6:]).all()
+
+
+# ---------------------------------------------------------------- MX formats
+
+E2M1_SPEC = [0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0]   # OCP MX v1.0, FP4 E2M1 magnitudes
+
+
+def test_mx_element_and_scale_tables(orc):
+    for c in range(16):
+        v = orc.e2m1_to_f64(c)
+        assert abs(v) == E2M1_SPEC[c & 7] and (np.signbit(v) == bool(c & 8))
+    assert orc.e8m0_to_f64(127) == 1.0 and orc.e8m0_to_f64(0) == 2.0 ** -127
+    assert orc.e8m0_to_f64(254) == 2.0 ** 127 and np.isnan(orc.e8m0_to_f64(255))
+
+
+def test_e2m1_encode_nearest_even_saturating(orc):
+    ties = {0.25: 0, 0.75: 2, 1.25: 2, 1.75: 4, 2.5: 4, 3.5: 6, 5.0: 6}
+    for v, c in ties.items():
+        assert orc.e2m1_from_f64(v) == c and orc.e2m1_from_f64(-v) == c | 8
+    assert orc.e2m1_from_f64(6.5) == 7 and orc.e2m1_from_f64(1e30) == 7
+    assert orc.e2m1_from_f64(-0.0) == 8 and orc.e2m1_from_f64(0.1) == 0
+    rng = np.random.default_rng(11)
+    for v in rng.uniform(-7, 7, 2000):
+        c = orc.e2m1_from_f64(v)
+        d = abs(abs(v) - abs(orc.e2m1_to_f64(c)))
+        if abs(v) <= 6:
+            assert d <= min(abs(abs(v) - m) for m in E2M1_SPEC)   # a nearest value
+        else:
+            assert c & 7 == 7
+        assert bool(c & 8) == (v < 0)
+
+
+@pytest.mark.parametrize("q", [4, 5])
+def test_mx_quantize_scale_rule_and_roundtrip(orc, q):
+    """Every block's largest magnitude lands in the element format's top
+    binade (the scale is the largest power of two that does not push it past
+    2^(emax+1)), and every element is within half a unit of its binade, or
+    clipped at the largest finite value."""
+    emax, top, mbits = (8, 448.0, 3) if q == 4 else (2, 6.0, 1)
+    rng = np.random.default_rng(q)
+    m, n = 7, 32 * 9 + 5
+    mag = 2.0 ** rng.integers(-60, 60, (m, 1))
+    A = (rng.standard_normal((m, n)) * mag).astype(np.float32)
+    A[3, 32:64] = 0.0                                  # a block of zeros
+    A[4, 100] = np.nan                                 # a block with a NaN
+    A[5, :32] = np.float32(2.0 ** -140)                # subnormal binary32 block
+    codes, scales = orc.quantize_mx(A, q)
+    assert codes.shape == (m, n if q == 4 else (n + 1) // 2) and scales.shape == (m, 10)
+    for i in range(m):
+        for b in range(10):
+            blk = A[i, 32 * b:32 * b + 32].astype(np.float64)
+            code = int(scales[i, b])
+            if np.isnan(blk).any():
+                assert code == 255
+                continue
+            amax = np.abs(blk).max()
+            if amax == 0:
+                assert code == 0
+                continue
+            X = 2.0 ** (code - 127)
+            if 0 < code < 254:
+                assert 2.0 ** emax <= amax / X < 2.0 ** (emax + 1)
+            for j in range(blk.shape[0]):
+                jj = 32 * b + j
+                p = (orc.e4m3_to_f32(int(codes[i, jj])) if q == 4
+                     else orc.e2m1_to_f64(int(codes[i, jj // 2] >> (4 * (jj & 1))) & 15))
+                a = blk[j]
+                err = abs(a - X * p)
+                if abs(a) / X > top:
+                    assert X * abs(p) == X * top and err == abs(a) - X * top
+                else:
+                    # half a unit in the binade of a/X, or of the subnormal quantum
+                    e = max(np.floor(np.log2(abs(a) / X)) if a != 0 else -99, 1 - (7 if q == 4 else 1))
+                    assert err <= X * 2.0 ** (e - mbits - 1) * (1 + 1e-12)
+    if q == 5:
+        assert (codes[:, -1] >> 4 == 0).all()          # n odd: unused high nibble is 0
+
+
+@pytest.mark.parametrize("q", [4, 5])
+def test_gemv_mx_against_rationals(orc, q):
+    from fractions import Fraction
+    rng = np.random.default_rng(40 + q)
+    m, n = 3, 70
+    A = rng.standard_normal((m, n)).astype(np.float32) * np.float32(2.0 ** 5)
+    codes, scales = orc.quantize_mx(A, q)
+    x = rng.standard_normal(n).astype(np.float32)
+    c0 = rng.standard_normal(m)
+    c = orc.gemv_mx(codes, scales, x, c0, q, n)
+    for i in range(m):
+        ex, mag = Fraction(c0[i]), abs(c0[i])
+        for j in range(n):
+            X = Fraction(2) ** (int(scales[i, j // 32]) - 127)
+            p = (orc.e4m3_to_f32(int(codes[i, j])) if q == 4
+                 else orc.e2m1_to_f64(int(codes[i, j // 2] >> (4 * (j & 1))) & 15))
+            t = X * Fraction(p) * Fraction(float(x[j]))
+            ex += t
+            mag += abs(float(t))
+        assert abs(Fraction(c[i]) - ex) <= Fraction((n + 2) * 2.0 ** -53 * mag)
