@@ -43,6 +43,8 @@ KERNEL_SOURCES = {
     "gemv_q_bf16": ["quant.hip", "sb_rowdot.hpp", "sb_quant.hpp", "sb_device.hpp"],
     "gemv_q_e4m3": ["quant.hip", "sb_rowdot.hpp", "sb_quant.hpp", "sb_device.hpp"],
     "dot2_f32": ["dot.hip", "sb_device.hpp"],
+    "gemv_mx_fp8": ["mx.hip", "sb_quant.hpp", "sb_device.hpp"],
+    "gemv_mx_fp4": ["mx.hip", "sb_quant.hpp", "sb_device.hpp"],
 }
 
 
@@ -88,7 +90,8 @@ def build_ops(sb, torch, dev, sel):
     ops = []
     want = (lambda name: sel is None or name in sel)
     A = None
-    if any(want(k) for k in ("gemv_n_f64", "gemv_t_f64", "gemv2_f64", "gemv_q_bf16", "gemv_q_e4m3")):
+    if any(want(k) for k in ("gemv_n_f64", "gemv_t_f64", "gemv2_f64", "gemv_q_bf16", "gemv_q_e4m3", "gemv_mx_fp8",
+                             "gemv_mx_fp4")):
         log("drawing A 16384x16384 binary64")
         A = uni((M, N), 201)
     if want("gemv_n_f64"):
@@ -123,6 +126,19 @@ def build_ops(sb, torch, dev, sel):
         cq = torch.zeros(M, dtype=torch.float32, device=dev)
         ops.append((name, es * M * N + 4 * N + 8 * M + 4 * M, 2 * M * N,
                     (lambda Aq=Aq, s=s, xq=xq, cq=cq, q=q: sb.sb_gemv_q(Aq, s, xq, cq, q))))
+    for q, name, rb in ((sb.SB_MXFP8_E4M3, "gemv_mx_fp8", N), (sb.SB_MXFP4_E2M1, "gemv_mx_fp4", N // 2)):
+        if not want(name):
+            continue
+        log(f"MX-quantising A for {name} (untimed pre-step)")
+        A32 = A.float()
+        Q, S = sb.mx_buffers(q, M, N, dev)
+        sb.sb_quantize_mx(A32, Q, S, q)
+        del A32
+        g.manual_seed(402)
+        xm = torch.randn(N, generator=g, device=dev, dtype=torch.float32)
+        cm = torch.zeros(M, dtype=torch.float32, device=dev)
+        ops.append((name, M * rb + M * (N // 32) + 4 * N + 8 * M, 2 * M * N,
+                    (lambda Q=Q, S=S, xm=xm, cm=cm, q=q: sb.sb_gemv_mx(Q, S, xm, cm, q))))
     if want("dot2_f32"):
         log("generating ill-conditioned pairs n=2^27 (cond 1e8)")
         import workloads
@@ -318,8 +334,9 @@ def main():
             (per["gemv_n_f64"]["us"] + per["gemv_t_f64"]["us"]) / per["gemv2_f64"]["us"], 3)
     if "gemv_n_f64" in per and "gemv_q_bf16" in per:
         extras["bf16_over_f64_flops"] = round(per["gemv_q_bf16"]["TFLOP/s"] / per["gemv_n_f64"]["TFLOP/s"], 3)
-    if "gemv_n_f64" in per and "gemv_q_e4m3" in per:
-        extras["e4m3_over_f64_flops"] = round(per["gemv_q_e4m3"]["TFLOP/s"] / per["gemv_n_f64"]["TFLOP/s"], 3)
+    for k, label in (("gemv_q_e4m3", "e4m3"), ("gemv_mx_fp8", "mxfp8"), ("gemv_mx_fp4", "mxfp4")):
+        if "gemv_n_f64" in per and k in per:
+            extras[f"{label}_over_f64_flops"] = round(per[k]["TFLOP/s"] / per["gemv_n_f64"]["TFLOP/s"], 3)
 
     out = {
         "metric": "GEMV HBM GB/s & % of peak, FP64 vs BF16-A; batched p50/p99 latency",
@@ -327,7 +344,8 @@ def main():
         "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": "fp64 gemv N/T and two-sided 16384x16384, dot n=2^28, ger 16384x16384; "
-                               "bf16-A and e4m3-A gemv 16384x16384 (f32 x, c); dot2 f32 n=2^27 cond 1e8",
+                               "bf16-A and e4m3-A (row scales), mxfp8-A and mxfp4-A (32-element block scales) "
+                               "gemv 16384x16384 (f32 x, c); dot2 f32 n=2^27 cond 1e8",
                    "ops": names, "parallelism": "single GPU"},
         "roofline": roof, "ops": per, **extras,
     }

@@ -47,13 +47,14 @@ typedef int32_t sb_status;
 #define SB_EUNSUPPORTED (-4)  /* valid arguments, combination not implemented */
 #define SB_EINTERNAL (-5)     /* unexpected internal failure */
 
-typedef enum { SB_F64 = 0, SB_F32 = 1, SB_BF16 = 2, SB_FP8_E4M3 = 3 } sb_dtype;
+typedef enum { SB_F64 = 0, SB_F32 = 1, SB_BF16 = 2, SB_FP8_E4M3 = 3, SB_MXFP8_E4M3 = 4,
+               SB_MXFP4_E2M1 = 5 } sb_dtype;
 typedef enum { SB_ROW_MAJOR = 0, SB_COL_MAJOR = 1 } sb_layout;
 typedef enum { SB_N = 0, SB_T = 1 } sb_op;
 
 /* Operation kinds, for sb_workspace_bytes. */
 typedef enum { SB_KIND_GEMV = 0, SB_KIND_DOT = 1, SB_KIND_GER = 2, SB_KIND_GEMV_Q = 3,
-               SB_KIND_DOT2 = 4, SB_KIND_PROBE_READ = 5, SB_KIND_GEMV2 = 6 } sb_kind;
+               SB_KIND_DOT2 = 4, SB_KIND_PROBE_READ = 5, SB_KIND_GEMV2 = 6, SB_KIND_GEMV_MX = 7 } sb_kind;
 
 typedef struct sb_handle sb_handle;
 
@@ -206,6 +207,40 @@ sb_status sb_quantize_rows(sb_handle* handle, sb_dtype q, int64_t m, int64_t n,
  */
 sb_status sb_gemv_q(sb_handle* handle, sb_dtype q, int64_t m, int64_t n, const void* Aq,
                     int64_t ldq, const float* scales, const float* x, float* c);
+
+/*
+ * Microscaled storage of A (OCP Microscaling Formats v1.0; the paper's
+ * element size S_data is generic and its GEMV bound by the bytes of A,
+ * sections 4.1 and 4.3).  Each row is cut into blocks of 32 consecutive
+ * elements (the last one may be shorter); a block has one E8M0 scale byte,
+ * X = 2^(code - 127) (code 255 is NaN), and element codes P_j:
+ *   q = SB_MXFP8_E4M3: OCP E4M3 codes, one byte per element;
+ *   q = SB_MXFP4_E2M1: OCP E2M1 codes (magnitudes 0, .5, 1, 1.5, 2, 3, 4, 6),
+ *                      element 2k in the low nibble of byte k of the row, an
+ *                      unused last high nibble 0.
+ * Element j of row i decodes to X_i,j/32 * P_ij.
+ * Layout: Q row-major with ldq bytes per row (ldq >= the row's code bytes
+ * and a multiple of 16; Q 16-byte aligned); S row-major, lds >= ceil(n/32)
+ * scale bytes per row.  Both are device memory owned by the caller.
+ *
+ * sb_quantize_mx: codes and scales of the binary32 m x n matrix A (lda):
+ * per block, code = clamp(floor(log2 amax) - emax + 127, 0, 254) with emax
+ * = 8 (E4M3) or 2 (E2M1), 0 for an all-zero block, 255 (and element codes
+ * 0) for a block holding a NaN or infinity; P_j = a_j / X rounded to
+ * nearest even and saturated to the largest finite element value.  A, Q and
+ * S must not overlap.
+ *
+ * sb_gemv_mx: c += (X * P) x with x (n entries) and c (m entries) binary32,
+ * products and sums in binary32 (each block's partial sum scaled by its X).
+ * c must not overlap Q, S or x.  Needs sb_workspace_bytes of kind
+ * SB_KIND_GEMV_MX (dtype q) when rows are longer than 32768 elements.
+ * Both return SB_EINVAL for other q, strides below the minimum or a
+ * misaligned Q, and SB_OK without launching when m or n is 0.
+ */
+sb_status sb_quantize_mx(sb_handle* handle, sb_dtype q, int64_t m, int64_t n, const float* A, int64_t lda,
+                         void* Q, int64_t ldq, uint8_t* S, int64_t lds);
+sb_status sb_gemv_mx(sb_handle* handle, sb_dtype q, int64_t m, int64_t n, const void* Q, int64_t ldq,
+                     const uint8_t* S, int64_t lds, const float* x, float* c);
 
 /*
  * Compensated DOT in binary32: *alpha += x . y evaluated with error-free

@@ -28,14 +28,15 @@ __all__ = [
     "sb_stream_read", "sb_stream_copy", "sb_gemv_desc", "GemvProblem", "make_descs", "sb_gemv_batched",
     "sb_gemv_batched_resolve", "sb_gemv_batched_table_bytes", "BatchTable", "sb_fill_uniform",
     "SB_CUTOFF_DOT_SMALL_BYTES", "SB_CUTOFF_GEMV_T_SMALL_SPLITS", "sb_set_cutoff", "sb_get_cutoff",
+    "SB_MXFP8_E4M3", "SB_MXFP4_E2M1", "SB_KIND_GEMV_MX", "mx_buffers", "sb_quantize_mx", "sb_gemv_mx",
 ]
 
 SB_OK, SB_EINVAL, SB_ENOMEM, SB_EDEVICE, SB_EUNSUPPORTED, SB_EINTERNAL = 0, -1, -2, -3, -4, -5
-SB_F64, SB_F32, SB_BF16, SB_FP8_E4M3 = 0, 1, 2, 3
+SB_F64, SB_F32, SB_BF16, SB_FP8_E4M3, SB_MXFP8_E4M3, SB_MXFP4_E2M1 = 0, 1, 2, 3, 4, 5
 SB_ROW_MAJOR, SB_COL_MAJOR = 0, 1
 SB_N, SB_T = 0, 1
 SB_KIND_GEMV, SB_KIND_DOT, SB_KIND_GER, SB_KIND_GEMV_Q, SB_KIND_DOT2, SB_KIND_PROBE_READ = 0, 1, 2, 3, 4, 5
-SB_KIND_GEMV2 = 6
+SB_KIND_GEMV2, SB_KIND_GEMV_MX = 6, 7
 SB_CUTOFF_DOT_SMALL_BYTES, SB_CUTOFF_GEMV_T_SMALL_SPLITS = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -89,6 +90,8 @@ def load():
     L.sb_quantize_rows.argtypes = [P, I32, I64, I64, P, I64, P, I64, P]
     L.sb_gemv_q.argtypes = [P, I32, I64, I64, P, I64, P, P, P]
     L.sb_dot2_f32.argtypes = [P, I64, P, P, P]
+    L.sb_quantize_mx.argtypes = [P, I32, I64, I64, P, I64, P, I64, P, I64]
+    L.sb_gemv_mx.argtypes = [P, I32, I64, I64, P, I64, P, I64, P, P]
     L.sb_gemv_batched_table_bytes.argtypes = [ctypes.POINTER(sb_gemv_desc), I32, ctypes.POINTER(SZ)]
     L.sb_gemv_batched_table_bytes.restype = SZ
     L.sb_gemv_batched_resolve.argtypes = [ctypes.POINTER(sb_gemv_desc), I32, ctypes.POINTER(sb_gemv_desc)]
@@ -103,7 +106,7 @@ def load():
     L.sb_stream_copy.argtypes = [P, P, P, SZ]
     for f in ("sb_fill_uniform", "sb_generate_batched", "sb_gemv_batched_resolve", "sb_gemv_batched_encode", "sb_gemv_batched_run", "sb_gemv_batched",
               "sb_stream_read", "sb_stream_copy", "sb_handle_create", "sb_handle_destroy", "sb_set_stream", "sb_set_workspace", "sb_set_cutoff", "sb_get_cutoff", "sb_gemv", "sb_gemv2",
-              "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32"):
+              "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32", "sb_quantize_mx", "sb_gemv_mx"):
         getattr(L, f).restype = I32
     _lib = L
     return L
@@ -335,6 +338,64 @@ def sb_gemv_q(Aq: torch.Tensor, scales: torch.Tensor, x: torch.Tensor, c: torch.
     h = handle_for(Aq)
     h.prepare(sb_workspace_bytes(SB_KIND_GEMV_Q, q, 0, 0, m, n, h))
     h.check(load().sb_gemv_q(h.h, q, m, n, _ptr(Aq), ldq, _ptr(scales), _ptr(x), _ptr(c)))
+    return c
+
+
+def mx_row_bytes(q: int, n: int) -> int:
+    """Bytes of element codes in one row of an MX matrix with n columns."""
+    return n if q == SB_MXFP8_E4M3 else (n + 1) // 2
+
+
+def mx_buffers(q: int, m: int, n: int, device=None):
+    """Uninitialised (Q, S) device tensors for an m x n MX matrix: Q is
+    m x ldq bytes with ldq the row's code bytes rounded up to 16, S is
+    m x ceil(n/32) scale bytes."""
+    if q not in (SB_MXFP8_E4M3, SB_MXFP4_E2M1):
+        raise ValueError("q must be SB_MXFP8_E4M3 or SB_MXFP4_E2M1")
+    ldq = max(16, (mx_row_bytes(q, n) + 15) // 16 * 16)
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    return (torch.empty((m, ldq), dtype=torch.uint8, device=dev),
+            torch.empty((m, max(1, (n + 31) // 32)), dtype=torch.uint8, device=dev))
+
+
+def _mx_check(Q: torch.Tensor, S: torch.Tensor, q: int, m: int, n: int):
+    if Q.dtype != torch.uint8 or S.dtype != torch.uint8 or Q.dim() != 2 or S.dim() != 2:
+        raise TypeError("Q and S must be 2-D uint8 tensors")
+    if q not in (SB_MXFP8_E4M3, SB_MXFP4_E2M1):
+        raise ValueError("q must be SB_MXFP8_E4M3 or SB_MXFP4_E2M1")
+    if Q.shape[0] != m or S.shape[0] != m or Q.shape[1] < mx_row_bytes(q, n) or S.shape[1] < (n + 31) // 32:
+        raise ValueError("Q or S too small for the matrix")
+    if (m > 1 and (Q.stride(1) != 1 or S.stride(1) != 1)):
+        raise ValueError("Q and S rows must be contiguous")
+
+
+def sb_quantize_mx(A: torch.Tensor, Q: torch.Tensor, S: torch.Tensor, q: int):
+    """MX quantisation of a row-major binary32 A into codes Q and scales S."""
+    _device_check(A, Q, S)
+    if A.dtype != torch.float32:
+        raise TypeError("A must be float32")
+    la, lda = _matrix_layout(A)
+    if la != SB_ROW_MAJOR:
+        raise ValueError("A must be row-major")
+    m, n = A.shape
+    _mx_check(Q, S, q, m, n)
+    h = handle_for(A)
+    h.prepare(0)
+    h.check(load().sb_quantize_mx(h.h, q, m, n, _ptr(A), lda, _ptr(Q), Q.stride(0), _ptr(S), S.stride(0)))
+    return Q, S
+
+
+def sb_gemv_mx(Q: torch.Tensor, S: torch.Tensor, x: torch.Tensor, c: torch.Tensor, q: int) -> torch.Tensor:
+    """c += (X * P) x in place for the MX matrix (Q, S) with x.numel() columns."""
+    _device_check(Q, S, x, c)
+    _vec(x), _vec(c)
+    if x.dtype != torch.float32 or c.dtype != torch.float32:
+        raise TypeError("x and c must be float32")
+    m, n = c.numel(), x.numel()
+    _mx_check(Q, S, q, m, n)
+    h = handle_for(Q)
+    h.prepare(sb_workspace_bytes(SB_KIND_GEMV_MX, q, 0, 0, m, n, h))
+    h.check(load().sb_gemv_mx(h.h, q, m, n, _ptr(Q), Q.stride(0), _ptr(S), S.stride(0), _ptr(x), _ptr(c)))
     return c
 
 

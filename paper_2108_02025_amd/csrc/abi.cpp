@@ -31,6 +31,8 @@ int esize_of(sb_dtype dt)
     case SB_F32: return 4;
     case SB_BF16: return 2;
     case SB_FP8_E4M3: return 1;
+    case SB_MXFP8_E4M3:
+    case SB_MXFP4_E2M1: return 0;  // block-scaled codes: sizes come from mx_row_bytes
     }
     return 0;
 }
@@ -56,6 +58,18 @@ Range range_of(const void* p, int64_t elems, int es)
 }
 
 bool overlap(Range a, Range b) { return a.lo < a.hi && b.lo < b.hi && a.lo < b.hi && b.lo < a.hi; }
+
+// Storage-only element types: GEMV, DOT and GER compute in binary64 or
+// binary32; narrow codes go through the quantised and MX entry points.
+bool narrow(sb_dtype dt)
+{
+    return dt == SB_BF16 || dt == SB_FP8_E4M3 || dt == SB_MXFP8_E4M3 || dt == SB_MXFP4_E2M1;
+}
+
+bool is_mx(sb_dtype q) { return q == SB_MXFP8_E4M3 || q == SB_MXFP4_E2M1; }
+
+// Bytes of one row of MX element codes: n (E4M3) or ceil(n/2) (E2M1).
+int64_t mx_row_bytes(sb_dtype q, int64_t n) { return q == SB_MXFP8_E4M3 ? n : (n + 1) / 2; }
 
 bool misaligned(const void* p, int es) { return (reinterpret_cast<uintptr_t>(p) % (uintptr_t)es) != 0; }
 
@@ -185,6 +199,9 @@ size_t sb_workspace_bytes(const sb_handle* handle, sb_kind kind, sb_dtype dtype,
         const bool row_dot = (layout == SB_ROW_MAJOR) == (op == SB_N);
         return row_dot ? sb::plan_gemv_n(es, rows, cols).ws : sb::plan_gemv_t(es, rows, cols, t_small).ws;
     }
+    case SB_KIND_GEMV_MX:
+        if (!is_mx(dtype)) return bad;
+        return (m == 0 || n == 0) ? 0 : sb::gemv_mx_ws_bytes(dtype, m, n);
     case SB_KIND_GEMV2: {
         if (dtype != SB_F64 && dtype != SB_F32) return bad;
         if (layout != SB_ROW_MAJOR && layout != SB_COL_MAJOR) return bad;
@@ -213,7 +230,7 @@ sb_status sb_gemv(sb_handle* handle, sb_dtype dtype, sb_layout layout, sb_op op,
 {
     if (!handle) return fail(nullptr, SB_EINVAL, "sb_gemv: NULL handle");
     SB_GUARD_BEGIN
-    if (dtype == SB_BF16 || dtype == SB_FP8_E4M3)
+    if (narrow(dtype))
         return fail(handle, SB_EUNSUPPORTED, "sb_gemv: narrow storage needs sb_gemv_q");
     if (dtype != SB_F64 && dtype != SB_F32) return fail(handle, SB_EINVAL, "sb_gemv: bad dtype %d", (int)dtype);
     if (layout != SB_ROW_MAJOR && layout != SB_COL_MAJOR) return fail(handle, SB_EINVAL, "sb_gemv: bad layout %d", (int)layout);
@@ -248,7 +265,7 @@ sb_status sb_gemv2(sb_handle* handle, sb_dtype dtype, sb_layout layout, int64_t 
 {
     if (!handle) return fail(nullptr, SB_EINVAL, "sb_gemv2: NULL handle");
     SB_GUARD_BEGIN
-    if (dtype == SB_BF16 || dtype == SB_FP8_E4M3) return fail(handle, SB_EUNSUPPORTED, "sb_gemv2: narrow dtype");
+    if (narrow(dtype)) return fail(handle, SB_EUNSUPPORTED, "sb_gemv2: narrow dtype");
     if (dtype != SB_F64 && dtype != SB_F32) return fail(handle, SB_EINVAL, "sb_gemv2: bad dtype %d", (int)dtype);
     if (layout != SB_ROW_MAJOR && layout != SB_COL_MAJOR) return fail(handle, SB_EINVAL, "sb_gemv2: bad layout %d", (int)layout);
     if (m < 0 || n < 0) return fail(handle, SB_EINVAL, "sb_gemv2: negative size m=%lld n=%lld", (long long)m, (long long)n);
@@ -279,7 +296,7 @@ sb_status sb_dot(sb_handle* handle, sb_dtype dtype, int64_t n, const void* x, co
 {
     if (!handle) return fail(nullptr, SB_EINVAL, "sb_dot: NULL handle");
     SB_GUARD_BEGIN
-    if (dtype == SB_BF16 || dtype == SB_FP8_E4M3) return fail(handle, SB_EUNSUPPORTED, "sb_dot: narrow dtype");
+    if (narrow(dtype)) return fail(handle, SB_EUNSUPPORTED, "sb_dot: narrow dtype");
     if (dtype != SB_F64 && dtype != SB_F32) return fail(handle, SB_EINVAL, "sb_dot: bad dtype %d", (int)dtype);
     if (n < 0) return fail(handle, SB_EINVAL, "sb_dot: negative n=%lld", (long long)n);
     const int es = esize_of(dtype);
@@ -300,7 +317,7 @@ sb_status sb_ger(sb_handle* handle, sb_dtype dtype, sb_layout layout, int64_t m,
 {
     if (!handle) return fail(nullptr, SB_EINVAL, "sb_ger: NULL handle");
     SB_GUARD_BEGIN
-    if (dtype == SB_BF16 || dtype == SB_FP8_E4M3) return fail(handle, SB_EUNSUPPORTED, "sb_ger: narrow dtype");
+    if (narrow(dtype)) return fail(handle, SB_EUNSUPPORTED, "sb_ger: narrow dtype");
     if (dtype != SB_F64 && dtype != SB_F32) return fail(handle, SB_EINVAL, "sb_ger: bad dtype %d", (int)dtype);
     if (layout != SB_ROW_MAJOR && layout != SB_COL_MAJOR) return fail(handle, SB_EINVAL, "sb_ger: bad layout %d", (int)layout);
     if (m < 0 || n < 0) return fail(handle, SB_EINVAL, "sb_ger: negative size");
@@ -366,6 +383,66 @@ sb_status sb_gemv_q(sb_handle* handle, sb_dtype q, int64_t m, int64_t n, const v
     if (overlap(rc, range_of(Aq, q_el, qs)) || overlap(rc, range_of(scales, m, 4)) || overlap(rc, range_of(x, n, 4)))
         return fail(handle, SB_EINVAL, "sb_gemv_q: c overlaps an input");
     return sb::run_gemv_q(handle, q, m, n, Aq, ldq, scales, x, c);
+    SB_GUARD_END
+}
+
+// Checks shared by the MX quantiser and GEMV: sizes, strides, extents.
+static sb_status mx_layout_check(sb_handle* handle, const char* what, sb_dtype q, int64_t m, int64_t n, int64_t ldq,
+                                 int64_t lds, int64_t* q_bytes, int64_t* s_bytes)
+{
+    if (!is_mx(q)) return fail(handle, SB_EINVAL, "%s: q must be MXFP8_E4M3 or MXFP4_E2M1", what);
+    if (m < 0 || n < 0) return fail(handle, SB_EINVAL, "%s: negative size", what);
+    const int64_t rb = mx_row_bytes(q, n), nb = (n + 31) / 32;
+    if (ldq < (rb > 1 ? rb : 1) || ldq % 16 != 0)
+        return fail(handle, SB_EINVAL, "%s: ldq=%lld must cover a row (%lld bytes) and be a multiple of 16", what,
+                    (long long)ldq, (long long)rb);
+    if (lds < (nb > 1 ? nb : 1)) return fail(handle, SB_EINVAL, "%s: lds=%lld below %lld blocks", what, (long long)lds, (long long)nb);
+    *q_bytes = span_elems(m, rb, ldq);
+    *s_bytes = span_elems(m, nb, lds);
+    if (*q_bytes < 0 || *s_bytes < 0 || *q_bytes > kMaxBytes || *s_bytes > kMaxBytes)
+        return fail(handle, SB_EINVAL, "%s: extent overflows", what);
+    return SB_OK;
+}
+
+sb_status sb_quantize_mx(sb_handle* handle, sb_dtype q, int64_t m, int64_t n, const float* A, int64_t lda, void* Q,
+                         int64_t ldq, uint8_t* S, int64_t lds)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_quantize_mx: NULL handle");
+    SB_GUARD_BEGIN
+    int64_t qb, sbytes;
+    sb_status st = mx_layout_check(handle, "sb_quantize_mx", q, m, n, ldq, lds, &qb, &sbytes);
+    if (st != SB_OK) return st;
+    if (lda < (n > 1 ? n : 1)) return fail(handle, SB_EINVAL, "sb_quantize_mx: lda below n");
+    const int64_t a_el = span_elems(m, n, lda);
+    int64_t t;
+    if (a_el < 0 || !mul_ok(a_el, 4, &t) || t > kMaxBytes) return fail(handle, SB_EINVAL, "sb_quantize_mx: extent overflows");
+    if (m == 0 || n == 0) return SB_OK;
+    if (!A || !Q || !S) return fail(handle, SB_EINVAL, "sb_quantize_mx: NULL pointer");
+    if (misaligned(A, 4) || (reinterpret_cast<uintptr_t>(Q) & 15u) != 0)
+        return fail(handle, SB_EINVAL, "sb_quantize_mx: A must be 4-byte and Q 16-byte aligned");
+    const Range ra = range_of(A, a_el, 4), rq = range_of(Q, qb, 1), rs = range_of(S, sbytes, 1);
+    if (overlap(ra, rq) || overlap(ra, rs) || overlap(rq, rs))
+        return fail(handle, SB_EINVAL, "sb_quantize_mx: A, Q and S must not overlap");
+    return sb::run_quantize_mx(handle, q, m, n, A, lda, Q, ldq, S, lds);
+    SB_GUARD_END
+}
+
+sb_status sb_gemv_mx(sb_handle* handle, sb_dtype q, int64_t m, int64_t n, const void* Q, int64_t ldq,
+                     const uint8_t* S, int64_t lds, const float* x, float* c)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_gemv_mx: NULL handle");
+    SB_GUARD_BEGIN
+    int64_t qb, sbytes;
+    sb_status st = mx_layout_check(handle, "sb_gemv_mx", q, m, n, ldq, lds, &qb, &sbytes);
+    if (st != SB_OK) return st;
+    if (m == 0 || n == 0) return SB_OK;
+    if (!Q || !S || !x || !c) return fail(handle, SB_EINVAL, "sb_gemv_mx: NULL pointer");
+    if ((reinterpret_cast<uintptr_t>(Q) & 15u) != 0 || misaligned(x, 4) || misaligned(c, 4))
+        return fail(handle, SB_EINVAL, "sb_gemv_mx: Q must be 16-byte and x, c 4-byte aligned");
+    const Range rc = range_of(c, m, 4);
+    if (overlap(rc, range_of(Q, qb, 1)) || overlap(rc, range_of(S, sbytes, 1)) || overlap(rc, range_of(x, n, 4)))
+        return fail(handle, SB_EINVAL, "sb_gemv_mx: c overlaps an input");
+    return sb::run_gemv_mx(handle, q, m, n, Q, ldq, S, lds, x, c);
     SB_GUARD_END
 }
 

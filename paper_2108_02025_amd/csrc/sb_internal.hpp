@@ -97,6 +97,11 @@ sb_status run_quantize_rows(sb_handle* h, sb_dtype q, int64_t m, int64_t n, cons
 sb_status run_gemv_q(sb_handle* h, sb_dtype q, int64_t m, int64_t n, const void* Aq, int64_t ldq,
                      const float* scales, const float* x, float* c);
 size_t gemv_q_ws_bytes(sb_dtype q, int64_t m, int64_t n);
+sb_status run_quantize_mx(sb_handle* h, sb_dtype q, int64_t m, int64_t n, const float* A, int64_t lda, void* Q,
+                          int64_t ldq, uint8_t* S, int64_t lds);
+sb_status run_gemv_mx(sb_handle* h, sb_dtype q, int64_t m, int64_t n, const void* Q, int64_t ldq, const uint8_t* S,
+                      int64_t lds, const float* x, float* c);
+size_t gemv_mx_ws_bytes(sb_dtype q, int64_t m, int64_t n);
 
 // ---- operand generation ---------------------------------------------------
 sb_status run_fill_uniform(sb_handle* h, sb_dtype dt, void* out, int64_t count, uint64_t seed, uint64_t counter0);

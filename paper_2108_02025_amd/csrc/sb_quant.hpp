@@ -67,4 +67,34 @@ __device__ __forceinline__ float row_scale(bool bf16, float amax)
     return s == 0.0f ? 1.0f : s;
 }
 
+// ------------------------------------------------------------ MX formats ---
+// OCP Microscaling: blocks of 32 elements share an E8M0 scale 2^(code-127).
+
+// binary32 -> OCP E2M1 (FP4; magnitudes 0, 0.5, 1, 1.5, 2, 3, 4, 6, no NaN
+// or infinity): the code counts the rounding boundaries that |v| passes.  A
+// value on a boundary is a tie and goes to the even code, so the test is
+// ">=" where the code above is even and ">" where it is odd; past 5 the
+// magnitude saturates to 6.  The sign bit is kept.
+__device__ __forceinline__ uint8_t e2m1_encode(float v)
+{
+    const float a = fabsf(v);
+    const uint32_t code = (uint32_t)(a > 0.25f) + (uint32_t)(a >= 0.75f) + (uint32_t)(a > 1.25f) +
+                          (uint32_t)(a >= 1.75f) + (uint32_t)(a > 2.5f) + (uint32_t)(a >= 3.5f) +
+                          (uint32_t)(a > 5.0f);
+    return (uint8_t)(((f32_bits(v) >> 28) & 8u) | code);
+}
+
+// E8M0 code of a block whose largest magnitude is the finite amax:
+// floor(log2 amax) - emax + 127, clamped to [0, 254]; 0 when amax is 0.
+// emax is the exponent of the element format's largest value (8 for E4M3,
+// 2 for E2M1), so amax / 2^(code-127) lands in [2^emax, 2^(emax+1)).
+__device__ __forceinline__ int mx_scale_code(float amax, int emax)
+{
+    const uint32_t a = f32_bits(amax);
+    if (a == 0u) return 0;
+    // normal: the exponent field; subnormal (a * 2^-149): the top set bit
+    const int e = a >= 0x00800000u ? (int)(a >> 23) - 127 : -118 - __clz((int)a);
+    return min(max(e - emax + 127, 0), 254);
+}
+
 }  // namespace sb

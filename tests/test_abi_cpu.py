@@ -132,7 +132,7 @@ def test_gemv2_validation_and_workspace(L, h):
     def g2(dt=0, layout=0, m=10, n=12, A=A_, lda=12, x=X_, y=Y_, c=C_, d=D_):
         return L.sb_gemv2(h, dt, layout, m, n, A, lda, x, y, c, d)
     assert L.sb_gemv2(None, 0, 0, 1, 1, A_, 1, X_, Y_, C_, D_) == -1
-    assert g2(dt=2) == -4 and g2(dt=5) == -1 and g2(layout=3) == -1
+    assert g2(dt=2) == -4 and g2(dt=5) == -4 and g2(dt=9) == -1 and g2(layout=3) == -1
     assert g2(m=-1) == -1 and g2(lda=11) == -1 and g2(layout=1, lda=9) == -1
     assert g2(A=None) == -1 and g2(y=None) == -1 and g2(d=None) == -1
     assert g2(d=A_ + 8) == -1                      # d inside A
@@ -147,6 +147,30 @@ def test_gemv2_validation_and_workspace(L, h):
     assert ws(None, 6, 0, 1, 0, 16384, 16384) == ws(None, 6, 0, 0, 0, 16384, 16384)
     assert ws(None, 6, 0, 0, 0, 64, 64) == 0       # one band each way: direct update
     assert ws(None, 6, 2, 0, 0, 64, 64) == (1 << 64) - 1
+
+
+def test_mx_validation_and_workspace(L, h):
+    S_ = FAKE + (5 << 36)
+    qz = L.sb_quantize_mx
+    assert qz(h, 3, 4, 64, A_, 64, C_, 64, S_, 2) == -1      # not an MX type
+    assert qz(h, 4, 4, 64, A_, 63, C_, 64, S_, 2) == -1      # lda < n
+    assert qz(h, 4, 4, 64, A_, 64, C_, 48, S_, 2) == -1      # ldq below the row bytes
+    assert qz(h, 5, 4, 64, A_, 64, C_, 40, S_, 2) == -1      # ldq not a multiple of 16
+    assert qz(h, 5, 4, 64, A_, 64, C_, 32, S_, 1) == -1      # lds below ceil(n/32)
+    assert qz(h, 5, 4, 64, A_, 64, C_ + 8, 32, S_, 2) == -1  # Q not 16-byte aligned
+    assert qz(h, 4, 4, 64, A_, 64, A_ + 64, 64, S_, 2) == -1  # Q overlaps A
+    assert qz(h, 4, 0, 64, None, 64, None, 64, None, 2) == 0
+    gm = L.sb_gemv_mx
+    assert gm(h, 2, 4, 64, C_, 64, S_, 2, X_, A_) == -1
+    assert gm(h, 4, 4, 64, C_, 64, S_, 2, X_, S_ + 2) == -1   # c overlaps S
+    assert gm(h, 5, 4, 64, C_, 32, S_, 2, None, A_) == -1
+    assert gm(h, 5, 4, 0, None, 16, None, 1, None, A_) == 0   # empty rows: c unchanged
+    # rows of 40000 binary32 x values are split in 8192-column chunks
+    assert L.sb_workspace_bytes(None, 7, 4, 0, 0, 1000, 40000) == 5 * 1000 * 4
+    assert L.sb_workspace_bytes(None, 7, 5, 0, 0, 1000, 16384) == 0
+    assert L.sb_workspace_bytes(None, 7, 3, 0, 0, 1000, 100) == (1 << 64) - 1
+    assert gm(h, 4, 1000, 40000, C_, 40000, S_, 1250, X_, A_) == -2   # no workspace
+    assert L.sb_gemv(h, 4, 0, 0, 4, 4, A_, 4, X_, C_) == -4          # MX types are storage only
 
 
 def test_dot_ger_quant_validation(L, h):
