@@ -8,9 +8,10 @@ c binary32) arrive on a trace.  The host loop:
   2. admits the queue head when its operands fit the HBM budget (a first-fit
      pool carved from one device buffer); admission never skips the head, so
      no request starves;
-  3. materialises the operands on the device, on a generation stream: A and
-     x from SplitMix64 counters (seeded per request), c zeroed; bfloat16
-     requests are quantised per row right away;
+  3. materialises the operands of every request admitted in a round with
+     one launch of the batched generator on a generation stream: A and x
+     from SplitMix64 counters (seeded per request), c zeroed, bfloat16 rows
+     scaled and encoded in the same kernel;
   4. whenever fewer than `max_inflight` batches are on the GPU, packs every
      materialised request into the next batch, writes its table and replays
      a captured launch of the batched persistent kernel (one HIP graph per
