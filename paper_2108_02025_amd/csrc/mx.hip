@@ -41,6 +41,12 @@
 #ifndef SB_GEMVMX_WAVES_PER_CU
 #define SB_GEMVMX_WAVES_PER_CU 32
 #endif
+#ifndef SB_GEMVMX_NT_BIG
+#define SB_GEMVMX_NT_BIG 512
+#endif
+#ifndef SB_GEMVMX_STAGE_MAX
+#define SB_GEMVMX_STAGE_MAX (128 * 1024)
+#endif
 
 namespace sb {
 
@@ -265,7 +271,7 @@ static GemvMxPlan plan_gemv_mx(bool fp4, int64_t m, int64_t n)
 {
     GemvMxPlan p{};
     const int64_t P = fp4 ? 32 : 16;
-    if (n * 4 <= 128 * 1024) {
+    if (n * 4 <= SB_GEMVMX_STAGE_MAX) {
         p.nsplit = 1;
         p.KC = std::max<int64_t>(round_up(n, 4), 4);
     } else {
@@ -273,7 +279,7 @@ static GemvMxPlan plan_gemv_mx(bool fp4, int64_t m, int64_t n)
         p.nsplit = ceil_div(n, p.KC);
     }
     p.lds = (size_t)(round_up(p.KC, P) * 4);  // chunk-major x: whole vectors
-    p.NT = p.lds > 80 * 1024 ? 1024 : (p.lds > 40 * 1024 ? 512 : 256);
+    p.NT = p.lds > 80 * 1024 ? 1024 : (p.lds > 40 * 1024 ? SB_GEMVMX_NT_BIG : 256);
     const int64_t wpb = p.NT / 64;
     const int64_t bpc =
         std::max<int64_t>(1, std::min<int64_t>((160 * 1024) / (int64_t)p.lds, SB_GEMVMX_WAVES_PER_CU / wpb));
