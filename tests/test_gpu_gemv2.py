@@ -129,3 +129,31 @@ def test_gemv2_full_sizes(sb, m, n):
     c, d = run(sb, A, x, y, c0, d0, 0)
     assert_within(c, cref, gemv_bound(A, x, c0, 0, n, U64), "full c")
     assert_within(d, dref, gemv_bound(A, y, d0, 1, m, U64), "full d")
+
+
+def test_gemv2_specials_propagate(sb):
+    """NaN and infinity reach exactly the outputs whose sums contain them,
+    as in the oracle: entries of A poison one row sum and one column sum;
+    an infinite x entry every row sum, a NaN y entry every column sum."""
+    m, n = 300, 500
+    A, x, y, c0, d0 = inputs(m, n, 77, "normal", np.float64)
+    A[10, 20] = np.nan
+    A[30, 40] = np.inf
+
+    def same_specials(got, ref):
+        assert np.array_equal(np.isnan(got), np.isnan(ref))
+        assert np.array_equal(np.isposinf(got), np.isposinf(ref))
+        assert np.array_equal(np.isneginf(got), np.isneginf(ref))
+
+    cref, dref = oracle.gemv2(A, x, y, c0, d0)
+    for layout in (0, 1):
+        c, d = run(sb, A, x, y, c0, d0, layout)
+        same_specials(c, cref)
+        same_specials(d, dref)
+        assert np.isfinite(cref).sum() == m - 2 and np.isfinite(dref).sum() == n - 2
+    x2, y2 = x.copy(), y.copy()
+    x2[100], y2[200] = -np.inf, np.nan
+    cref, dref = oracle.gemv2(A, x2, y2, c0, d0)
+    c, d = run(sb, A, x2, y2, c0, d0, 0)
+    same_specials(c, cref)
+    same_specials(d, dref)

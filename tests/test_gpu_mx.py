@@ -188,3 +188,30 @@ def test_mx_full_size(sb, q):
     err = normwise(got, exact)
     print(f"q={q}: normwise error against the binary64 GEMV of A: {err:.3e}")
     assert err < (0.04 if q == 4 else 0.15)
+
+
+@pytest.mark.parametrize("q", QS)
+def test_mx_padded_strides_and_specials(sb, q):
+    """A read through a padded leading dimension into padded Q and S rows;
+    an infinite x entry and a NaN in A propagate as in the oracle."""
+    m, n, lda = 37, 1001, 1040
+    rng = np.random.default_rng(70 + q)
+    store = np.full((m, lda), np.nan, dtype=np.float32)
+    store[:, :n] = rng.standard_normal((m, n)).astype(np.float32)
+    A = np.ascontiguousarray(store[:, :n])
+    codes, scales = oracle.quantize_mx(A, q)
+    Q = torch.zeros((m, 16 * ((oracle.mx_row_bytes(q, n) + 15) // 16) + 64), dtype=torch.uint8, device="cuda")
+    S = torch.zeros((m, (n + 31) // 32 + 7), dtype=torch.uint8, device="cuda")
+    sb.sb_quantize_mx(dev(store)[:, :n], Q, S, q)
+    rb, nb = oracle.mx_row_bytes(q, n), (n + 31) // 32
+    assert np.array_equal(host(Q)[:, :rb], codes) and np.array_equal(host(S)[:, :nb], scales)
+    x = rng.standard_normal(n).astype(np.float32)
+    x[500] = np.inf
+    c0 = np.zeros(m)
+    cd = torch.zeros(m, dtype=torch.float32, device="cuda")
+    sb.sb_gemv_mx(Q, S, dev(x), cd, q)
+    got = host(cd).astype(np.float64)
+    ref = oracle.gemv_mx(codes, scales, x, c0, q, n)
+    assert np.array_equal(np.isnan(got), np.isnan(ref)) and np.array_equal(np.isinf(got), np.isinf(ref))
+    fin = np.isfinite(ref)
+    assert fin.sum() < m and (~fin).sum() > 0
