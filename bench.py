@@ -356,8 +356,9 @@ def main():
         from paper_2108_02025_amd.tuner import TuningTable
         tuning = TuningTable.load()
         serving = {"tuned": tuning is not None}
-        for label, budget in (("budget_4GiB", 4 << 30), ("budget_512MiB", 512 << 20)):
-            trace = make_trace(4096, rate=1e5, seed=501)
+        for label, budget, dots in (("budget_4GiB", 4 << 30, 0.0), ("budget_512MiB", 512 << 20, 0.0),
+                                    ("budget_4GiB_with_25pct_dot", 4 << 30, 0.25)):
+            trace = make_trace(4096, rate=1e5, seed=501, dot_fraction=dots, dot_hi=1 << 16)
             server = Server(budget_bytes=budget, tuning=tuning)
             st = server.run(trace)
             serving[label] = st.as_dict()
@@ -366,7 +367,9 @@ def main():
                 f"device-busy {st.device_busy_GBs:.1f} GB/s, {st.batches} batches")
             del server
         out["serving"] = {"trace": "4096 requests, Poisson 1e5 req/s, m,n log-uniform [64,8192], "
-                                   "f32 / bf16-A 50:50, uniform[-1,1), c0 = 0", **serving}
+                                   "f32 / bf16-A 50:50, uniform[-1,1), c0 = 0 (the _with_25pct_dot run "
+                                   "turns a quarter of them into f32 DOTs of length log-uniform [64,65536])",
+                          **serving}
     if not args.no_cpu:
         log("timing the CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(step_bytes)

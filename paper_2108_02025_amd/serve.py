@@ -2,7 +2,9 @@
 streaming core).
 
 Requests c = A x (A m x n, binary32 or bfloat16-A with per-row scales, x and
-c binary32) arrive on a trace.  The host loop:
+c binary32) and DOT requests alpha = x . y (binary32; served as the one-row
+GEMV whose row is x, which is the same sum) arrive on a trace.  The host
+loop:
 
   1. releases each request at its arrival time into a FIFO queue;
   2. admits the queue head when its operands fit the HBM budget (a first-fit
@@ -54,6 +56,7 @@ class Request:
     m: int
     n: int
     seed: int
+    op: str = "gemv"   # "dot": alpha = x . y, the one-row binary32 GEMV (m = 1)
     t_admit: float = math.nan
     t_launch: float = math.nan
     t_done: float = math.nan
@@ -83,16 +86,24 @@ def device_bytes(kind: str, m: int, n: int) -> int:
 
 
 def make_trace(n_requests: int = 4096, rate: float = 1e5, seed: int = 501, lo: int = 64, hi: int = 8192,
-               bf16_fraction: float = 0.5) -> list[Request]:
+               bf16_fraction: float = 0.5, dot_fraction: float = 0.0, dot_hi: int | None = None) -> list[Request]:
     """Poisson arrivals at `rate` requests/s; m and n log-uniform in [lo, hi];
-    kind bfloat16-A with probability `bf16_fraction`, else binary32."""
+    kind bfloat16-A with probability `bf16_fraction`, else binary32.  With
+    `dot_fraction` > 0 that share of requests are binary32 DOTs of length
+    log-uniform in [lo, dot_hi] (default hi), drawn after the GEMV fields so
+    the rest of the trace does not change."""
     rng = np.random.default_rng(seed)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, n_requests))
     arrivals -= arrivals[0]
     m = np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), n_requests))).astype(int)
     n = np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), n_requests))).astype(int)
     kinds = np.where(rng.random(n_requests) < bf16_fraction, "bf16", "f32")
-    return [Request(i, float(arrivals[i]), str(kinds[i]), int(m[i]), int(n[i]), seed * (1 << 32) + i)
+    ops = np.full(n_requests, "gemv")
+    if dot_fraction > 0:
+        is_dot = rng.random(n_requests) < dot_fraction
+        dn = np.rint(np.exp(rng.uniform(math.log(lo), math.log(dot_hi or hi), n_requests))).astype(int)
+        ops[is_dot], kinds[is_dot], m[is_dot], n[is_dot] = "dot", "f32", 1, dn[is_dot]
+    return [Request(i, float(arrivals[i]), str(kinds[i]), int(m[i]), int(n[i]), seed * (1 << 32) + i, str(ops[i]))
             for i in range(n_requests)]
 
 
@@ -189,6 +200,7 @@ class Stats:
     batches: int
     mean_batch: float
     total_bytes: int
+    dot_requests: int = 0
 
     def as_dict(self) -> dict:
         return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in dataclasses.asdict(self).items()}
@@ -401,7 +413,8 @@ class Server:
             p50_ms=pct(lat, 50), p99_ms=pct(lat, 99), p999_ms=pct(lat, 99.9),
             queue_p50_ms=pct(q, 50), materialise_p50_ms=pct(mat, 50), execute_p50_ms=pct(ex, 50),
             aggregate_GBs=total / span / 1e9, device_busy_GBs=total / busy / 1e9 if busy > 0 else math.nan,
-            batches=nbatches, mean_batch=len(ok) / max(nbatches, 1), total_bytes=total)
+            batches=nbatches, mean_batch=len(ok) / max(nbatches, 1), total_bytes=total,
+            dot_requests=sum(r.op == "dot" for r in ok))
 
     def result_of(self, r: Request) -> torch.Tensor:
         return self.results[r.result_at:r.result_at + r.m]

@@ -153,6 +153,8 @@ class TuningTable:
         return cls(data)
 
     def __call__(self, kind: str, m: int, n: int) -> dict | None:
+        if n > 1 << LOG2[-1]:
+            return None  # beyond the tuned widths: the automatic split fits any row
         e = self.buckets.get(bucket(kind, m, n))
         if e is None:
             return None

@@ -41,7 +41,10 @@ def check_sampled(sb, server, trace):
             continue
         got = host(server.result_of(r)).astype(np.float64)
         A, x = host_operands(r)
-        if r.kind == "f32":
+        if r.op == "dot":
+            ref = np.array([oracle.dot(A[0], x, 0.0)])   # alpha = x . y with x = the row, y = the vector
+            mag = np.abs(A.astype(np.float64)) @ np.abs(x.astype(np.float64))
+        elif r.kind == "f32":
             ref = oracle.gemv(A, x, np.zeros(r.m))
             mag = np.abs(A.astype(np.float64)) @ np.abs(x.astype(np.float64))
         else:
@@ -64,6 +67,21 @@ def test_serve_trace_matches_oracle_and_alone(sb):
     assert st.n == 400 and st.rejected == 0 and st.batches >= 1
     assert all(r.t_admit >= r.arrival and r.t_done >= r.t_launch >= r.t_admit for r in trace)
     assert check_sampled(sb, server, trace) == 50
+
+
+def test_serve_gemv_and_dot_requests(sb):
+    """A mixed trace of GEMV and DOT requests (DOTs up to 65536 long, split
+    along their length inside the batch): every sampled result matches the
+    oracle and is bit-identical alone."""
+    from paper_2108_02025_amd.serve import Server, make_trace
+    from paper_2108_02025_amd.tuner import TuningTable
+    trace = make_trace(240, rate=2e4, seed=909, lo=64, hi=2048, dot_fraction=0.4, dot_hi=65536)
+    assert any(r.op == "dot" and r.n > 8192 for r in trace)
+    server = Server(budget_bytes=1 << 30, sample_every=3, tuning=TuningTable.load())
+    st = server.run(trace)
+    print(st.as_dict())
+    assert st.n == 240 and st.rejected == 0 and st.dot_requests == sum(r.op == "dot" for r in trace)
+    assert check_sampled(sb, server, trace) == 80
 
 
 def test_serve_small_budget_queues_and_rejects(sb):

@@ -43,3 +43,17 @@ def test_pool_first_fit_and_merge():
 def test_request_bytes():
     assert device_bytes("f32", 64, 64) == 64 * 64 * 4 + 256 + 256
     assert device_bytes("bf16", 100, 100) == 20224 + 512 + 512 + 512
+
+
+def test_trace_dot_requests():
+    from paper_2108_02025_amd.serve import make_trace
+    base = make_trace(300, seed=3)
+    mixed = make_trace(300, seed=3, dot_fraction=0.3, dot_hi=1 << 16)
+    dots = [r for r in mixed if r.op == "dot"]
+    assert 50 < len(dots) < 130
+    assert all(r.m == 1 and r.kind == "f32" and 64 <= r.n <= 1 << 16 for r in dots)
+    for a, b in zip(base, mixed):   # the GEMV fields are drawn first and do not change
+        assert a.arrival == b.arrival
+        if b.op == "gemv":
+            assert (a.kind, a.m, a.n, a.seed) == (b.kind, b.m, b.n, b.seed)
+    assert all(r.op == "gemv" for r in base)
