@@ -182,11 +182,18 @@ def time_ops(torch, ops, steps):
     return per, t0.elapsed_time(t1) / steps
 
 
-def cpu_baseline(step_bytes):
-    """The CPU oracle (single thread, as it stands) on the step's operations:
-    binary64 GEMV N/T, GER on the full 16384 x 16384 size and DOT on the full
-    2^28; the quantised GEMV on 4096 rows and the exact dot on 2^24 pairs.
-    Each operation's rate is applied to the full step's bytes."""
+def cpu_baseline(step_bytes, thread_counts=(1,)):
+    """The CPU oracle, as it stands, on the step's operations: binary64 GEMV
+    N/T, the two-sided GEMV and GER on the full 16384 x 16384 size and DOT
+    on the full 2^28; the quantised GEMVs on 4096 rows, the MX GEMVs on 1024
+    and the exact dot on 2^24 pairs.  With threads > 1 each call is cut into that many
+    disjoint row slices (chunks for the dots) run concurrently (the oracle's
+    C code releases the interpreter lock); slices of a column sum are added
+    afterwards, which is enough for timing.  Each operation's rate is applied
+    to the full step's bytes.  Returns one result per thread count; the
+    inputs are drawn once."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
 
     import oracle
@@ -194,45 +201,66 @@ def cpu_baseline(step_bytes):
 
     oracle.build()
     M = N = 16384
-    rates, parts = {}, []
+    rates = {t: {} for t in thread_counts}
+    parts = {t: [] for t in thread_counts}
+    pools = {t: ThreadPoolExecutor(t) for t in thread_counts}
 
-    def timed(name, nbytes, fn):
-        t = time.perf_counter()
-        fn()
-        dt = time.perf_counter() - t
-        rates[name] = nbytes / dt
-        parts.append(f"{name}:{nbytes / 1e6:.0f}MB/{dt:.2f}s")
-        log(f"oracle {name}: {nbytes / dt / 1e9:.2f} GB/s")
+    def timed(name, nbytes, fn, n):
+        """fn(a, b) runs the oracle on rows (or elements) [a, b)."""
+        for t in thread_counts:
+            b = np.linspace(0, n, t + 1).astype(int)
+            t0 = time.perf_counter()
+            list(pools[t].map(lambda ab: fn(*ab), zip(b[:-1], b[1:])))
+            dt = time.perf_counter() - t0
+            rates[t][name] = nbytes / dt
+            parts[t].append(f"{name}:{nbytes / 1e6:.0f}MB/{dt:.2f}s")
+            log(f"oracle x{t} {name}: {nbytes / dt / 1e9:.2f} GB/s")
 
     A, x, c0 = workloads.gemv_inputs(M, N, seed=201)
-    timed("gemv_n_f64", 8 * (M * N + N + 2 * M), lambda: oracle.gemv(A, x, c0))
-    timed("gemv_t_f64", 8 * (M * N + M + 2 * N), lambda: oracle.gemv(A, x, c0, op=oracle.OP_T))
+    y2, d0 = np.ones(M), np.zeros(N)
+    timed("gemv_n_f64", 8 * (M * N + N + 2 * M), lambda a, b: oracle.gemv(A[a:b], x, c0[a:b]), M)
+    timed("gemv_t_f64", 8 * (M * N + M + 2 * N),
+          lambda a, b: oracle.gemv(A[a:b], x[a:b], c0, op=oracle.OP_T), M)
+    timed("gemv2_f64", 8 * (M * N + 3 * M + 3 * N),
+          lambda a, b: oracle.gemv2(A[a:b], x, y2[a:b], c0[a:b], d0), M)
     rows = 4096
     A32 = np.ascontiguousarray(A[:rows]).astype(np.float32)
     del A
     xq = np.random.default_rng(401).standard_normal(N).astype(np.float32)
     for q, name, es in ((oracle.Q_BF16, "gemv_q_bf16", 2), (oracle.Q_E4M3, "gemv_q_e4m3", 1)):
         codes, s = oracle.quantize_rows(A32, q)
-        timed(name, es * rows * N + 4 * N + 12 * rows, lambda: oracle.gemv_q(codes, s, xq, np.zeros(rows), q))
+        timed(name, es * rows * N + 4 * N + 12 * rows,
+              lambda a, b: oracle.gemv_q(codes[a:b], s[a:b], xq, np.zeros(b - a), q), rows)
+    mrows = 1024
+    for q, name, rb in ((oracle.Q_MXFP8, "gemv_mx_fp8", N), (oracle.Q_MXFP4, "gemv_mx_fp4", N // 2)):
+        codes, s = oracle.quantize_mx(A32[:mrows], q)
+        timed(name, mrows * rb + mrows * (N // 32) + 4 * N + 8 * mrows,
+              lambda a, b: oracle.gemv_mx(codes[a:b], s[a:b], xq, np.zeros(b - a), q, N), mrows)
     del A32
     nd = 1 << 28
     dx, dy, da = workloads.dot_inputs(nd, seed=202)
-    timed("dot_f64", 8 * (2 * nd + 2), lambda: oracle.dot(dx, dy, da[0]))
+    timed("dot_f64", 8 * (2 * nd + 2), lambda a, b: oracle.dot(dx[a:b], dy[a:b], da[0]), nd)
     del dx, dy
     gx, gy, gC = workloads.ger_inputs(M, N, seed=203)
-    timed("ger_f64", 8 * (2 * M * N + M + N), lambda: oracle.ger(gx, gy, gC))
+    timed("ger_f64", 8 * (2 * M * N + M + N), lambda a, b: oracle.ger(gx[a:b], gy, gC[a:b]), M)
     del gC
     n2 = 1 << 24
     hx, hy, _, _ = workloads.illcond_dot_inputs(n2, seed=402)
-    timed("dot2_f32", 4 * (2 * n2 + 2), lambda: oracle.dot_exact_f32(hx, hy))
-    total_t = sum(b / rates[k] for k, b in step_bytes.items() if k in rates)
-    total_b = sum(b for k, b in step_bytes.items() if k in rates)
-    return {
-        "value": round(total_b / total_t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-        "sample": "single-thread oracle: fp64 gemv N/T and ger on 16384x16384, dot on 2^28 (full size); "
-                  "quantised gemv on 4096 of the 16384 rows, exact dot on 2^24 ill-conditioned pairs; "
-                  "each operation's rate applied to the full step's bytes (" + "; ".join(parts) + ")",
-    }
+    timed("dot2_f32", 4 * (2 * n2 + 2), lambda a, b: oracle.dot_exact_f32(hx[a:b], hy[a:b]), n2)
+    out = []
+    for t in thread_counts:
+        pools[t].shutdown()
+        total_t = sum(b / rates[t][k] for k, b in step_bytes.items() if k in rates[t])
+        total_b = sum(b for k, b in step_bytes.items() if k in rates[t])
+        who = "single-thread oracle" if t == 1 else f"oracle on {t} threads (disjoint slices)"
+        out.append({
+            "value": round(total_b / total_t / 1e9, 3), "unit": "GB/s", "cores": t, "kind": "oracle",
+            "sample": who + ": fp64 gemv N/T, two-sided gemv and ger on 16384x16384, dot on 2^28 (full size); "
+                      "quantised gemv on 4096 and MX gemv on 1024 of the 16384 rows, exact dot on 2^24 "
+                      "ill-conditioned pairs; "
+                      "each operation's rate applied to the full step's bytes (" + "; ".join(parts[t]) + ")",
+        })
+    return out
 
 
 def small_problems(sb, torch, dev):
@@ -372,7 +400,11 @@ def main():
                           **serving}
     if not args.no_cpu:
         log("timing the CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(step_bytes)
+        cores = min(16, len(os.sched_getaffinity(0)))
+        res = cpu_baseline(step_bytes, (1, cores) if cores > 1 else (1,))
+        out["cpu_baseline"] = res[0]
+        if cores > 1:
+            out["cpu_baseline_all_cores"] = res[1]
     print(json.dumps(out), flush=True)
 
 
