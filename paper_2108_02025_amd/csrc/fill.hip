@@ -21,9 +21,11 @@
 
 namespace sb {
 
-__device__ __forceinline__ double splitmix_uniform(uint64_t seed, uint64_t c)
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+// The output of a SplitMix64 state z = seed + (c + 1) * golden (mod 2^64).
+__device__ __forceinline__ double splitmix_from_state(uint64_t z)
 {
-    uint64_t z = seed + (c + 1ull) * 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z = z ^ (z >> 31);
@@ -31,12 +33,27 @@ __device__ __forceinline__ double splitmix_uniform(uint64_t seed, uint64_t c)
     return 2.0 * u - 1.0;
 }
 
+// Counters c, c + stride, c + 2 * stride, ...: the state advances by
+// stride * golden each step (one addition instead of a multiplication).
+struct SplitMixWalk {
+    uint64_t z, step;
+    __device__ SplitMixWalk(uint64_t seed, uint64_t c, uint64_t stride)
+        : z(seed + (c + 1ull) * kGolden), step(stride * kGolden) {}
+    __device__ double next()
+    {
+        const double v = splitmix_from_state(z);
+        z += step;
+        return v;
+    }
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void fill_uniform_kernel(T* out, int64_t count, uint64_t seed, uint64_t counter0)
 {
     const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < count; k += stride)
-        out[k] = (T)splitmix_uniform(seed, counter0 + (uint64_t)k);
+    int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    SplitMixWalk g(seed, counter0 + (uint64_t)k, (uint64_t)stride);
+    for (; k < count; k += stride) out[k] = (T)g.next();
 }
 
 sb_status run_fill_uniform(sb_handle* h, sb_dtype dt, void* out, int64_t count, uint64_t seed, uint64_t counter0)
@@ -56,9 +73,9 @@ sb_status run_fill_uniform(sb_handle* h, sb_dtype dt, void* out, int64_t count, 
 //
 // One launch makes the operands of many requests: every row of every A is a
 // work item (binary32 rows are generated in place; bfloat16 rows are
-// generated twice, once for the row's amax and once for the codes, exactly
-// as sb_fill_uniform followed by sb_quantize_rows would produce them), plus
-// one item per request for x (counters m*n ... m*n + n - 1) and the zeroed c.
+// generated, reduced to their amax and encoded, exactly as sb_fill_uniform
+// followed by sb_quantize_rows would produce them), plus one item per
+// request for x (counters m*n ... m*n + n - 1) and the zeroed c.
 
 struct GenHeader {
     int64_t count, nitems, pad[6];
@@ -75,14 +92,18 @@ struct GenRec {
 };
 static_assert(sizeof(GenHeader) == 64 && sizeof(GenRec) == 80, "generator table layout");
 
+// One wave per work item (four items per workgroup): rows are short (the
+// serving trace's median is a few hundred values), so the item's overhead —
+// finding its request and, for bfloat16, reducing the row's amax — stays
+// inside the wave, with no workgroup barriers.
 __global__ __launch_bounds__(256) void generate_kernel(const unsigned char* table)
 {
-    __shared__ float red[4];
-    __shared__ float s_sh;
     const GenHeader* hdr = reinterpret_cast<const GenHeader*>(table);
     const GenRec* recs = reinterpret_cast<const GenRec*>(table + sizeof(GenHeader));
     const int64_t count = hdr->count, nitems = hdr->nitems;
-    for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t waves = (int64_t)gridDim.x * (256 / kWave);
+    for (int64_t item = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave; item < nitems; item += waves) {
         int64_t lo = 0, hi = count - 1;
         while (lo < hi) {
             const int64_t mid = (lo + hi + 1) >> 1;
@@ -97,32 +118,28 @@ __global__ __launch_bounds__(256) void generate_kernel(const unsigned char* tabl
             const uint64_t c0 = (uint64_t)(row * r.n);
             if (r.dtype == SB_F32) {
                 float* Ar = static_cast<float*>(r.A) + row * r.lda;
-                for (int64_t j = threadIdx.x; j < r.n; j += 256) Ar[j] = (float)splitmix_uniform(r.seed, c0 + j);
+                SplitMixWalk g(r.seed, c0 + lane, kWave);
+                for (int64_t j = lane; j < r.n; j += kWave) Ar[j] = (float)g.next();
             } else {
                 float amax = 0.0f;
-                for (int64_t j = threadIdx.x; j < r.n; j += 256) {
-                    const float v = fabsf((float)splitmix_uniform(r.seed, c0 + j));
+                SplitMixWalk g(r.seed, c0 + lane, kWave);
+                for (int64_t j = lane; j < r.n; j += kWave) {
+                    const float v = fabsf((float)g.next());
                     if (v == v && v > amax) amax = v;
                 }
 #pragma unroll
-                for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
-                if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = amax;
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    s_sh = row_scale(true, fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
-                    r.scales[row] = s_sh;
-                }
-                __syncthreads();
-                const float s = s_sh;
+                for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, kWave));
+                const float s = row_scale(true, amax);
+                if (lane == 0) r.scales[row] = s;
                 uint16_t* Qr = static_cast<uint16_t*>(r.A) + row * r.lda;
-                for (int64_t j = threadIdx.x; j < r.n; j += 256)
-                    Qr[j] = bf16_encode((float)splitmix_uniform(r.seed, c0 + j) / s);
-                __syncthreads();  // s_sh and red are reused by the next item
+                SplitMixWalk g2(r.seed, c0 + lane, kWave);
+                for (int64_t j = lane; j < r.n; j += kWave) Qr[j] = bf16_encode((float)g2.next() / s);
             }
         } else {
             const uint64_t c0 = (uint64_t)(r.m * r.n);
-            for (int64_t j = threadIdx.x; j < r.n; j += 256) r.x[j] = (float)splitmix_uniform(r.seed, c0 + j);
-            for (int64_t i = threadIdx.x; i < r.m; i += 256) r.c[i] = 0.0f;
+            SplitMixWalk g(r.seed, c0 + lane, kWave);
+            for (int64_t j = lane; j < r.n; j += kWave) r.x[j] = (float)g.next();
+            for (int64_t i = lane; i < r.m; i += kWave) r.c[i] = 0.0f;
         }
     }
 }
@@ -180,7 +197,7 @@ sb_status sb_generate_batched(sb_handle* handle, const sb_gen_desc* descs, int32
                         image.size(), handle->ws_bytes);
         const hipError_t e = hipMemcpyAsync(handle->ws, image.data(), image.size(), hipMemcpyHostToDevice, handle->stream);
         if (e != hipSuccess) return fail(handle, SB_EDEVICE, "sb_generate_batched: copy: %s", hipGetErrorString(e));
-        const int64_t grid = std::min<int64_t>(items, 4096);
+        const int64_t grid = std::min<int64_t>((items + 3) / 4, 4096);  // four items (waves) per workgroup
         hipLaunchKernelGGL(sb::generate_kernel, dim3((unsigned)grid), dim3(256), 0, handle->stream,
                            static_cast<const unsigned char*>(handle->ws));
         return sb::check_launch(handle, "generate_kernel");
