@@ -84,6 +84,20 @@ def test_serve_gemv_and_dot_requests(sb):
     assert check_sampled(sb, server, trace) == 80
 
 
+def test_serve_full_trace_sampled(sb):
+    """The measured serving workload itself (4096 requests, 1e5/s, 4 GiB,
+    tuned configurations): every 128th request against the oracle and
+    alone."""
+    from paper_2108_02025_amd.serve import Server, make_trace
+    from paper_2108_02025_amd.tuner import TuningTable
+    trace = make_trace(4096, rate=1e5, seed=501)
+    server = Server(budget_bytes=4 << 30, sample_every=128, tuning=TuningTable.load())
+    st = server.run(trace)
+    print(st.as_dict())
+    assert st.n == 4096 and st.rejected == 0
+    assert check_sampled(sb, server, trace) == 32
+
+
 def test_serve_small_budget_queues_and_rejects(sb):
     from paper_2108_02025_amd.serve import Request, Server, device_bytes, make_trace
     trace = make_trace(200, rate=5e4, seed=7, lo=64, hi=2048)
