@@ -387,7 +387,7 @@ def main():
         for label, budget, dots in (("budget_4GiB", 4 << 30, 0.0), ("budget_512MiB", 512 << 20, 0.0),
                                     ("budget_4GiB_with_25pct_dot", 4 << 30, 0.25)):
             trace = make_trace(4096, rate=1e5, seed=501, dot_fraction=dots, dot_hi=1 << 16)
-            server = Server(budget_bytes=budget, tuning=tuning)
+            server = Server(budget_bytes=budget, tuning=tuning, sample_every=256)  # results unchecked here
             st = server.run(trace)
             serving[label] = st.as_dict()
             log(f"serving {label}: p50 {st.p50_ms:.2f} ms, p99 {st.p99_ms:.2f} ms, "
