@@ -36,7 +36,10 @@ namespace sb {
 constexpr int kBatNT = 256;
 constexpr int kBatWaves = kBatNT / kWave;
 constexpr int64_t kBatLds = 32 * 1024;     // x chunk bytes per tile
-constexpr int64_t kBatTileBytes = 256 * 1024;  // automatic tile size target (bytes of A)
+#ifndef SB_BAT_TILE_BYTES
+#define SB_BAT_TILE_BYTES (256 * 1024)
+#endif
+constexpr int64_t kBatTileBytes = SB_BAT_TILE_BYTES;  // automatic tile size target (bytes of A)
 #ifndef SB_BAT_UNROLL_PLAIN
 #define SB_BAT_UNROLL_PLAIN 8
 #endif
