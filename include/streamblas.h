@@ -315,6 +315,25 @@ sb_status sb_gemv_batched_run(sb_handle* handle, const void* dev_table, int32_t 
 sb_status sb_gemv_batched(sb_handle* handle, const sb_gemv_desc* descs, int32_t count);
 
 /*
+ * Batched plans: the descriptors are checked, resolved and encoded once; the
+ * table is copied (on the handle's stream) into the handle's workspace,
+ * which must hold sb_gemv_batched_table_bytes; sb_plan_run then launches the
+ * persistent kernel on the handle's current stream with no host work, as
+ * often as wanted (a captured sb_plan_run can be replayed).  The table
+ * belongs to the plan: a later call on the same handle that writes the
+ * workspace (a split GEMV, a two-stage DOT, another batch or plan, a probe,
+ * the generator) or a new workspace makes sb_plan_run fail with SB_EINVAL
+ * until the plan is created again.  Calls on the handle that need no
+ * workspace leave the plan valid.  A plan must be destroyed before its
+ * handle; sb_plan_destroy(NULL) is accepted.  A batch with no work gives a
+ * plan whose runs launch nothing.
+ */
+typedef struct sb_plan sb_plan;
+sb_status sb_plan_create(sb_handle* handle, const sb_gemv_desc* descs, int32_t count, sb_plan** out);
+sb_status sb_plan_run(sb_plan* plan);
+sb_status sb_plan_destroy(sb_plan* plan);
+
+/*
  * Operand generation (serving form: requests' operands are made on the
  * device where they are used).  out[k] = 2u - 1 with u = (z >> 11) * 2^-53
  * and z = SplitMix64(seed, counter0 + k) (Steele, Lea and Flood, OOPSLA

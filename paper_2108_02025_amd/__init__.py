@@ -29,6 +29,7 @@ __all__ = [
     "sb_gemv_batched_resolve", "sb_gemv_batched_table_bytes", "BatchTable", "sb_fill_uniform",
     "SB_CUTOFF_DOT_SMALL_BYTES", "SB_CUTOFF_GEMV_T_SMALL_SPLITS", "sb_set_cutoff", "sb_get_cutoff",
     "SB_MXFP8_E4M3", "SB_MXFP4_E2M1", "SB_KIND_GEMV_MX", "mx_buffers", "sb_quantize_mx", "sb_gemv_mx",
+    "Plan",
 ]
 
 SB_OK, SB_EINVAL, SB_ENOMEM, SB_EDEVICE, SB_EUNSUPPORTED, SB_EINTERNAL = 0, -1, -2, -3, -4, -5
@@ -98,6 +99,9 @@ def load():
     L.sb_gemv_batched_encode.argtypes = [ctypes.POINTER(sb_gemv_desc), I32, P, P, SZ]
     L.sb_gemv_batched_run.argtypes = [P, P, I32]
     L.sb_gemv_batched.argtypes = [P, ctypes.POINTER(sb_gemv_desc), I32]
+    L.sb_plan_create.argtypes = [P, ctypes.POINTER(sb_gemv_desc), I32, ctypes.POINTER(P)]
+    L.sb_plan_run.argtypes = [P]
+    L.sb_plan_destroy.argtypes = [P]
     L.sb_fill_uniform.argtypes = [P, I32, P, I64, ctypes.c_uint64, ctypes.c_uint64]
     L.sb_generate_batched_bytes.argtypes = [I32]
     L.sb_generate_batched_bytes.restype = SZ
@@ -106,7 +110,8 @@ def load():
     L.sb_stream_copy.argtypes = [P, P, P, SZ]
     for f in ("sb_fill_uniform", "sb_generate_batched", "sb_gemv_batched_resolve", "sb_gemv_batched_encode", "sb_gemv_batched_run", "sb_gemv_batched",
               "sb_stream_read", "sb_stream_copy", "sb_handle_create", "sb_handle_destroy", "sb_set_stream", "sb_set_workspace", "sb_set_cutoff", "sb_get_cutoff", "sb_gemv", "sb_gemv2",
-              "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32", "sb_quantize_mx", "sb_gemv_mx"):
+              "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32", "sb_quantize_mx", "sb_gemv_mx",
+              "sb_plan_create", "sb_plan_run", "sb_plan_destroy"):
         getattr(L, f).restype = I32
     _lib = L
     return L
@@ -512,6 +517,33 @@ def sb_gemv_batched(problems) -> None:
     h = handle_for(problems[0].A)
     h.prepare(total)
     h.check(load().sb_gemv_batched(h.h, descs, len(problems)))
+
+
+class Plan:
+    """A batched plan (sb_plan_*): the problems are encoded once into the
+    workspace of a handle private to the plan, and run() launches them on
+    the current stream with no host work (a captured run() can be replayed).
+    The plan keeps the problems' tensors alive."""
+
+    def __init__(self, problems, device=None):
+        self.problems = list(problems)
+        dev = self.problems[0].A.device if self.problems else device
+        self.handle = Handle(dev)
+        total, _ = sb_gemv_batched_table_bytes(self.problems) if self.problems else (0, 0)
+        self.handle.prepare(total)
+        self._descs = make_descs(self.problems) if self.problems else (sb_gemv_desc * 1)()
+        p = ctypes.c_void_p()
+        self.handle.check(load().sb_plan_create(self.handle.h, self._descs, len(self.problems), ctypes.byref(p)))
+        self.p = p
+
+    def run(self) -> None:
+        self.handle.prepare(0)  # the current stream
+        self.handle.check(load().sb_plan_run(self.p))
+
+    def __del__(self):
+        if getattr(self, "p", None) and _lib is not None:
+            _lib.sb_plan_destroy(self.p)
+            self.p = None
 
 
 class BatchTable:

@@ -125,6 +125,7 @@ sb_status sb_handle_create(void* workspace, size_t ws_bytes, void* stream, sb_ha
     if (!h) return fail(nullptr, SB_EINTERNAL, "sb_handle_create: out of host memory");
     h->ws = workspace;
     h->ws_bytes = workspace ? ws_bytes : 0;
+    h->ws_gen = 0;
     h->stream = static_cast<hipStream_t>(stream);
     h->dot_small_bytes = sb::kDefaultDotSmallBytes;
     h->gemv_t_small_splits = sb::kDefaultGemvTSmallSplits;
@@ -152,6 +153,7 @@ sb_status sb_set_workspace(sb_handle* handle, void* workspace, size_t ws_bytes)
     if (!workspace && ws_bytes) return fail(handle, SB_EINVAL, "sb_set_workspace: NULL workspace of %zu bytes", ws_bytes);
     handle->ws = workspace;
     handle->ws_bytes = workspace ? ws_bytes : 0;
+    ++handle->ws_gen;
     return SB_OK;
 }
 

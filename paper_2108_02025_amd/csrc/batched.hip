@@ -25,6 +25,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <new>
 #include <vector>
 
 #include "sb_device.hpp"
@@ -495,7 +496,7 @@ sb_status sb_gemv_batched(sb_handle* handle, const sb_gemv_desc* descs, int32_t 
             return fail(handle, SB_ENOMEM, "sb_gemv_batched needs %zu workspace bytes, handle has %zu", L.total,
                         handle->ws_bytes);
         std::vector<unsigned char> image(L.image);
-        sb::encode(descs, count, L, static_cast<unsigned char*>(handle->ws), image.data());
+        sb::encode(descs, count, L, static_cast<unsigned char*>(sb::claim_ws(handle)), image.data());
         // From pageable memory the copy is staged before the call returns,
         // so the local image may be released afterwards.
         const hipError_t e = hipMemcpyAsync(handle->ws, image.data(), L.image, hipMemcpyHostToDevice, handle->stream);
@@ -504,6 +505,66 @@ sb_status sb_gemv_batched(sb_handle* handle, const sb_gemv_desc* descs, int32_t 
     } catch (...) {
         return fail(handle, SB_EINTERNAL, "sb_gemv_batched: unexpected C++ exception");
     }
+}
+
+}  // extern "C"
+
+// A batched plan: the table encoded once into the handle's workspace, run
+// any number of times without host work.
+struct sb_plan {
+    sb_handle* handle;
+    void* table;
+    uint64_t gen;
+    int64_t ntiles;
+};
+
+extern "C" {
+
+sb_status sb_plan_create(sb_handle* handle, const sb_gemv_desc* descs, int32_t count, sb_plan** out)
+{
+    if (!out) return fail(handle, SB_EINVAL, "sb_plan_create: out is NULL");
+    *out = nullptr;
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_plan_create: NULL handle");
+    try {
+        sb::BatLayout L;
+        char why[256];
+        const sb_status st = sb::layout(descs, count, L, why, sizeof why);
+        if (st != SB_OK) return fail(handle, st, "sb_plan_create: %s", why);
+        if (L.ntiles > 0) {
+            if (L.total > handle->ws_bytes || !sb::aligned16(handle->ws))
+                return fail(handle, SB_ENOMEM, "sb_plan_create needs %zu workspace bytes, handle has %zu", L.total,
+                            handle->ws_bytes);
+            std::vector<unsigned char> image(L.image);
+            sb::encode(descs, count, L, static_cast<unsigned char*>(sb::claim_ws(handle)), image.data());
+            const hipError_t e =
+                hipMemcpyAsync(handle->ws, image.data(), L.image, hipMemcpyHostToDevice, handle->stream);
+            if (e != hipSuccess)
+                return fail(handle, SB_EDEVICE, "sb_plan_create: copy of the table: %s", hipGetErrorString(e));
+        }
+        sb_plan* p = new (std::nothrow) sb_plan{handle, handle->ws, handle->ws_gen, L.ntiles};
+        if (!p) return fail(handle, SB_EINTERNAL, "sb_plan_create: out of host memory");
+        *out = p;
+        return SB_OK;
+    } catch (...) {
+        return fail(handle, SB_EINTERNAL, "sb_plan_create: unexpected C++ exception");
+    }
+}
+
+sb_status sb_plan_run(sb_plan* plan)
+{
+    if (!plan) return fail(nullptr, SB_EINVAL, "sb_plan_run: NULL plan");
+    if (plan->ntiles == 0) return SB_OK;
+    sb_handle* h = plan->handle;
+    if (h->ws != plan->table || h->ws_gen != plan->gen)
+        return fail(h, SB_EINVAL, "sb_plan_run: the handle's workspace was replaced or written by a later call; "
+                                  "create the plan again");
+    return sb_gemv_batched_run(h, plan->table, 0);
+}
+
+sb_status sb_plan_destroy(sb_plan* plan)
+{
+    delete plan;
+    return SB_OK;
 }
 
 }  // extern "C"

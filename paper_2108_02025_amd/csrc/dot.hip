@@ -327,7 +327,7 @@ static sb_status dot_typed(sb_handle* h, int64_t n, const T* x, const T* y, T* a
         else hipLaunchKernelGGL((dot_small_kernel<T, false>), dim3(1), dim3(kSmallNT), 0, h->stream, n, x, y, alpha);
         return check_launch(h, "dot_small_kernel");
     }
-    T* part = static_cast<T*>(h->ws);
+    T* part = static_cast<T*>(claim_ws(h));
     DotArgs<T> a{n, x, y, part, p.chunk};
     if (al) hipLaunchKernelGGL((dot_stage1_kernel<T, 256, true>), dim3((unsigned)p.nblocks), dim3(256), 0, h->stream, a);
     else hipLaunchKernelGGL((dot_stage1_kernel<T, 256, false>), dim3((unsigned)p.nblocks), dim3(256), 0, h->stream, a);
@@ -361,7 +361,7 @@ sb_status run_dot2(sb_handle* h, int64_t n, const float* x, const float* y, floa
             hipLaunchKernelGGL((dot2_small_kernel<false>), dim3(1), dim3(kSmallNT), 0, h->stream, n, x, y, alpha);
         return check_launch(h, "dot2_small_kernel");
     }
-    float* part = static_cast<float*>(h->ws);
+    float* part = static_cast<float*>(claim_ws(h));
     if (aligned16(x) && aligned16(y))
         hipLaunchKernelGGL((dot2_stage1_kernel<256, true>), dim3((unsigned)p.nblocks), dim3(256), 0,
                            h->stream, n, x, y, part, p.chunk);

@@ -195,7 +195,7 @@ sb_status sb_generate_batched(sb_handle* handle, const sb_gen_desc* descs, int32
         if (image.size() > handle->ws_bytes || !sb::aligned16(handle->ws))
             return fail(handle, SB_ENOMEM, "sb_generate_batched needs %zu workspace bytes, handle has %zu",
                         image.size(), handle->ws_bytes);
-        const hipError_t e = hipMemcpyAsync(handle->ws, image.data(), image.size(), hipMemcpyHostToDevice, handle->stream);
+        const hipError_t e = hipMemcpyAsync(sb::claim_ws(handle), image.data(), image.size(), hipMemcpyHostToDevice, handle->stream);
         if (e != hipSuccess) return fail(handle, SB_EDEVICE, "sb_generate_batched: copy: %s", hipGetErrorString(e));
         const int64_t grid = std::min<int64_t>((items + 3) / 4, 4096);  // four items (waves) per workgroup
         hipLaunchKernelGGL(sb::generate_kernel, dim3((unsigned)grid), dim3(256), 0, handle->stream,

@@ -312,7 +312,7 @@ static sb_status gemv_n_typed(sb_handle* h, int64_t rows, int64_t cols, const T*
     if (p.nsplit > 65535)
         return fail(h, SB_EUNSUPPORTED, "gemv: rows of %lld elements need %lld column splits (at most 65535)",
                     (long long)cols, (long long)p.nsplit);
-    GemvNArgs<T> a{rows, cols, ld, A, x, c, p.nsplit > 1 ? static_cast<T*>(h->ws) : nullptr, p.KC, p.RB};
+    GemvNArgs<T> a{rows, cols, ld, A, x, c, p.nsplit > 1 ? static_cast<T*>(claim_ws(h)) : nullptr, p.KC, p.RB};
     const bool al = aligned16(A) && ((ld * (int64_t)sizeof(T)) % 16 == 0);
     const dim3 grid((unsigned)ceil_div(rows, p.RB), (unsigned)p.nsplit);
     const bool ok = al ? dispatch_n<T, true>(p.NT, p.G, a, grid, p.lds, h->stream)
@@ -332,7 +332,7 @@ static sb_status gemv_t_typed(sb_handle* h, int64_t rows, int64_t cols, const T*
     const GemvTPlan p = plan_gemv_t(sizeof(T), rows, cols, h->gemv_t_small_splits);
     if (p.ws > h->ws_bytes)
         return fail(h, SB_ENOMEM, "gemv needs %zu workspace bytes, handle has %zu", p.ws, h->ws_bytes);
-    GemvTArgs<T> a{rows, cols, ld, A, x, c, p.nsplit > 1 ? static_cast<T*>(h->ws) : nullptr, p.RS};
+    GemvTArgs<T> a{rows, cols, ld, A, x, c, p.nsplit > 1 ? static_cast<T*>(claim_ws(h)) : nullptr, p.RS};
     const bool al = aligned16(A) && ((ld * (int64_t)sizeof(T)) % 16 == 0);
     const int64_t CW = 64 * (al ? 16 / (int64_t)sizeof(T) : 1);
     const dim3 grid((unsigned)ceil_div(cols, CW), (unsigned)p.nsplit);

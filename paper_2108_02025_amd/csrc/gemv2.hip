@@ -343,7 +343,7 @@ static sb_status gemv2_typed(sb_handle* h, int64_t rows, int64_t cols, const T* 
     const Gemv2Plan p = plan_gemv2(sizeof(T), rows, cols);
     if (p.ws > h->ws_bytes)
         return fail(h, SB_ENOMEM, "gemv2 needs %zu workspace bytes, handle has %zu", p.ws, h->ws_bytes);
-    unsigned char* ws = static_cast<unsigned char*>(h->ws);
+    unsigned char* ws = static_cast<unsigned char*>(p.ws ? claim_ws(h) : h->ws);
     Gemv2Args<T> a{rows, cols, ld, M, vc, vr, out_r, out_c,
                    p.ncb > 1 ? reinterpret_cast<T*>(ws) : nullptr,
                    p.nsplit > 1 ? reinterpret_cast<T*>(ws + p.ws_c_offset) : nullptr, p.RS, p.nsplit};

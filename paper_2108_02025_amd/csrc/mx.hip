@@ -361,7 +361,7 @@ sb_status run_gemv_mx(sb_handle* h, sb_dtype q, int64_t m, int64_t n, const void
         return fail(h, SB_EUNSUPPORTED, "gemv_mx: rows of %lld elements need %lld column splits (at most 65535)",
                     (long long)n, (long long)p.nsplit);
     GemvMxArgs a{m, n, ldq, lds, static_cast<const uint8_t*>(Q), S, x, c,
-                 p.nsplit > 1 ? static_cast<float*>(h->ws) : nullptr, p.KC, p.RB};
+                 p.nsplit > 1 ? static_cast<float*>(claim_ws(h)) : nullptr, p.KC, p.RB};
     const dim3 grid((unsigned)ceil_div(m, p.RB), (unsigned)p.nsplit);
     const bool ok = fp4 ? dispatch_mx<true>(p.NT, p.G, a, grid, p.lds, h->stream)
                         : dispatch_mx<false>(p.NT, p.G, a, grid, p.lds, h->stream);

@@ -92,7 +92,7 @@ sb_status run_stream_read(sb_handle* h, const void* src, size_t bytes)
         return fail(h, SB_ENOMEM, "stream_read needs %zu workspace bytes, handle has %zu", (size_t)blocks * 16,
                     h->ws_bytes);
     hipLaunchKernelGGL(stream_read_kernel, dim3((unsigned)blocks), dim3(kProbeNT), 0, h->stream,
-                       static_cast<const v4u*>(src), n16, chunk, static_cast<v4u*>(h->ws));
+                       static_cast<const v4u*>(src), n16, chunk, static_cast<v4u*>(claim_ws(h)));
     return check_launch(h, "stream_read_kernel");
 }
 

@@ -239,7 +239,7 @@ sb_status run_gemv_q(sb_handle* h, sb_dtype q, int64_t m, int64_t n, const void*
     if (p.nsplit > 65535)
         return fail(h, SB_EUNSUPPORTED, "gemv_q: rows of %lld codes need %lld column splits (at most 65535)",
                     (long long)n, (long long)p.nsplit);
-    GemvQArgs a{m, n, ldq, Aq, scales, x, c, p.nsplit > 1 ? static_cast<float*>(h->ws) : nullptr, p.KC, p.RB};
+    GemvQArgs a{m, n, ldq, Aq, scales, x, c, p.nsplit > 1 ? static_cast<float*>(claim_ws(h)) : nullptr, p.KC, p.RB};
     const dim3 grid((unsigned)ceil_div(m, p.RB), (unsigned)p.nsplit);
     bool ok;
     if (q == SB_BF16)

@@ -11,6 +11,7 @@
 struct sb_handle {
     void* ws;
     size_t ws_bytes;
+    uint64_t ws_gen;  // advanced whenever a call writes the workspace (plans check it)
     hipStream_t stream;
     int64_t dot_small_bytes;      // SB_CUTOFF_DOT_SMALL_BYTES
     int64_t gemv_t_small_splits;  // SB_CUTOFF_GEMV_T_SMALL_SPLITS
@@ -18,6 +19,14 @@ struct sb_handle {
 };
 
 namespace sb {
+
+// The workspace for a call that writes it: advances the handle's workspace
+// generation, which invalidates a batched plan whose table lives there.
+inline void* claim_ws(sb_handle* h)
+{
+    ++h->ws_gen;
+    return h->ws;
+}
 
 // Record a formatted failure reason on the handle (or the thread-local
 // slot when h is NULL) and return `st`.

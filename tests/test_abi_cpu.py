@@ -173,6 +173,22 @@ def test_mx_validation_and_workspace(L, h):
     assert L.sb_gemv(h, 4, 0, 0, 4, 4, A_, 4, X_, C_) == -4          # MX types are storage only
 
 
+def test_plan_validation(L, h):
+    import paper_2108_02025_amd as sb
+    p = ctypes.c_void_p()
+    arr = (sb.sb_gemv_desc * 1)(_desc(sb, 1, 100, 100, A_, C_))
+    assert L.sb_plan_create(h, arr, 1, None) == -1
+    assert L.sb_plan_create(None, arr, 1, ctypes.byref(p)) == -1
+    assert L.sb_plan_create(h, arr, 1, ctypes.byref(p)) == -2 and not p.value   # no workspace
+    bad = (sb.sb_gemv_desc * 1)(_desc(sb, 1, 10, 10, A_, C_, group=3))
+    assert L.sb_plan_create(h, bad, 1, ctypes.byref(p)) == -1
+    empty = (sb.sb_gemv_desc * 1)(_desc(sb, 1, 0, 10, 0, 0, x=0))
+    assert L.sb_plan_create(h, empty, 1, ctypes.byref(p)) == 0 and p.value
+    assert L.sb_plan_run(p) == 0               # nothing to launch
+    assert L.sb_plan_destroy(p) == 0
+    assert L.sb_plan_run(None) == -1 and L.sb_plan_destroy(None) == 0
+
+
 def test_dot_ger_quant_validation(L, h):
     assert L.sb_dot(h, 0, -1, X_, A_, C_) == -1
     assert L.sb_dot(h, 0, 10, X_, A_, None) == -1

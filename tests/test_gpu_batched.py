@@ -171,3 +171,82 @@ def test_batched_rejects_bad_input(sb):
         sb.sb_gemv_batched_resolve([sb.GemvProblem(A, x, c, group=64, rows_per_tile=3)])
     r = sb.sb_gemv_batched_resolve([sb.GemvProblem(A, x, c)])
     assert r[0]["split"] == 1 and r[0]["group"] in (4, 8, 16, 32, 64)
+
+
+def test_plan_runs_match_batched_and_replay(sb):
+    """A plan gives the one-call batched results bit for bit, run after run
+    (each run adds A x again), also from a captured graph replayed with
+    eager work in between."""
+    rng = np.random.default_rng(77)
+    probs, hosts = [], []
+    for i in range(12):
+        m, n = int(rng.integers(1, 2000)), int(rng.integers(1, 12000))
+        P, H = make_problem(sb, rng, ["f64", "f32", "bf16", "e4m3"][i % 4], m, n, seed=300 + i)
+        probs.append(P)
+        hosts.append(H)
+    ref = [fresh_copy(sb, P, H) for P, H in zip(probs, hosts)]
+    for _ in range(3):
+        sb.sb_gemv_batched(ref)
+    want = [host(P.c).copy() for P in ref]
+    plan = sb.Plan(probs)
+    for _ in range(3):
+        plan.run()
+    assert all(np.array_equal(host(P.c), w) for P, w in zip(probs, want))
+    # graph replays: reset c, replay three times with eager GEMVs between
+    for P, H in zip(probs, hosts):
+        P.c.copy_(dev(H["c0"]))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.run()
+    torch.cuda.synchronize()
+    for P, H in zip(probs, hosts):
+        P.c.copy_(dev(H["c0"]))
+    other = torch.ones((300, 300), dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        g.replay()
+        sb.sb_gemv(other, torch.ones(300, dtype=torch.float64, device="cuda"),
+                   torch.zeros(300, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+    assert all(np.array_equal(host(P.c), w) for P, w in zip(probs, want))
+
+
+def test_plan_invalidated_by_workspace_writes(sb):
+    """Through the C-ABI: a call that writes the handle's workspace (a
+    two-stage DOT) makes sb_plan_run fail until the plan is made again; a
+    call that needs no workspace leaves it valid."""
+    import ctypes
+    L = sb.load()
+    rng = np.random.default_rng(5)
+    P, H = make_problem(sb, rng, "f32", 300, 700, seed=9)
+    descs = sb.make_descs([P])
+    total, _ = sb.sb_gemv_batched_table_bytes([P])
+    ws = torch.empty(max(total, 1 << 22), dtype=torch.uint8, device="cuda")
+    h = ctypes.c_void_p()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert L.sb_handle_create(ctypes.c_void_p(ws.data_ptr()), ws.numel(), stream, ctypes.byref(h)) == 0
+    p = ctypes.c_void_p()
+    try:
+        assert L.sb_plan_create(h, descs, 1, ctypes.byref(p)) == 0
+        assert L.sb_plan_run(p) == 0
+        x = torch.rand(1 << 20, dtype=torch.float64, device="cuda")
+        a = torch.zeros(1, dtype=torch.float64, device="cuda")
+        assert L.sb_dot(h, 0, 100, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                        ctypes.c_void_p(a.data_ptr())) == 0           # small: no workspace
+        assert L.sb_plan_run(p) == 0
+        assert L.sb_dot(h, 0, 1 << 20, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                        ctypes.c_void_p(a.data_ptr())) == 0           # two-stage: writes the workspace
+        assert L.sb_plan_run(p) == -1 and b"create the plan again" in L.sb_last_error(h)
+        assert L.sb_plan_destroy(p) == 0
+        assert L.sb_plan_create(h, descs, 1, ctypes.byref(p)) == 0 and L.sb_plan_run(p) == 0
+        torch.cuda.synchronize()
+        got = host(P.c).astype(np.float64)
+        ref = oracle.gemv(H["A"], H["x"], H["c0"])
+        ref = oracle.gemv(H["A"], H["x"], oracle.gemv(H["A"], H["x"], ref))   # three runs in all
+        assert_within(got, ref, 6 * gemv_bound(H["A"], H["x"], np.abs(H["c0"]) + 3 * np.abs(ref), 0, 700, U32), "plan")
+    finally:
+        L.sb_plan_destroy(p)
+        L.sb_handle_destroy(h)
