@@ -6,17 +6,21 @@ size, operands resident in HBM before timing starts:
 
   gemv_n_f64   c += A x,    A 16384 x 16384 binary64 row-major, uniform[-1,1)
   gemv_t_f64   c += A^T x,  same A
+  gemv2_f64    c += A x and d += A^T y in one pass over the same A
   dot_f64      alpha += x . y, n = 2^28 binary64
   ger_f64      C += x (outer) y, C 16384 x 16384 binary64
   gemv_q_bf16  c += diag(s) Q x, Q = bfloat16 codes of A (per-row scales), x binary32
   gemv_q_e4m3  the same with OCP E4M3FN codes
+  gemv_mx_fp8  c += A x with A as MXFP8 (E4M3 codes, one E8M0 scale per 32)
+  gemv_mx_fp4  the same with MXFP4 (E2M1 codes)
   dot2_f32     compensated binary32 dot, n = 2^27, condition number 1e8
 
 (quantisation of A is a one-off pre-step and is not timed).  ``value`` is the
 aggregate algorithmic HBM throughput of the step: the bytes each operation
 must move (every operand element touched once) summed over the step, divided
 by the step time.  Per-operation times come from HIP events recorded on the
-stream the library launches on.
+stream the library launches on, one between consecutive operations, created
+without the system-scope fence (``--fenced-events`` uses default events).
 
     python bench.py [--steps K] [--warmup W] [--no-cpu] [--ops a,b]
 """
@@ -161,25 +165,75 @@ def build_probes(sb, torch, dev):
             ("probe_copy", 2 * (8 << 28), 0, lambda: sb.sb_stream_copy(half, dst))]
 
 
-def time_ops(torch, ops, steps):
-    """Per-operation HIP-event times (us) over `steps` passes, and the total."""
-    ev = {n: [] for n, *_ in ops}
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
+class HipEvents:
+    """HIP timing events recorded on the stream the library launches on
+    (torch's current stream).  By default they are created with
+    hipEventDisableSystemFence: such an event only takes a GPU timestamp,
+    without the system-scope release (cache write-back and invalidation)
+    that a default event performs when it completes, whose cost would
+    otherwise fall into the window of the operation that follows it.
+    Kernels on the stream still run strictly one after another."""
+
+    DISABLE_SYSTEM_FENCE = 0x20000000
+
+    def __init__(self, torch, fence=False):
+        import ctypes
+
+        from paper_2108_02025_amd.build import torch_lib_dir
+        self.ct = ctypes
+        self.hip = ctypes.CDLL(os.path.join(torch_lib_dir(), "libamdhip64.so"))
+        self.hip.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+        self.hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.flags = 0 if fence else self.DISABLE_SYSTEM_FENCE
+        self.torch = torch
+        self.events = []
+
+    def _check(self, rc, what):
+        if rc != 0:
+            raise RuntimeError(f"{what} failed with HIP error {rc}")
+
+    def record(self):
+        ev = self.ct.c_void_p()
+        self._check(self.hip.hipEventCreateWithFlags(self.ct.byref(ev), self.flags), "hipEventCreateWithFlags")
+        self.events.append(ev)
+        stream = self.torch.cuda.current_stream().cuda_stream
+        self._check(self.hip.hipEventRecord(ev, self.ct.c_void_p(stream)), "hipEventRecord")
+        return ev
+
+    def ms(self, a, b):
+        out = self.ct.c_float()
+        self._check(self.hip.hipEventElapsedTime(self.ct.byref(out), a, b), "hipEventElapsedTime")
+        return out.value
+
+    def close(self):
+        for ev in self.events:
+            self.hip.hipEventDestroy(ev)
+        self.events = []
+
+
+def time_ops(torch, ops, steps, fence=False):
+    """Per-operation times (us) over `steps` passes, and the step time (ms).
+    One event is recorded between consecutive operations, so an operation's
+    window runs from the event before it to the event after it."""
+    ev = HipEvents(torch, fence)
+    per = {n: [] for n, *_ in ops}
     torch.cuda.synchronize()
-    t0.record()
+    marks = [ev.record()]
     for _ in range(steps):
         for name, _, _, fn in ops:
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record()
             fn()
-            b.record()
-            ev[name].append((a, b))
-    t1.record()
+            marks.append(ev.record())
     torch.cuda.synchronize()
-    per = {n: 1e3 * sum(a.elapsed_time(b) for a, b in v) / len(v) for n, v in ev.items()}
-    return per, t0.elapsed_time(t1) / steps
+    k = 0
+    for _ in range(steps):
+        for name, *_ in ops:
+            per[name].append(ev.ms(marks[k], marks[k + 1]))
+            k += 1
+    total = ev.ms(marks[0], marks[-1])
+    ev.close()
+    return {n: 1e3 * sum(v) / len(v) for n, v in per.items()}, total / steps
 
 
 def cpu_baseline(step_bytes, thread_counts=(1,)):
@@ -302,6 +356,8 @@ def main():
     ap.add_argument("--no-probes", action="store_true", help="skip the HBM read/copy ceiling probes")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
     ap.add_argument("--no-small", action="store_true", help="skip the small-problem latencies")
+    ap.add_argument("--fenced-events", action="store_true",
+                    help="time with default HIP events (system-scope release at every event)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -327,7 +383,7 @@ def main():
     torch.cuda.synchronize()
     log("warmup done")
 
-    us_per, ms_step = time_ops(torch, ops, args.steps)
+    us_per, ms_step = time_ops(torch, ops, args.steps, args.fenced_events)
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step")
 
     per = {}
@@ -350,7 +406,7 @@ def main():
         probes = build_probes(sb, torch, dev)
         for _, _, _, fn in probes:
             fn()
-        p_us, _ = time_ops(torch, probes, max(3, args.steps // 2))
+        p_us, _ = time_ops(torch, probes, max(3, args.steps // 2), args.fenced_events)
         ceil = {name: round(nb / p_us[name] / 1e3, 1) for name, nb, _, _ in probes}
         extras["hbm_ceiling_GBs"] = {"read": ceil["probe_read"], "copy": ceil["probe_copy"]}
         for name in per:
