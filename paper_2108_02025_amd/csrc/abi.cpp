@@ -353,8 +353,8 @@ sb_status sb_quantize_rows(sb_handle* handle, sb_dtype q, int64_t m, int64_t n, 
     if (lda < need || ldq < need) return fail(handle, SB_EINVAL, "sb_quantize_rows: lda/ldq below n");
     const int qs = esize_of(q);
     const int64_t a_el = span_elems(m, n, lda), q_el = span_elems(m, n, ldq);
-    int64_t t;
-    if (a_el < 0 || q_el < 0 || !mul_ok(a_el, 4, &t) || t > kMaxBytes)
+    int64_t t, tq;
+    if (a_el < 0 || q_el < 0 || !mul_ok(a_el, 4, &t) || t > kMaxBytes || !mul_ok(q_el, qs, &tq) || tq > kMaxBytes)
         return fail(handle, SB_EINVAL, "sb_quantize_rows: extent overflows");
     if ((a_el > 0 && (!A || !Aq)) || (m > 0 && !scales)) return fail(handle, SB_EINVAL, "sb_quantize_rows: NULL pointer");
     if (misaligned(A, 4) || misaligned(Aq, qs) || misaligned(scales, 4))

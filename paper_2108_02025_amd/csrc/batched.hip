@@ -205,11 +205,11 @@ __global__ __launch_bounds__(kBatNT, 4) void gemv_batched_kernel(const unsigned 
             const unsigned char* xg = static_cast<const unsigned char*>(p.x) + k0 * xs_size;
             const int64_t nbytes = klen * xs_size;
             if (((reinterpret_cast<uintptr_t>(xg) | (uintptr_t)nbytes) & 15) == 0) {
-                for (int64_t e = threadIdx.x; e < nbytes / 16; e += kBatNT)
-                    reinterpret_cast<v4u*>(xs)[e] = reinterpret_cast<const v4u*>(xg)[e];
+                stage_to_lds<kBatNT, 8>(reinterpret_cast<const v4u*>(xg), nbytes / 16,
+                                        [&](int64_t e, v4u v) { reinterpret_cast<v4u*>(xs)[e] = v; });
             } else {
-                for (int64_t e = threadIdx.x; e < nbytes / 4; e += kBatNT)
-                    reinterpret_cast<uint32_t*>(xs)[e] = reinterpret_cast<const uint32_t*>(xg)[e];
+                stage_to_lds<kBatNT, 16>(reinterpret_cast<const uint32_t*>(xg), nbytes / 4,
+                                         [&](int64_t e, uint32_t v) { reinterpret_cast<uint32_t*>(xs)[e] = v; });
             }
             __syncthreads();
             cached_p = pi;

@@ -47,6 +47,9 @@ namespace sb {
 #ifndef SB_GEMV_N_WAVES_PER_CU
 #define SB_GEMV_N_WAVES_PER_CU 32
 #endif
+#ifndef SB_GEMV_N_SPLIT_MIN_BYTES
+#define SB_GEMV_N_SPLIT_MIN_BYTES (32ll << 20)
+#endif
 #ifndef SB_GEMV_T_SMALL_SPLITS
 #define SB_GEMV_T_SMALL_SPLITS 2
 #endif
@@ -78,7 +81,7 @@ __global__ __launch_bounds__(NT) void gemv_n_kernel(GemvNArgs<T> a)
     const int64_t klen = min(a.cols, k0 + a.KC) - k0;
 
     // Stage x[k0, k0 + klen) in LDS (read by every row of this workgroup).
-    for (int64_t t = threadIdx.x; t < klen; t += NT) xs[t] = a.x[k0 + t];
+    stage_to_lds<NT>(a.x + k0, klen, [&](int64_t t, T v) { xs[t] = v; });
     __syncthreads();
 
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -200,18 +203,12 @@ constexpr int64_t kCUs = 256;                  // MI355X compute units
 constexpr int64_t kLdsPerCU = 160 * 1024;      // gfx950 LDS per compute unit
 constexpr int64_t kMaxStagedX = 128 * 1024;    // x bytes staged whole before splitting
 constexpr int64_t kSplitChunkBytes = 32 * 1024;
+constexpr int64_t kSplitFloorBytes = 16 * 1024;  // smallest chunk the few-rows split goes down to
 
-GemvNPlan plan_gemv_n(int esize, int64_t rows, int64_t cols)
+// Launch shape for a column chunk of KC elements (nsplit chunks per row).
+static void shape_gemv_n(GemvNPlan& p, int esize, int64_t rows)
 {
-    GemvNPlan p{};
     const int W = 16 / esize;
-    if (cols * esize <= kMaxStagedX) {
-        p.nsplit = 1;
-        p.KC = std::max<int64_t>(round_up(cols, W), W);
-    } else {
-        p.KC = kSplitChunkBytes / esize;
-        p.nsplit = ceil_div(cols, p.KC);
-    }
     p.lds = (size_t)round_up(p.KC * esize, 16);
     p.NT = p.lds > 80 * 1024 ? 1024 : (p.lds > 40 * 1024 ? 512 : 256);
     const int64_t waves_per_block = p.NT / 64;
@@ -225,6 +222,31 @@ GemvNPlan plan_gemv_n(int esize, int64_t rows, int64_t cols)
     const int64_t target = kCUs * bpc;
     const int64_t row_blocks = std::max<int64_t>(1, ceil_div(target, p.nsplit));
     p.RB = round_up(std::max<int64_t>(1, ceil_div(rows, row_blocks)), pass);
+}
+
+GemvNPlan plan_gemv_n(int esize, int64_t rows, int64_t cols)
+{
+    GemvNPlan p{};
+    const int W = 16 / esize;
+    if (cols * esize <= kMaxStagedX) {
+        p.nsplit = 1;
+        p.KC = std::max<int64_t>(round_up(cols, W), W);
+    } else {
+        p.KC = kSplitChunkBytes / esize;
+        p.nsplit = ceil_div(cols, p.KC);
+    }
+    shape_gemv_n(p, esize, rows);
+    // Few long rows: with one group per row there are fewer waves than the
+    // chip holds (16 per compute unit), so halve the column chunk until
+    // there are enough; the partial sums then go through the second stage.
+    // Only for operands large enough that the second launch pays off.
+    if (rows * cols * esize >= SB_GEMV_N_SPLIT_MIN_BYTES) {
+        while (ceil_div(rows * p.G, 64) * p.nsplit < kCUs * 16 && p.KC * esize > kSplitFloorBytes) {
+            p.KC = round_up(ceil_div(p.KC, 2), W);
+            p.nsplit = ceil_div(cols, p.KC);
+            shape_gemv_n(p, esize, rows);
+        }
+    }
     p.ws = p.nsplit > 1 ? (size_t)(p.nsplit * rows * esize) : 0;
     return p;
 }

@@ -108,7 +108,7 @@ __global__ __launch_bounds__(NT, SB_GEMVQ_MIN_WAVES) void gemv_q_kernel(GemvQArg
     const int64_t s = blockIdx.y;
     const int64_t k0 = s * a.KC;
     const int64_t klen = min(a.n, k0 + a.KC) - k0;
-    for (int64_t t = threadIdx.x; t < klen; t += NT) xs[t] = a.x[k0 + t];
+    stage_to_lds<NT>(a.x + k0, klen, [&](int64_t t, float v) { xs[t] = v; });
     __syncthreads();
 
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;

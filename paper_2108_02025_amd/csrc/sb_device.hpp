@@ -35,6 +35,32 @@ __device__ __forceinline__ void st_stream(V* p, V v)
     else *p = v;
 }
 
+// Copy n elements of a vector from global memory into LDS (put(t, v) stores
+// element t), SU loads in flight per thread: a plain strided loop waits for
+// each load before the next, which at 16 or 32 elements per thread made the
+// staging of x a visible fixed cost of every GEMV call.  The caller
+// synchronises the workgroup afterwards.
+#ifndef SB_STAGE_UNROLL
+#define SB_STAGE_UNROLL 16
+#endif
+template <int NT, int SU = SB_STAGE_UNROLL, typename T, typename F>
+__device__ __forceinline__ void stage_to_lds(const T* __restrict__ src, int64_t n, F put)
+{
+    for (int64_t base = 0; base < n; base += (int64_t)SU * NT) {
+        T v[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int64_t t = base + (int64_t)u * NT + threadIdx.x;
+            v[u] = t < n ? src[t] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int64_t t = base + (int64_t)u * NT + threadIdx.x;
+            if (t < n) put(t, v[u]);
+        }
+    }
+}
+
 // Separately rounded multiply / add / subtract.  Contraction into fused
 // multiply-add is switched off inside each helper, so the operation keeps
 // its own rounding even after inlining next to an addition (the default

@@ -81,6 +81,13 @@ def test_gemv_validation(L, h):
 def test_workspace_sizing_and_enomem(L, h):
     ws = L.sb_workspace_bytes
     assert ws(None, 0, 0, 0, 0, 1024, 1024) == 0          # x fits in LDS: no split
+    # few long rows (operand >= 32 MiB): columns split until there are 16
+    # waves per compute unit, in chunks of at least 16 KiB
+    assert ws(None, 0, 0, 0, 0, 1024, 16384) == 4 * 1024 * 8
+    assert ws(None, 0, 0, 0, 0, 512, 16384) == 8 * 512 * 8
+    assert ws(None, 0, 0, 0, 0, 4096, 16384) == 0
+    assert ws(None, 0, 0, 0, 0, 1024, 4095) == 0          # 32 MiB minus a column: not split
+    assert ws(None, 0, 0, 1, 1, 16384, 1024) == 4 * 1024 * 8   # column-major T: same plan
     short_wide = ws(None, 0, 0, 0, 0, 256, 262144)
     assert short_wide > 0 and short_wide % (256 * 8) == 0
     assert ws(None, 0, 0, 1, 1, 262144, 256) == short_wide  # column-major T: same kernel and plan

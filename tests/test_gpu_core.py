@@ -76,6 +76,24 @@ def test_gemv_edge_sizes(sb, dt, op, m, n):
 
 
 @pytest.mark.parametrize("dt", [0, 1])
+@pytest.mark.parametrize("m,n", [(512, 16384), (1024, 16384), (1000, 20001), (2048, 16384)])
+def test_gemv_few_long_rows_split(sb, dt, m, n):
+    """Few rows of a large operand: the row-dot plan splits the columns so
+    that every compute unit has waves (partial sums, then the ordered second
+    stage).  Row-major N and column-major T take that path."""
+    npd = NP[dt]
+    assert sb.sb_workspace_bytes(sb.SB_KIND_GEMV, dt, 0, 0, m, n) > 0, "expected a column split"
+    A, x, c0 = workloads.gemv_inputs(m, n, seed=m + n, dist="normal", dtype=npd)
+    ref = oracle.gemv(A, x, c0)
+    got = run_gemv(sb, A, x, c0, 0, 0)
+    assert_within(got, ref, gemv_bound(A, x, c0, 0, n, U64 if dt == 0 else U32), f"{m}x{n}")
+    got_t = run_gemv(sb, np.ascontiguousarray(A.T), x, c0, 1, 1)  # column-major T of A^T
+    assert np.array_equal(got_t, got)
+    Ai, xi, ci = workloads.gemv_inputs(m, n, seed=5, dist="int7" if dt else "int8", dtype=npd)
+    assert np.array_equal(run_gemv(sb, Ai, xi, ci, 0, 0), oracle.gemv(Ai, xi, ci))
+
+
+@pytest.mark.parametrize("dt", [0, 1])
 def test_gemv_layout_equivalence_bitwise(sb, dt):
     """(row-major, N) and (column-major, T) on one buffer are the same
     computation; so are (row-major, T) and (column-major, N)."""
