@@ -352,7 +352,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--ops", default=None, help="comma-separated subset of operations")
+    ap.add_argument("--ops", default=None, help="comma-separated subset of operations, in step order")
     ap.add_argument("--no-probes", action="store_true", help="skip the HBM read/copy ceiling probes")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
     ap.add_argument("--no-small", action="store_true", help="skip the small-problem latencies")
@@ -374,6 +374,9 @@ def main():
     torch.cuda.set_device(dev)
     sel = set(args.ops.split(",")) if args.ops else None
     ops = build_ops(sb, torch, dev, sel)
+    if args.ops:  # run in the order given
+        order = args.ops.split(",")
+        ops.sort(key=lambda o: order.index(o[0]))
     names = [o[0] for o in ops]
     log(f"ops: {names}; warmup {args.warmup}, steps {args.steps}")
 

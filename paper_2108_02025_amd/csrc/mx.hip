@@ -230,7 +230,7 @@ __global__ __launch_bounds__(NT, SB_GEMVMX_MIN_WAVES) void gemv_mx_kernel(GemvMx
     const int64_t k0 = s * a.KC;
     const int64_t klen = min(a.n, k0 + a.KC) - k0;
     const int64_t NVC = (klen + P - 1) / P;
-    for (int64_t t = threadIdx.x; t < klen; t += NT) xs[xs_slot<P>(t, NVC)] = a.x[k0 + t];
+    stage_to_lds<NT>(a.x + k0, klen, [&](int64_t t, float v) { xs[xs_slot<P>(t, NVC)] = v; });
     __syncthreads();
 
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
