@@ -26,6 +26,9 @@
 #include "sb_internal.hpp"
 #include "sb_quant.hpp"
 
+#ifndef SB_GEMVMX_TOUCH_SCALES
+#define SB_GEMVMX_TOUCH_SCALES 1
+#endif
 #ifndef SB_GEMVMX_UNROLL_FP8
 #define SB_GEMVMX_UNROLL_FP8 8
 #endif
@@ -230,13 +233,25 @@ __global__ __launch_bounds__(NT, SB_GEMVMX_MIN_WAVES) void gemv_mx_kernel(GemvMx
     const int64_t k0 = s * a.KC;
     const int64_t klen = min(a.n, k0 + a.KC) - k0;
     const int64_t NVC = (klen + P - 1) / P;
+    const int64_t r0 = (int64_t)blockIdx.x * a.RB;
+    const int64_t r1 = min(a.m, r0 + a.RB);
+
+    // Read one byte of every 64 of this workgroup's block scales (one load
+    // per thread at most) before staging x, so that the row loop finds
+    // them in L2: after other kernels have filled the caches, their first
+    // reads would otherwise wait on HBM inside the loop.
+    uint32_t touch = 0;
+    {
+        const int64_t sbytes = (klen + 31) / 32, per_row = (sbytes + 63) / 64;
+        const int64_t i = threadIdx.x, row = r0 + i / per_row;
+        if (SB_GEMVMX_TOUCH_SCALES && i < (r1 - r0) * per_row) touch = a.S[row * a.lds + k0 / 32 + (i % per_row) * 64];
+    }
     stage_to_lds<NT>(a.x + k0, klen, [&](int64_t t, float v) { xs[xs_slot<P>(t, NVC)] = v; });
     __syncthreads();
+    if (a.m < 0) a.c[0] = (float)touch;  // never taken (m >= 0): keeps the loads
 
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int g = lane / G, l = lane % G;
-    const int64_t r0 = (int64_t)blockIdx.x * a.RB;
-    const int64_t r1 = min(a.m, r0 + a.RB);
     const int64_t qoff = FP4 ? k0 / 2 : k0;  // k0 is a multiple of 32
     for (int64_t row = r0 + w * GW + g; row < r1; row += NW * GW) {
         float t = mx_row_dot<FP4, G, U>(a.Q + row * a.ldq + qoff, a.S + row * a.lds + k0 / 32, klen, xs, NVC, l);
