@@ -290,9 +290,15 @@ __global__ __launch_bounds__(256) void gemv2_finish_kernel(int64_t rows, int64_t
                                                            int64_t nsplit, const T* part_r,
                                                            const T* part_c, T* out_r, T* out_c)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (part_r && i < rows) out_r[i] = out_r[i] + ordered_split_sum<16>(part_r + i, ncb, rows);
-    if (part_c && i < cols) out_c[i] = out_c[i] + ordered_split_sum<16>(part_c + i, nsplit, cols);
+    // the first ceil(rows/256) workgroups finish out_r, the rest out_c
+    const int64_t rb = (rows + 255) / 256;
+    if ((int64_t)blockIdx.x < rb) {
+        const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+        if (part_r && i < rows) out_r[i] = out_r[i] + ordered_split_sum<16>(part_r + i, ncb, rows);
+    } else {
+        const int64_t j = ((int64_t)blockIdx.x - rb) * 256 + threadIdx.x;
+        if (part_c && j < cols) out_c[j] = out_c[j] + ordered_split_sum<16>(part_c + j, nsplit, cols);
+    }
 }
 
 // ---------------------------------------------------------------- plans ---
@@ -343,6 +349,8 @@ static sb_status gemv2_typed(sb_handle* h, int64_t rows, int64_t cols, const T* 
     const Gemv2Plan p = plan_gemv2(sizeof(T), rows, cols);
     if (p.ws > h->ws_bytes)
         return fail(h, SB_ENOMEM, "gemv2 needs %zu workspace bytes, handle has %zu", p.ws, h->ws_bytes);
+    if (p.ncb > 0x7FFFFFFF || ceil_div(rows, 256) + ceil_div(cols, 256) > ((int64_t)1 << 23))
+        return fail(h, SB_EUNSUPPORTED, "gemv2: %lld x %lld exceeds the launch grid", (long long)rows, (long long)cols);
     unsigned char* ws = static_cast<unsigned char*>(p.ws ? claim_ws(h) : h->ws);
     Gemv2Args<T> a{rows, cols, ld, M, vc, vr, out_r, out_c,
                    p.ncb > 1 ? reinterpret_cast<T*>(ws) : nullptr,
@@ -358,7 +366,7 @@ static sb_status gemv2_typed(sb_handle* h, int64_t rows, int64_t cols, const T* 
     }
     sb_status st = check_launch(h, "gemv2_kernel");
     if (st != SB_OK || (p.ncb == 1 && p.nsplit == 1)) return st;
-    hipLaunchKernelGGL(gemv2_finish_kernel<T>, dim3((unsigned)ceil_div(std::max(rows, cols), 256)), dim3(256), 0,
+    hipLaunchKernelGGL(gemv2_finish_kernel<T>, dim3((unsigned)(ceil_div(rows, 256) + ceil_div(cols, 256))), dim3(256), 0,
                        h->stream, rows, cols, p.ncb, p.nsplit, static_cast<const T*>(a.part_r),
                        static_cast<const T*>(a.part_c), out_r, out_c);
     return check_launch(h, "gemv2_finish_kernel");

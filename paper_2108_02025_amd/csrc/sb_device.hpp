@@ -126,22 +126,21 @@ __device__ __forceinline__ T block_sum(T v, T* lds)
 
 // p[0] + p[stride] + ... + p[(ns - 1) * stride], added in order of the
 // index (so the bits do not depend on how the loads are scheduled), with
-// the loads issued AHEAD at a time before their additions: split partial
-// sums were just written and sit in L2, where a chain of dependent loads
-// would cost one L2 latency per split.
+// the loads issued AHEAD at a time before their additions, the last batch
+// predicated: split partial sums were just written and sit in L2, where a
+// chain of dependent loads would cost one L2 latency per split.
 template <int AHEAD = 8, typename T>
 __device__ __forceinline__ T ordered_split_sum(const T* p, int64_t ns, int64_t stride)
 {
     T t = p[0];
-    int64_t s = 1;
-    for (; s + AHEAD <= ns; s += AHEAD) {
+    for (int64_t s = 1; s < ns; s += AHEAD) {
         T v[AHEAD];
 #pragma unroll
-        for (int u = 0; u < AHEAD; ++u) v[u] = p[(s + u) * stride];
+        for (int u = 0; u < AHEAD; ++u) v[u] = s + u < ns ? p[(s + u) * stride] : T(0);
 #pragma unroll
-        for (int u = 0; u < AHEAD; ++u) t += v[u];
+        for (int u = 0; u < AHEAD; ++u)
+            if (s + u < ns) t += v[u];
     }
-    for (; s < ns; ++s) t += p[s * stride];
     return t;
 }
 
