@@ -5,11 +5,14 @@
 // the GPU the analogous fixed cost is a kernel launch, so a batch of
 // problems shares one launch: every problem is cut into tiles of RT rows x KC
 // columns (KC covering all of n unless the problem is split along its
-// columns), the tiles of all problems are numbered consecutively, and a
-// fixed grid of workgroups takes contiguous ranges of tile numbers.  A tile
-// stages its x chunk in LDS (kept if the workgroup's
-// next tile uses the same chunk) and runs the same per-row dot products as
-// the single-call kernels.
+// columns), and runs of consecutive tiles of one problem form work items.
+// The host deals the items to the workgroups of a persistent grid, largest
+// first, each to the workgroup with the least work so far (the
+// longest-processing-time-first rule), so the workgroups finish together
+// whatever the mix of shapes, without any counter traffic on the device.
+// A tile stages its x chunk in LDS (kept if the workgroup's next tile uses
+// the same chunk) and runs the same per-row dot products as the single-call
+// kernels.
 //
 // A problem split into S column chunks writes per-split partial sums to
 // scratch; the tile that completes a row tile (a per-row-tile counter
@@ -18,14 +21,16 @@
 // tile, split) configuration, never on the rest of the batch or on which
 // workgroup ran it: a problem gives the same bits alone and in a mix.
 //
-// The table (header, problem records, zeroed counters) is encoded on the
-// host and copied to device memory before the launch; the kernel reads the
-// tile count from it, so a captured launch can be replayed over new tables
-// written to the same address.
+// The table (header, problem records, work items grouped by workgroup,
+// zeroed split counters) is encoded on the host and copied to device memory
+// before the launch; the kernel reads everything it needs from it, so a
+// captured launch can be replayed over new tables written to the same
+// address.
 #include <string.h>
 
 #include <algorithm>
 #include <new>
+#include <queue>
 #include <vector>
 
 #include "sb_device.hpp"
@@ -37,10 +42,28 @@ namespace sb {
 constexpr int kBatNT = 256;
 constexpr int kBatWaves = kBatNT / kWave;
 constexpr int64_t kBatLds = 32 * 1024;     // x chunk bytes per tile
+// Automatic tile height: about SB_BAT_TILE_BYTES of A per tile, and at most
+// SB_BAT_MAX_PASSES row passes of the workgroup (a pass: the rows its groups
+// take at once), since short rows are latency-bound per pass.
 #ifndef SB_BAT_TILE_BYTES
 #define SB_BAT_TILE_BYTES (256 * 1024)
 #endif
-constexpr int64_t kBatTileBytes = SB_BAT_TILE_BYTES;  // automatic tile size target (bytes of A)
+#ifndef SB_BAT_ITEMS_PER_WG
+#define SB_BAT_ITEMS_PER_WG 4
+#endif
+#ifndef SB_BAT_MAX_PASSES
+#define SB_BAT_MAX_PASSES 8
+#endif
+// Cost of a tile for the division of the work: its bytes of A, a fixed
+// SB_BAT_TILE_COST for the set-up and x staging, and SB_BAT_PASS_COST per row
+// pass (one memory latency each).
+#ifndef SB_BAT_TILE_COST
+#define SB_BAT_TILE_COST 4096
+#endif
+#ifndef SB_BAT_PASS_COST
+#define SB_BAT_PASS_COST 8192
+#endif
+constexpr int64_t kBatTileBytes = SB_BAT_TILE_BYTES;  // largest automatic tile (bytes of A)
 #ifndef SB_BAT_UNROLL_PLAIN
 #define SB_BAT_UNROLL_PLAIN 8
 #endif
@@ -61,7 +84,12 @@ struct BatHeader {
     int64_t count;
     int64_t ntiles;
     int64_t total_cost;  // sum of tile costs, KiB units
-    int64_t pad[5];
+    int64_t nitems;      // work items
+    int64_t items_off;   // byte offset of the work items (grouped by workgroup)
+    int64_t lists_off;   // byte offset of grid + 1 int32 offsets: workgroup b's items are [off[b], off[b + 1])
+    int32_t grid;        // workgroups the items were dealt to
+    int32_t pad;
+    int64_t pad2;
 };
 
 struct BatProblem {
@@ -78,27 +106,16 @@ struct BatProblem {
     int32_t aligned, pad;
     int64_t pad2;
 };
+
+// Tiles [first, first + count) (numbered within the problem) of one problem.
+struct BatItem {
+    int32_t problem;
+    int32_t count;
+    int64_t first;
+};
 static_assert(sizeof(BatHeader) == 64, "header layout");
 static_assert(sizeof(BatProblem) == 144, "problem record layout");
-
-// The first tile whose start cost is at least C (tile start costs increase
-// strictly: each tile costs at least the fixed per-tile overhead).
-__device__ __forceinline__ int64_t first_tile_at_cost(const BatProblem* probs, int64_t count, int64_t ntiles,
-                                                      int64_t total, int64_t C)
-{
-    if (C >= total) return ntiles;
-    int64_t lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (probs[mid].cost0 <= C) lo = mid;
-        else hi = mid - 1;
-    }
-    const BatProblem& p = probs[lo];
-    const int64_t tiles = p.rtiles * p.S;
-    int64_t local = p.tile_cost > 0 ? (C - p.cost0 + p.tile_cost - 1) / p.tile_cost : 0;
-    if (local > tiles) local = tiles;
-    return p.tile0 + local;
-}
+static_assert(sizeof(BatItem) == 16, "work item layout");
 
 // Rows [r0, r1) of one tile, per-row results to c or to the split partials.
 // Not inlined: each (dtype, group, alignment) variant gets its own register
@@ -169,82 +186,70 @@ __global__ __launch_bounds__(kBatNT, 4) void gemv_batched_kernel(const unsigned 
     __shared__ int last_flag;
     const BatHeader* hdr = reinterpret_cast<const BatHeader*>(table);
     const BatProblem* probs = reinterpret_cast<const BatProblem*>(table + sizeof(BatHeader));
-    const int64_t count = hdr->count, ntiles = hdr->ntiles, total = hdr->total_cost;
+    const BatItem* items = reinterpret_cast<const BatItem*>(table + hdr->items_off);
+    const int32_t* lists = reinterpret_cast<const int32_t*>(table + hdr->lists_off);
+    const int64_t dealt = hdr->grid;
     int64_t cached_p = -1, cached_s = -1;
-    // Workgroup b takes the tiles whose start cost lies in
-    // [b*C/grid, (b+1)*C/grid): contiguous tile ranges of equal bytes, so
-    // consecutive tiles of one problem also reuse the staged x chunk.
-    const int64_t t_begin = first_tile_at_cost(probs, count, ntiles, total, (int64_t)blockIdx.x * total / gridDim.x);
-    const int64_t t_end = first_tile_at_cost(probs, count, ntiles, total,
-                                             ((int64_t)blockIdx.x + 1) * total / gridDim.x);
 
-    if (t_begin >= t_end) return;
-    // One search for the problem owning the first tile; later tiles of the
-    // contiguous range advance through the records in order.
-    int64_t pi = 0;
-    {
-        int64_t lo = 0, hi = count - 1;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi + 1) >> 1;
-            if (probs[mid].tile0 <= t_begin) lo = mid;
-            else hi = mid - 1;
-        }
-        pi = lo;
-    }
-    BatProblem p = probs[pi];
-    for (int64_t t = t_begin; t < t_end; ++t) {
-        while (t >= p.tile0 + p.rtiles * p.S) p = probs[++pi];  // skips problems without tiles
-        const int64_t local = t - p.tile0;
-        const int64_t s = local % p.S, rt = local / p.S;
-        const int64_t r0 = rt * p.RT, r1 = min(p.m, r0 + p.RT);
-        const int64_t k0 = s * p.KC, klen = min(p.n, k0 + p.KC) - k0;
+    // This workgroup's lists: its own, and those of workgroups beyond the
+    // grid when the grid is smaller than the one the items were dealt to.
+    for (int64_t b = blockIdx.x; b < dealt; b += gridDim.x)
+    for (int64_t item = lists[b]; item < lists[b + 1]; ++item) {
+        const BatItem it = items[item];
+        const int64_t pi = it.problem;
+        const BatProblem p = probs[pi];
+        for (int64_t local = it.first; local < it.first + it.count; ++local) {
+            const int64_t s = local % p.S, rt = local / p.S;
+            const int64_t r0 = rt * p.RT, r1 = min(p.m, r0 + p.RT);
+            const int64_t k0 = s * p.KC, klen = min(p.n, k0 + p.KC) - k0;
 
-        if (pi != cached_p || s != cached_s) {
-            __syncthreads();  // every row of the previous tile has read x
-            const int xs_size = p.dtype == SB_F64 ? 8 : 4;
-            const unsigned char* xg = static_cast<const unsigned char*>(p.x) + k0 * xs_size;
-            const int64_t nbytes = klen * xs_size;
-            if (((reinterpret_cast<uintptr_t>(xg) | (uintptr_t)nbytes) & 15) == 0) {
-                stage_to_lds<kBatNT, 8>(reinterpret_cast<const v4u*>(xg), nbytes / 16,
-                                        [&](int64_t e, v4u v) { reinterpret_cast<v4u*>(xs)[e] = v; });
-            } else {
-                stage_to_lds<kBatNT, 16>(reinterpret_cast<const uint32_t*>(xg), nbytes / 4,
-                                         [&](int64_t e, uint32_t v) { reinterpret_cast<uint32_t*>(xs)[e] = v; });
+            if (pi != cached_p || s != cached_s) {
+                __syncthreads();  // every row of the previous tile has read x
+                const int xs_size = p.dtype == SB_F64 ? 8 : 4;
+                const unsigned char* xg = static_cast<const unsigned char*>(p.x) + k0 * xs_size;
+                const int64_t nbytes = klen * xs_size;
+                if (((reinterpret_cast<uintptr_t>(xg) | (uintptr_t)nbytes) & 15) == 0) {
+                    stage_to_lds<kBatNT, 8>(reinterpret_cast<const v4u*>(xg), nbytes / 16,
+                                            [&](int64_t e, v4u v) { reinterpret_cast<v4u*>(xs)[e] = v; });
+                } else {
+                    stage_to_lds<kBatNT, 16>(reinterpret_cast<const uint32_t*>(xg), nbytes / 4,
+                                             [&](int64_t e, uint32_t v) { reinterpret_cast<uint32_t*>(xs)[e] = v; });
+                }
+                __syncthreads();
+                cached_p = pi;
+                cached_s = s;
             }
-            __syncthreads();
-            cached_p = pi;
-            cached_s = s;
-        }
 
-        switch (p.dtype) {
-        case SB_F64:
-            if (p.aligned) bat_rows_g<SB_F64, true>(p, s, r0, r1, k0, klen, xs);
-            else bat_rows_g<SB_F64, false>(p, s, r0, r1, k0, klen, xs);
-            break;
-        case SB_F32:
-            if (p.aligned) bat_rows_g<SB_F32, true>(p, s, r0, r1, k0, klen, xs);
-            else bat_rows_g<SB_F32, false>(p, s, r0, r1, k0, klen, xs);
-            break;
-        case SB_BF16: bat_rows_g<SB_BF16, false>(p, s, r0, r1, k0, klen, xs); break;
-        default: bat_rows_g<SB_FP8_E4M3, false>(p, s, r0, r1, k0, klen, xs); break;
-        }
-
-        if (p.S > 1) {
-            // Publish this split's partials; the tile that completes the row
-            // tile adds all splits in order.
-            __threadfence();
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                last_flag = atomicAdd(&p.counters[rt], 1) == p.S - 1;
-                // every split of this row tile has arrived: rearm the counter
-                // so the same table can be launched again
-                if (last_flag) atomicExch(&p.counters[rt], 0);
+            switch (p.dtype) {
+            case SB_F64:
+                if (p.aligned) bat_rows_g<SB_F64, true>(p, s, r0, r1, k0, klen, xs);
+                else bat_rows_g<SB_F64, false>(p, s, r0, r1, k0, klen, xs);
+                break;
+            case SB_F32:
+                if (p.aligned) bat_rows_g<SB_F32, true>(p, s, r0, r1, k0, klen, xs);
+                else bat_rows_g<SB_F32, false>(p, s, r0, r1, k0, klen, xs);
+                break;
+            case SB_BF16: bat_rows_g<SB_BF16, false>(p, s, r0, r1, k0, klen, xs); break;
+            default: bat_rows_g<SB_FP8_E4M3, false>(p, s, r0, r1, k0, klen, xs); break;
             }
-            __syncthreads();
-            if (last_flag) {
+
+            if (p.S > 1) {
+                // Publish this split's partials; the tile that completes the
+                // row tile adds all splits in order.
                 __threadfence();
-                if (p.dtype == SB_F64) bat_finish<double>(p, r0, r1);
-                else bat_finish<float>(p, r0, r1);
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    last_flag = atomicAdd(&p.counters[rt], 1) == p.S - 1;
+                    // every split of this row tile has arrived: rearm the
+                    // counter so the same table can be launched again
+                    if (last_flag) atomicExch(&p.counters[rt], 0);
+                }
+                __syncthreads();
+                if (last_flag) {
+                    __threadfence();
+                    if (p.dtype == SB_F64) bat_finish<double>(p, r0, r1);
+                    else bat_finish<float>(p, r0, r1);
+                }
             }
         }
     }
@@ -293,6 +298,7 @@ static bool resolve(const sb_gemv_desc& in, sb_gemv_desc& out, int64_t* KC, int6
     if (RT == 0) {
         const int64_t row_bytes = std::max<int64_t>(1, std::min<int64_t>(kc, in.n)) * es;
         RT = std::max<int64_t>(pass, (tile_bytes / row_bytes) / pass * pass);
+        RT = std::min<int64_t>(RT, (int64_t)SB_BAT_MAX_PASSES * pass);
         RT = std::min<int64_t>(RT, round_up(std::max<int64_t>(in.m, 1), pass));
     } else if (RT % pass) {
         snprintf(why, whylen, "rows_per_tile %lld is not a multiple of %lld", (long long)RT, (long long)pass);
@@ -308,9 +314,11 @@ static bool resolve(const sb_gemv_desc& in, sb_gemv_desc& out, int64_t* KC, int6
 
 struct BatLayout {
     std::vector<sb_gemv_desc> res;
-    std::vector<int64_t> kc, tiles, rtiles, counter_off, partial_off;
-    size_t image = 0, total = 0;
-    int64_t ntiles = 0;
+    std::vector<int64_t> kc, tiles, rtiles, tile_cost, counter_off, partial_off;
+    std::vector<BatItem> items;
+    std::vector<int32_t> lists;  // grid + 1 offsets into items
+    size_t image = 0, total = 0, items_off = 0, lists_off = 0;
+    int64_t ntiles = 0, total_cost = 0;
 };
 
 static sb_status layout(const sb_gemv_desc* d, int32_t count, BatLayout& L, char* why, size_t whylen)
@@ -323,12 +331,11 @@ static sb_status layout(const sb_gemv_desc* d, int32_t count, BatLayout& L, char
     L.kc.resize(count);
     L.tiles.resize(count);
     L.rtiles.resize(count);
+    L.tile_cost.resize(count);
     L.counter_off.resize(count);
     L.partial_off.resize(count);
-    size_t off = sizeof(BatHeader) + (size_t)count * sizeof(BatProblem);
-    // Automatic tile height: about 256 KiB of A per tile (measured better
-    // than smaller, better balanced tiles: the per-tile set-up costs more than
-    // the imbalance).  The rows of a tile never change a row's arithmetic.
+    // The rows of a tile never change a row's arithmetic, so results do not
+    // depend on the tile size.
     const int64_t tile_bytes = kBatTileBytes;
     for (int32_t i = 0; i < count; ++i) {
         const sb_gemv_desc& in = d[i];
@@ -355,14 +362,76 @@ static sb_status layout(const sb_gemv_desc* d, int32_t count, BatLayout& L, char
             snprintf(why, whylen, "descriptor %d: %s", i, sub);
             return SB_EINVAL;
         }
-        const int64_t rt = (in.m == 0 || in.n == 0) ? 0 : ceil_div(in.m, L.res[i].rows_per_tile);
+        const sb_gemv_desc& r = L.res[i];
+        const int64_t rt = (in.m == 0 || in.n == 0) ? 0 : ceil_div(in.m, r.rows_per_tile);
         L.rtiles[i] = rt;
-        L.tiles[i] = rt * L.res[i].split;
+        L.tiles[i] = rt * r.split;
         L.ntiles += L.tiles[i];
+        // tile cost: its bytes of A, the set-up and x staging, and one
+        // memory latency per row pass
+        const int64_t a_bytes = (int64_t)r.rows_per_tile * std::min<int64_t>(L.kc[i], in.n) * es;
+        const int64_t passes = ceil_div(r.rows_per_tile, (int64_t)kBatWaves * (64 / r.group));
+        L.tile_cost[i] = L.tiles[i] > 0 ? (a_bytes + SB_BAT_TILE_COST + passes * SB_BAT_PASS_COST + 1023) / 1024 : 0;
+        L.total_cost += L.tile_cost[i] * L.tiles[i];
+    }
+    // Work items: runs of consecutive tiles of one problem costing about
+    // 1/SB_BAT_ITEMS_PER_WG of a workgroup's share of the batch.  They are
+    // dealt largest first, each to the workgroup with the least cost so far
+    // (ties to the lowest index); a workgroup's items then run in problem
+    // and tile order, so consecutive tiles of one problem reuse the staged x.
+    const int64_t grid = kBatGrid;
+    const int64_t target = std::max<int64_t>(1, L.total_cost / ((int64_t)SB_BAT_ITEMS_PER_WG * grid));
+    std::vector<BatItem> items;
+    for (int32_t i = 0; i < count; ++i) {
+        if (L.tiles[i] == 0) continue;
+        const int64_t per = std::min<int64_t>(std::max<int64_t>(1, target / L.tile_cost[i]), (int64_t)1 << 30);
+        for (int64_t first = 0; first < L.tiles[i]; first += per)
+            items.push_back(BatItem{i, (int32_t)std::min<int64_t>(per, L.tiles[i] - first), first});
+    }
+    if (items.size() > ((size_t)1 << 30)) {
+        snprintf(why, whylen, "too many work items");
+        return SB_EINVAL;
+    }
+    auto item_cost = [&](const BatItem& a) { return a.count * L.tile_cost[a.problem]; };
+    std::stable_sort(items.begin(), items.end(),
+                     [&](const BatItem& a, const BatItem& b) { return item_cost(a) > item_cost(b); });
+    typedef std::pair<int64_t, int32_t> Load;  // (cost so far, workgroup); stale entries skipped
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+    std::vector<int64_t> load(grid, 0);
+    for (int32_t b = 0; b < (int32_t)grid; ++b) heap.push({0, b});
+    std::vector<int32_t> owner(items.size());
+    std::vector<int32_t> per_wg(grid + 1, 0);
+    for (size_t j = 0; j < items.size(); ++j) {
+        const int64_t c = item_cost(items[j]);
+        while (heap.top().first != load[heap.top().second]) heap.pop();  // skip stale entries
+        const int32_t b = heap.top().second;
+        owner[j] = b;
+        ++per_wg[b + 1];
+        load[b] += c;
+        heap.push({load[b], b});
+    }
+    L.lists.assign(per_wg.begin(), per_wg.end());
+    for (int64_t b = 0; b < grid; ++b) L.lists[b + 1] += L.lists[b];
+    L.items.resize(items.size());
+    {
+        std::vector<int32_t> fill(L.lists.begin(), L.lists.end() - 1);
+        for (size_t j = 0; j < items.size(); ++j) L.items[fill[owner[j]]++] = items[j];
+        for (int64_t b = 0; b < grid; ++b)
+            std::sort(L.items.begin() + L.lists[b], L.items.begin() + L.lists[b + 1],
+                      [](const BatItem& a, const BatItem& c) {
+                          return a.problem != c.problem ? a.problem < c.problem : a.first < c.first;
+                      });
+    }
+    size_t off = sizeof(BatHeader) + (size_t)count * sizeof(BatProblem);
+    L.items_off = off;
+    off += L.items.size() * sizeof(BatItem);
+    L.lists_off = off;
+    off += L.lists.size() * sizeof(int32_t);
+    for (int32_t i = 0; i < count; ++i) {
         L.counter_off[i] = -1;
-        if (L.res[i].split > 1 && rt > 0) {
+        if (L.res[i].split > 1 && L.rtiles[i] > 0) {
             L.counter_off[i] = (int64_t)off;
-            off += (size_t)rt * sizeof(int32_t);
+            off += (size_t)L.rtiles[i] * sizeof(int32_t);
         }
     }
     L.image = round_up((int64_t)off, 64);
@@ -400,6 +469,12 @@ static void encode(const sb_gemv_desc* d, int32_t count, const BatLayout& L, uns
     BatHeader* hdr = reinterpret_cast<BatHeader*>(image);
     hdr->count = count;
     hdr->ntiles = L.ntiles;
+    hdr->nitems = (int64_t)L.items.size();
+    hdr->items_off = (int64_t)L.items_off;
+    hdr->lists_off = (int64_t)L.lists_off;
+    hdr->grid = (int32_t)(L.lists.size() - 1);
+    if (!L.items.empty()) memcpy(image + L.items_off, L.items.data(), L.items.size() * sizeof(BatItem));
+    memcpy(image + L.lists_off, L.lists.data(), L.lists.size() * sizeof(int32_t));
     BatProblem* P = reinterpret_cast<BatProblem*>(image + sizeof(BatHeader));
     int64_t tile0 = 0, cost = 0;
     for (int32_t i = 0; i < count; ++i) {
@@ -415,9 +490,7 @@ static void encode(const sb_gemv_desc* d, int32_t count, const BatLayout& L, uns
         p.KC = L.kc[i];
         p.tile0 = tile0;
         p.rtiles = L.rtiles[i];
-        // tile cost: its bytes of A plus a fixed 4 KiB for staging and set-up
-        const int64_t a_bytes = (int64_t)r.rows_per_tile * std::min<int64_t>(L.kc[i], d[i].n) * esize(r.dtype);
-        p.tile_cost = L.tiles[i] > 0 ? (a_bytes + 4096 + 1023) / 1024 : 0;
+        p.tile_cost = L.tile_cost[i];
         p.cost0 = cost;
         cost += p.tile_cost * L.tiles[i];
         p.A = d[i].A;

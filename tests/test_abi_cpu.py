@@ -265,6 +265,28 @@ def test_batched_resolve_encode_on_host(L):
     assert count == 3 and tiles[0][0] == 0 and total_cost == cost
     assert tiles[1][0] == tiles[0][1] and tiles[2][0] == tiles[1][0] + tiles[1][1]
     assert ntiles == sum(t for _, t in tiles)
+    # work items: every tile of every problem exactly once, dealt to the
+    # workgroups so that no workgroup's cost exceeds both its even share and
+    # the lightest one's plus the largest item (the largest-first greedy rule)
+    nitems, items_off, lists_off, grid = struct.unpack_from("<qqqi", buf, 24)
+    assert items_off == 64 + 3 * 144 and lists_off == items_off + 16 * nitems and grid == 1024
+    lists = struct.unpack_from(f"<{grid + 1}i", buf, lists_off)
+    assert lists[0] == 0 and lists[-1] == nitems and all(a <= b for a, b in zip(lists, lists[1:]))
+    costs = [struct.unpack_from("<q", buf, 64 + 144 * k + 16 + 56)[0] for k in range(3)]
+    seen = [set() for _ in range(3)]
+    loads, biggest = [], 0
+    for b in range(grid):
+        load = 0
+        for j in range(lists[b], lists[b + 1]):
+            prob, cnt, first = struct.unpack_from("<iiq", buf, items_off + 16 * j)
+            assert cnt >= 1 and not seen[prob] & set(range(first, first + cnt))
+            seen[prob] |= set(range(first, first + cnt))
+            load += cnt * costs[prob]
+            biggest = max(biggest, cnt * costs[prob])
+        loads.append(load)
+    assert [len(t) for t in seen] == [t for _, t in tiles]
+    share = -(-total_cost // grid)
+    assert max(loads) <= max(share, min(loads) + biggest)
 
 
 def test_batched_validation(L):
@@ -284,4 +306,5 @@ def test_batched_validation(L):
     assert L.sb_gemv_batched_resolve(two, 2, (sb.sb_gemv_desc * 2)()) == -1  # outputs overlap
     assert b"overlap" in L.sb_last_error(None)
     empty = (sb.sb_gemv_desc * 1)(_desc(sb, 1, 0, 10, 0, 0, x=0))
-    assert L.sb_gemv_batched_table_bytes(empty, 1, None) == 256  # 64 + 144, rounded up to 64
+    # header, one record, no items, 1025 list offsets, rounded up to 64
+    assert L.sb_gemv_batched_table_bytes(empty, 1, None) == (64 + 144 + 4 * 1025 + 63) // 64 * 64
