@@ -30,7 +30,6 @@
 
 #include <algorithm>
 #include <new>
-#include <queue>
 #include <vector>
 
 #include "sb_device.hpp"
@@ -316,7 +315,7 @@ struct BatLayout {
     std::vector<sb_gemv_desc> res;
     std::vector<int64_t> kc, tiles, rtiles, tile_cost, counter_off, partial_off;
     std::vector<BatItem> items;
-    std::vector<int32_t> lists;  // grid + 1 offsets into items
+    int32_t grid = 0;            // workgroups the items are dealt to
     size_t image = 0, total = 0, items_off = 0, lists_off = 0;
     int64_t ntiles = 0, total_cost = 0;
 };
@@ -375,58 +374,26 @@ static sb_status layout(const sb_gemv_desc* d, int32_t count, BatLayout& L, char
         L.total_cost += L.tile_cost[i] * L.tiles[i];
     }
     // Work items: runs of consecutive tiles of one problem costing about
-    // 1/SB_BAT_ITEMS_PER_WG of a workgroup's share of the batch.  They are
-    // dealt largest first, each to the workgroup with the least cost so far
-    // (ties to the lowest index); a workgroup's items then run in problem
-    // and tile order, so consecutive tiles of one problem reuse the staged x.
-    const int64_t grid = kBatGrid;
-    const int64_t target = std::max<int64_t>(1, L.total_cost / ((int64_t)SB_BAT_ITEMS_PER_WG * grid));
-    std::vector<BatItem> items;
+    // 1/SB_BAT_ITEMS_PER_WG of a workgroup's share of the batch, listed in
+    // problem and tile order (dealt to the workgroups by deal_items).
+    const int64_t target = std::max<int64_t>(1, L.total_cost / ((int64_t)SB_BAT_ITEMS_PER_WG * kBatGrid));
     for (int32_t i = 0; i < count; ++i) {
         if (L.tiles[i] == 0) continue;
-        const int64_t per = std::min<int64_t>(std::max<int64_t>(1, target / L.tile_cost[i]), (int64_t)1 << 30);
+        const int64_t per =
+            std::min<int64_t>(std::max<int64_t>(1, (target + L.tile_cost[i] / 2) / L.tile_cost[i]), (int64_t)1 << 30);
         for (int64_t first = 0; first < L.tiles[i]; first += per)
-            items.push_back(BatItem{i, (int32_t)std::min<int64_t>(per, L.tiles[i] - first), first});
+            L.items.push_back(BatItem{i, (int32_t)std::min<int64_t>(per, L.tiles[i] - first), first});
+        if (L.items.size() > ((size_t)1 << 30)) {
+            snprintf(why, whylen, "too many work items");
+            return SB_EINVAL;
+        }
     }
-    if (items.size() > ((size_t)1 << 30)) {
-        snprintf(why, whylen, "too many work items");
-        return SB_EINVAL;
-    }
-    auto item_cost = [&](const BatItem& a) { return a.count * L.tile_cost[a.problem]; };
-    std::stable_sort(items.begin(), items.end(),
-                     [&](const BatItem& a, const BatItem& b) { return item_cost(a) > item_cost(b); });
-    typedef std::pair<int64_t, int32_t> Load;  // (cost so far, workgroup); stale entries skipped
-    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
-    std::vector<int64_t> load(grid, 0);
-    for (int32_t b = 0; b < (int32_t)grid; ++b) heap.push({0, b});
-    std::vector<int32_t> owner(items.size());
-    std::vector<int32_t> per_wg(grid + 1, 0);
-    for (size_t j = 0; j < items.size(); ++j) {
-        const int64_t c = item_cost(items[j]);
-        while (heap.top().first != load[heap.top().second]) heap.pop();  // skip stale entries
-        const int32_t b = heap.top().second;
-        owner[j] = b;
-        ++per_wg[b + 1];
-        load[b] += c;
-        heap.push({load[b], b});
-    }
-    L.lists.assign(per_wg.begin(), per_wg.end());
-    for (int64_t b = 0; b < grid; ++b) L.lists[b + 1] += L.lists[b];
-    L.items.resize(items.size());
-    {
-        std::vector<int32_t> fill(L.lists.begin(), L.lists.end() - 1);
-        for (size_t j = 0; j < items.size(); ++j) L.items[fill[owner[j]]++] = items[j];
-        for (int64_t b = 0; b < grid; ++b)
-            std::sort(L.items.begin() + L.lists[b], L.items.begin() + L.lists[b + 1],
-                      [](const BatItem& a, const BatItem& c) {
-                          return a.problem != c.problem ? a.problem < c.problem : a.first < c.first;
-                      });
-    }
+    L.grid = kBatGrid;
     size_t off = sizeof(BatHeader) + (size_t)count * sizeof(BatProblem);
     L.items_off = off;
     off += L.items.size() * sizeof(BatItem);
     L.lists_off = off;
-    off += L.lists.size() * sizeof(int32_t);
+    off += (size_t)(L.grid + 1) * sizeof(int32_t);
     for (int32_t i = 0; i < count; ++i) {
         L.counter_off[i] = -1;
         if (L.res[i].split > 1 && L.rtiles[i] > 0) {
@@ -462,6 +429,42 @@ static sb_status layout(const sb_gemv_desc* d, int32_t count, BatLayout& L, char
     return SB_OK;
 }
 
+// Deal the work items (in problem and tile order in L.items) to the
+// workgroups, largest first (close to the longest-processing-time-first
+// rule, in linear time after the sort).
+// Writes the items grouped by workgroup, each group still in problem and
+// tile order (so consecutive tiles of one problem reuse the staged x), and
+// the grid + 1 group offsets.
+static void deal_items(const BatLayout& L, BatItem* out, int32_t* lists)
+{
+    const size_t n = L.items.size();
+    const int32_t grid = L.grid;
+    if (n <= (size_t)grid) {  // one item per workgroup: nothing to balance
+        for (size_t j = 0; j < n; ++j) out[j] = L.items[j];
+        for (int32_t b = 0; b <= grid; ++b) lists[b] = (int32_t)std::min<size_t>((size_t)b, n);
+        return;
+    }
+    // (-cost, index): ascending order is largest first, ties in item order
+    std::vector<std::pair<int64_t, uint32_t>> order(n);
+    for (size_t j = 0; j < n; ++j) order[j] = {-(L.items[j].count * L.tile_cost[L.items[j].problem]), (uint32_t)j};
+    std::sort(order.begin(), order.end());
+    // Largest first in rounds of `grid` items, alternating direction (the
+    // snake order): round 0 gives workgroup b the (b+1)-th largest item,
+    // round 1 pairs it with the (2*grid-b)-th, and so on, so each round
+    // evens out the previous one; no workgroup ends above another by more
+    // than the largest item.
+    std::vector<int32_t> owner(n);
+    for (size_t k = 0; k < n; ++k) {
+        const size_t r = k / (size_t)grid, pos = k % (size_t)grid;
+        owner[order[k].second] = (int32_t)((r & 1) ? (size_t)grid - 1 - pos : pos);
+    }
+    std::vector<int32_t> fill(grid + 1, 0);
+    for (size_t j = 0; j < n; ++j) ++fill[owner[j] + 1];
+    for (int32_t b = 0; b < grid; ++b) fill[b + 1] += fill[b];
+    for (int32_t b = 0; b <= grid; ++b) lists[b] = fill[b];
+    for (size_t j = 0; j < n; ++j) out[fill[owner[j]]++] = L.items[j];  // creation order within a group
+}
+
 static void encode(const sb_gemv_desc* d, int32_t count, const BatLayout& L, unsigned char* dev_table,
                    unsigned char* image)
 {
@@ -472,9 +475,8 @@ static void encode(const sb_gemv_desc* d, int32_t count, const BatLayout& L, uns
     hdr->nitems = (int64_t)L.items.size();
     hdr->items_off = (int64_t)L.items_off;
     hdr->lists_off = (int64_t)L.lists_off;
-    hdr->grid = (int32_t)(L.lists.size() - 1);
-    if (!L.items.empty()) memcpy(image + L.items_off, L.items.data(), L.items.size() * sizeof(BatItem));
-    memcpy(image + L.lists_off, L.lists.data(), L.lists.size() * sizeof(int32_t));
+    hdr->grid = L.grid;
+    deal_items(L, reinterpret_cast<BatItem*>(image + L.items_off), reinterpret_cast<int32_t*>(image + L.lists_off));
     BatProblem* P = reinterpret_cast<BatProblem*>(image + sizeof(BatHeader));
     int64_t tile0 = 0, cost = 0;
     for (int32_t i = 0; i < count; ++i) {
