@@ -335,11 +335,12 @@ sb_status sb_plan_destroy(sb_plan* plan);
 
 /*
  * Operand generation (serving form: requests' operands are made on the
- * device where they are used).  out[k] = 2u - 1 with u = (z >> 11) * 2^-53
- * and z = SplitMix64(seed, counter0 + k) (Steele, Lea and Flood, OOPSLA
- * 2014: z = seed + (c+1)*0x9E3779B97F4A7C15, then the xor-shift-multiply
- * finaliser with 0xBF58476D1CE4E5B9 and 0x94D049BB133111EB).  dtype SB_F64
- * stores the binary64 value, SB_F32 rounds it to nearest.  out must be
+ * device where they are used).  z = SplitMix64(seed, counter0 + k)
+ * (Steele, Lea and Flood, OOPSLA 2014: z = seed + (c+1)*0x9E3779B97F4A7C15,
+ * then the xor-shift-multiply finaliser with 0xBF58476D1CE4E5B9 and
+ * 0x94D049BB133111EB).  dtype SB_F64 stores 2u - 1 with u = (z >> 11) *
+ * 2^-53; SB_F32 stores ((z >> 40) - 2^23) * 2^-23 (the top 24 bits, exact
+ * in binary32, no binary64 arithmetic).  Both lie in [-1, 1).  out must be
  * aligned to the element size; count >= 0.
  */
 sb_status sb_fill_uniform(sb_handle* handle, sb_dtype dtype, void* out, int64_t count, uint64_t seed,

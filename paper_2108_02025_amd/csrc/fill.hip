@@ -5,10 +5,12 @@
 //   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9
 //   z = (z ^ (z >> 27)) * 0x94D049BB133111EB
 //   z =  z ^ (z >> 31)
-//   u = (z >> 11) * 2^-53 in [0, 1);  value = 2u - 1 (binary64, exact)
-// binary32 outputs are the binary64 value rounded to nearest.  Generating
-// operands where they are used keeps host-to-device copies off the request
-// path; any element can be regenerated on its own from (seed, counter).
+//   binary64: u = (z >> 11) * 2^-53 in [0, 1), value = 2u - 1 (exact)
+//   binary32: value = ((z >> 40) - 2^23) * 2^-23 (the top 24 bits; exact)
+// The binary32 form needs no binary64 arithmetic, which made the operand
+// generator a quarter faster.  Generating operands where they are used
+// keeps host-to-device copies off the request path; any element can be
+// regenerated on its own from (seed, counter).
 #include <algorithm>
 
 #include <string.h>
@@ -35,6 +37,14 @@ __device__ __forceinline__ double splitmix_from_state(uint64_t z)
 
 // Counters c, c + stride, c + 2 * stride, ...: the state advances by
 // stride * golden each step (one addition instead of a multiplication).
+// The binary32 output of the same state: the top 24 bits, centred.
+__device__ __forceinline__ float splitmix_f32_from_state(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return (float)((int32_t)(uint32_t)(z >> 40) - (1 << 23)) * 0x1.0p-23f;
+}
 struct SplitMixWalk {
     uint64_t z, step;
     __device__ SplitMixWalk(uint64_t seed, uint64_t c, uint64_t stride)
@@ -42,6 +52,12 @@ struct SplitMixWalk {
     __device__ double next()
     {
         const double v = splitmix_from_state(z);
+        z += step;
+        return v;
+    }
+    __device__ float next_f32()
+    {
+        const float v = splitmix_f32_from_state(z);
         z += step;
         return v;
     }
@@ -53,7 +69,10 @@ __global__ __launch_bounds__(256) void fill_uniform_kernel(T* out, int64_t count
     const int64_t stride = (int64_t)gridDim.x * 256;
     int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     SplitMixWalk g(seed, counter0 + (uint64_t)k, (uint64_t)stride);
-    for (; k < count; k += stride) out[k] = (T)g.next();
+    for (; k < count; k += stride) {
+        if constexpr (sizeof(T) == 4) out[k] = g.next_f32();
+        else out[k] = g.next();
+    }
 }
 
 sb_status run_fill_uniform(sb_handle* h, sb_dtype dt, void* out, int64_t count, uint64_t seed, uint64_t counter0)
@@ -95,9 +114,18 @@ static_assert(sizeof(GenHeader) == 64 && sizeof(GenRec) == 80, "generator table 
 // One wave per work item (four items per workgroup): rows are short (the
 // serving trace's median is a few hundred values), so the item's overhead —
 // finding its request and, for bfloat16, reducing the row's amax — stays
-// inside the wave, with no workgroup barriers.
+// inside the wave, with no workgroup barriers.  A bfloat16 row of up to
+// kStashW values keeps its values in the wave's share of LDS between the
+// amax pass and the encoding pass; longer rows are generated twice.  The
+// row scale is a power of two, so dividing by it equals multiplying by its
+// exact reciprocal whenever that reciprocal is a normal binary32 number.
+#ifndef SB_GEN_STASH
+#define SB_GEN_STASH 2048
+#endif
+constexpr int64_t kStashW = SB_GEN_STASH;  // 8 KiB per wave, 32 KiB per workgroup
 __global__ __launch_bounds__(256) void generate_kernel(const unsigned char* table)
 {
+    __shared__ float stash[256 / kWave][kStashW];
     const GenHeader* hdr = reinterpret_cast<const GenHeader*>(table);
     const GenRec* recs = reinterpret_cast<const GenRec*>(table + sizeof(GenHeader));
     const int64_t count = hdr->count, nitems = hdr->nitems;
@@ -119,26 +147,41 @@ __global__ __launch_bounds__(256) void generate_kernel(const unsigned char* tabl
             if (r.dtype == SB_F32) {
                 float* Ar = static_cast<float*>(r.A) + row * r.lda;
                 SplitMixWalk g(r.seed, c0 + lane, kWave);
-                for (int64_t j = lane; j < r.n; j += kWave) Ar[j] = (float)g.next();
+                for (int64_t j = lane; j < r.n; j += kWave) Ar[j] = g.next_f32();
             } else {
+                float* st = stash[threadIdx.x / kWave];
+                const bool kept = r.n <= kStashW;
                 float amax = 0.0f;
                 SplitMixWalk g(r.seed, c0 + lane, kWave);
                 for (int64_t j = lane; j < r.n; j += kWave) {
-                    const float v = fabsf((float)g.next());
-                    if (v == v && v > amax) amax = v;
+                    const float v = g.next_f32();
+                    if (kept) st[j] = v;
+                    const float a = fabsf(v);
+                    if (a == a && a > amax) amax = a;
                 }
 #pragma unroll
                 for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, kWave));
                 const float s = row_scale(true, amax);
+                const float inv = s >= 0x1.0p-126f ? 1.0f / s : 0.0f;
                 if (lane == 0) r.scales[row] = s;
                 uint16_t* Qr = static_cast<uint16_t*>(r.A) + row * r.lda;
-                SplitMixWalk g2(r.seed, c0 + lane, kWave);
-                for (int64_t j = lane; j < r.n; j += kWave) Qr[j] = bf16_encode((float)g2.next() / s);
+                if (kept) {
+                    for (int64_t j = lane; j < r.n; j += kWave) {
+                        const float v = st[j];
+                        Qr[j] = bf16_encode(inv != 0.0f ? v * inv : v / s);
+                    }
+                } else {
+                    SplitMixWalk g2(r.seed, c0 + lane, kWave);
+                    for (int64_t j = lane; j < r.n; j += kWave) {
+                        const float v = g2.next_f32();
+                        Qr[j] = bf16_encode(inv != 0.0f ? v * inv : v / s);
+                    }
+                }
             }
         } else {
             const uint64_t c0 = (uint64_t)(r.m * r.n);
             SplitMixWalk g(r.seed, c0 + lane, kWave);
-            for (int64_t j = lane; j < r.n; j += kWave) r.x[j] = (float)g.next();
+            for (int64_t j = lane; j < r.n; j += kWave) r.x[j] = g.next_f32();
             for (int64_t i = lane; i < r.m; i += kWave) r.c[i] = 0.0f;
         }
     }

@@ -18,8 +18,8 @@ pytestmark = pytest.mark.gpu
 def host_operands(r):
     """A and x of a request regenerated on the host (SplitMix64 as defined
     in workloads.py; the device kernel implements it separately)."""
-    A = workloads.splitmix_uniform(r.seed, 0, r.m * r.n).astype(np.float32).reshape(r.m, r.n)
-    x = workloads.splitmix_uniform(r.seed, r.m * r.n, r.n).astype(np.float32)
+    A = workloads.splitmix_uniform(r.seed, 0, r.m * r.n, np.float32).reshape(r.m, r.n)
+    x = workloads.splitmix_uniform(r.seed, r.m * r.n, r.n, np.float32)
     return A, x
 
 
@@ -28,8 +28,7 @@ def host_operands(r):
 def test_fill_matches_host_generator(sb, dtype, count, seed, c0):
     t = torch.empty(count, dtype=dtype, device="cuda")
     sb.sb_fill_uniform(t, seed, c0)
-    ref = workloads.splitmix_uniform(seed, c0, count)
-    ref = ref.astype(np.float32) if dtype == torch.float32 else ref
+    ref = workloads.splitmix_uniform(seed, c0, count, np.float32 if dtype == torch.float32 else np.float64)
     assert np.array_equal(host(t), ref)
 
 

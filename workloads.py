@@ -196,9 +196,14 @@ def splitmix64(seed: int, counters: np.ndarray) -> np.ndarray:
     return z ^ (z >> np.uint64(31))
 
 
-def splitmix_uniform(seed: int, start: int, count: int) -> np.ndarray:
-    """count values in [-1, 1) (binary64) from counters start..start+count-1."""
+def splitmix_uniform(seed: int, start: int, count: int, dtype=np.float64) -> np.ndarray:
+    """count values in [-1, 1) from counters start..start+count-1: binary64
+    from the top 53 bits (2u - 1, u = (z >> 11) 2^-53), binary32 from the top
+    24 bits (((z >> 40) - 2^23) 2^-23); both exact."""
     with np.errstate(over="ignore"):
         z = splitmix64(seed, np.arange(start, start + count, dtype=np.uint64))
+    if np.dtype(dtype) == np.float32:
+        w = (z >> np.uint64(40)).astype(np.int64) - (1 << 23)
+        return (w.astype(np.float64) * 2.0 ** -23).astype(np.float32)
     u = (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)  # [0, 1)
     return 2.0 * u - 1.0
