@@ -338,10 +338,12 @@ sb_status sb_plan_destroy(sb_plan* plan);
  * device where they are used).  z = SplitMix64(seed, counter0 + k)
  * (Steele, Lea and Flood, OOPSLA 2014: z = seed + (c+1)*0x9E3779B97F4A7C15,
  * then the xor-shift-multiply finaliser with 0xBF58476D1CE4E5B9 and
- * 0x94D049BB133111EB).  dtype SB_F64 stores 2u - 1 with u = (z >> 11) *
- * 2^-53; SB_F32 stores ((z >> 40) - 2^23) * 2^-23 (the top 24 bits, exact
- * in binary32, no binary64 arithmetic).  Both lie in [-1, 1).  out must be
- * aligned to the element size; count >= 0.
+ * 0x94D049BB133111EB).  dtype SB_F64: element e = counter0 + k is 2u - 1
+ * with u = (z_e >> 11) * 2^-53.  SB_F32: two elements per state, element e
+ * is (f - 2^23) * 2^-23 with f = z_(e>>1) >> 40 for even e and
+ * (z_(e>>1) >> 8) & 0xFFFFFF for odd e (exact in binary32, no binary64
+ * arithmetic).  Both lie in [-1, 1).  out must be aligned to the element
+ * size; count >= 0.
  */
 sb_status sb_fill_uniform(sb_handle* handle, sb_dtype dtype, void* out, int64_t count, uint64_t seed,
                           uint64_t counter0);

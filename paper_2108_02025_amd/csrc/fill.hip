@@ -6,9 +6,12 @@
 //   z = (z ^ (z >> 27)) * 0x94D049BB133111EB
 //   z =  z ^ (z >> 31)
 //   binary64: u = (z >> 11) * 2^-53 in [0, 1), value = 2u - 1 (exact)
-//   binary32: value = ((z >> 40) - 2^23) * 2^-23 (the top 24 bits; exact)
-// The binary32 form needs no binary64 arithmetic, which made the operand
-// generator a quarter faster.  Generating operands where they are used
+//   binary32: two values per state: element e uses the state of counter
+//     e >> 1 and the 24-bit field f = z >> 40 (e even) or (z >> 8) & 0xFFFFFF
+//     (e odd); value = (f - 2^23) * 2^-23 (exact)
+// The binary32 form needs no binary64 arithmetic and half the hashing per
+// value, which made the operand generator about twice as fast.  Generating
+// operands where they are used
 // keeps host-to-device copies off the request path; any element can be
 // regenerated on its own from (seed, counter).
 #include <algorithm>
@@ -35,16 +38,18 @@ __device__ __forceinline__ double splitmix_from_state(uint64_t z)
     return 2.0 * u - 1.0;
 }
 
-// Counters c, c + stride, c + 2 * stride, ...: the state advances by
-// stride * golden each step (one addition instead of a multiplication).
-// The binary32 output of the same state: the top 24 bits, centred.
-__device__ __forceinline__ float splitmix_f32_from_state(uint64_t z)
+// The two binary32 outputs of a state (elements 2c and 2c + 1).
+__device__ __forceinline__ void splitmix_f32_pair(uint64_t z, float& even, float& odd)
 {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z = z ^ (z >> 31);
-    return (float)((int32_t)(uint32_t)(z >> 40) - (1 << 23)) * 0x1.0p-23f;
+    even = (float)((int32_t)(uint32_t)(z >> 40) - (1 << 23)) * 0x1.0p-23f;
+    odd = (float)((int32_t)((uint32_t)(z >> 8) & 0xFFFFFFu) - (1 << 23)) * 0x1.0p-23f;
 }
+
+// Counters c, c + stride, c + 2 * stride, ...: the state advances by
+// stride * golden each step (one addition instead of a multiplication).
 struct SplitMixWalk {
     uint64_t z, step;
     __device__ SplitMixWalk(uint64_t seed, uint64_t c, uint64_t stride)
@@ -55,23 +60,60 @@ struct SplitMixWalk {
         z += step;
         return v;
     }
-    __device__ float next_f32()
+    __device__ void next_f32_pair(float& even, float& odd)
     {
-        const float v = splitmix_f32_from_state(z);
+        splitmix_f32_pair(z, even, odd);
         z += step;
-        return v;
     }
 };
 
-template <typename T>
-__global__ __launch_bounds__(256) void fill_uniform_kernel(T* out, int64_t count, uint64_t seed, uint64_t counter0)
+// Elements [e0, e0 + len) of a stream taken in pairs (2p, 2p + 1) by lane l
+// of a group of L lanes: pairs p = e0/2 + l, e0/2 + l + L, ..., up to the
+// pair of the last element; visit(p, j) gets each pair with j = 2p - e0, the
+// range index of its even element (-1 when the range starts on an odd
+// element; j + 1 may be len when it ends on an even one).  Nothing is
+// visited for an empty range.
+template <int L, typename F>
+__device__ __forceinline__ void for_pairs(uint64_t e0, int64_t len, int l, F visit)
+{
+    if (len <= 0) return;
+    const uint64_t p0 = e0 >> 1, p1 = (e0 + (uint64_t)len - 1) >> 1;
+    for (uint64_t p = p0 + (uint64_t)l; p <= p1; p += L) visit(p, (int64_t)(2 * p - e0));
+}
+
+// Binary32 elements [e0, e0 + len) of a counter stream, lane l of a group of
+// L lanes: put(j, value) for each element j - e0 of the lane's pairs that
+// lies inside the range.
+template <int L, typename F>
+__device__ __forceinline__ void f32_stream(uint64_t seed, uint64_t e0, int64_t len, int l, F put)
+{
+    SplitMixWalk g(seed, (e0 >> 1) + (uint64_t)l, L);
+    for_pairs<L>(e0, len, l, [&](uint64_t, int64_t j) {
+        float v0, v1;
+        g.next_f32_pair(v0, v1);
+        if (j >= 0) put(j, v0);
+        if (j + 1 < len) put(j + 1, v1);
+    });
+}
+
+__global__ __launch_bounds__(256) void fill_uniform_f64_kernel(double* out, int64_t count, uint64_t seed,
+                                                               uint64_t counter0)
 {
     const int64_t stride = (int64_t)gridDim.x * 256;
     int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     SplitMixWalk g(seed, counter0 + (uint64_t)k, (uint64_t)stride);
-    for (; k < count; k += stride) {
-        if constexpr (sizeof(T) == 4) out[k] = g.next_f32();
-        else out[k] = g.next();
+    for (; k < count; k += stride) out[k] = g.next();
+}
+
+// Binary32: each workgroup takes a 2 * 256-element slice of pairs at a time.
+__global__ __launch_bounds__(256) void fill_uniform_f32_kernel(float* out, int64_t count, uint64_t seed,
+                                                               uint64_t counter0)
+{
+    const int64_t slice = 2 * 256 * 64;  // elements per workgroup slice (64 pairs per thread)
+    for (int64_t s0 = (int64_t)blockIdx.x * slice; s0 < count; s0 += (int64_t)gridDim.x * slice) {
+        const int64_t len = min(slice, count - s0);
+        f32_stream<256>(seed, counter0 + (uint64_t)s0, len, threadIdx.x,
+                        [&](int64_t j, float v) { out[s0 + j] = v; });
     }
 }
 
@@ -80,11 +122,11 @@ sb_status run_fill_uniform(sb_handle* h, sb_dtype dt, void* out, int64_t count, 
     if (count == 0) return SB_OK;
     const int64_t blocks = std::min<int64_t>(4096, (count + 255) / 256);
     if (dt == SB_F64)
-        hipLaunchKernelGGL(fill_uniform_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, h->stream,
+        hipLaunchKernelGGL(fill_uniform_f64_kernel, dim3((unsigned)blocks), dim3(256), 0, h->stream,
                            static_cast<double*>(out), count, seed, counter0);
     else
-        hipLaunchKernelGGL(fill_uniform_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, h->stream,
-                           static_cast<float*>(out), count, seed, counter0);
+        hipLaunchKernelGGL(fill_uniform_f32_kernel, dim3((unsigned)std::min<int64_t>(4096, (count + 32767) / 32768)),
+                           dim3(256), 0, h->stream, static_cast<float*>(out), count, seed, counter0);
     return check_launch(h, "fill_uniform_kernel");
 }
 
@@ -146,42 +188,37 @@ __global__ __launch_bounds__(256) void generate_kernel(const unsigned char* tabl
             const uint64_t c0 = (uint64_t)(row * r.n);
             if (r.dtype == SB_F32) {
                 float* Ar = static_cast<float*>(r.A) + row * r.lda;
-                SplitMixWalk g(r.seed, c0 + lane, kWave);
-                for (int64_t j = lane; j < r.n; j += kWave) Ar[j] = g.next_f32();
+                f32_stream<kWave>(r.seed, c0, r.n, lane, [&](int64_t j, float v) { Ar[j] = v; });
             } else {
                 float* st = stash[threadIdx.x / kWave];
                 const bool kept = r.n <= kStashW;
                 float amax = 0.0f;
-                SplitMixWalk g(r.seed, c0 + lane, kWave);
-                for (int64_t j = lane; j < r.n; j += kWave) {
-                    const float v = g.next_f32();
+                f32_stream<kWave>(r.seed, c0, r.n, lane, [&](int64_t j, float v) {
                     if (kept) st[j] = v;
                     const float a = fabsf(v);
                     if (a == a && a > amax) amax = a;
-                }
+                });
 #pragma unroll
                 for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, kWave));
                 const float s = row_scale(true, amax);
                 const float inv = s >= 0x1.0p-126f ? 1.0f / s : 0.0f;
                 if (lane == 0) r.scales[row] = s;
                 uint16_t* Qr = static_cast<uint16_t*>(r.A) + row * r.lda;
+                auto enc = [&](int64_t j, float v) { Qr[j] = bf16_encode(inv != 0.0f ? v * inv : v / s); };
                 if (kept) {
-                    for (int64_t j = lane; j < r.n; j += kWave) {
-                        const float v = st[j];
-                        Qr[j] = bf16_encode(inv != 0.0f ? v * inv : v / s);
-                    }
+                    // the elements this lane stashed in the first pass
+                    const int64_t n = r.n;
+                    for_pairs<kWave>(c0, n, lane, [&](uint64_t, int64_t j) {
+                        if (j >= 0) enc(j, st[j]);
+                        if (j + 1 < n) enc(j + 1, st[j + 1]);
+                    });
                 } else {
-                    SplitMixWalk g2(r.seed, c0 + lane, kWave);
-                    for (int64_t j = lane; j < r.n; j += kWave) {
-                        const float v = g2.next_f32();
-                        Qr[j] = bf16_encode(inv != 0.0f ? v * inv : v / s);
-                    }
+                    f32_stream<kWave>(r.seed, c0, r.n, lane, enc);
                 }
             }
         } else {
             const uint64_t c0 = (uint64_t)(r.m * r.n);
-            SplitMixWalk g(r.seed, c0 + lane, kWave);
-            for (int64_t j = lane; j < r.n; j += kWave) r.x[j] = g.next_f32();
+            f32_stream<kWave>(r.seed, c0, r.n, lane, [&](int64_t j, float v) { r.x[j] = v; });
             for (int64_t i = lane; i < r.m; i += kWave) r.c[i] = 0.0f;
         }
     }

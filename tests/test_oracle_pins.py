@@ -496,12 +496,18 @@ def test_splitmix64_published_vector():
     assert [int(v) for v in z] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
     u = workloads.splitmix_uniform(123, 0, 10000)
     assert u.min() >= -1 and u.max() < 1 and abs(u.mean()) < 0.05
-    # the two value maps, from the published first output: binary64 from
-    # the top 53 bits, binary32 from the top 24 bits
+    # the two value maps, from the published first outputs: binary64 from
+    # the top 53 bits, binary32 two per state from bits 40..63 and 8..31
     z0 = 0xE220A8397B1DCDAF
     assert workloads.splitmix_uniform(0, 0, 1)[0] == 2 * ((z0 >> 11) * 2.0 ** -53) - 1
-    f = workloads.splitmix_uniform(0, 0, 1, np.float32)[0]
-    assert f.dtype == np.float32 and float(f) == ((z0 >> 40) - 2 ** 23) / 2 ** 23
+    f = workloads.splitmix_uniform(0, 0, 4, np.float32)
+    z1 = 0x6E789E6AA1B965F4
+    assert f.dtype == np.float32 and [float(v) for v in f] == [
+        ((z0 >> 40) - 2 ** 23) / 2 ** 23, (((z0 >> 8) & 0xFFFFFF) - 2 ** 23) / 2 ** 23,
+        ((z1 >> 40) - 2 ** 23) / 2 ** 23, (((z1 >> 8) & 0xFFFFFF) - 2 ** 23) / 2 ** 23]
+    # a stream read from an odd start is the same stream
+    assert np.array_equal(workloads.splitmix_uniform(5, 7, 10, np.float32),
+                          workloads.splitmix_uniform(5, 0, 17, np.float32)[7:])
     v = workloads.splitmix_uniform(123, 0, 10000, np.float32)
     assert v.min() >= -1 and v.max() < 1 and np.all(v * np.float32(2 ** 23) == np.rint(v * 2 ** 23))
 

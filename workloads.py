@@ -197,13 +197,18 @@ def splitmix64(seed: int, counters: np.ndarray) -> np.ndarray:
 
 
 def splitmix_uniform(seed: int, start: int, count: int, dtype=np.float64) -> np.ndarray:
-    """count values in [-1, 1) from counters start..start+count-1: binary64
-    from the top 53 bits (2u - 1, u = (z >> 11) 2^-53), binary32 from the top
-    24 bits (((z >> 40) - 2^23) 2^-23); both exact."""
-    with np.errstate(over="ignore"):
-        z = splitmix64(seed, np.arange(start, start + count, dtype=np.uint64))
+    """count values in [-1, 1) for elements start..start+count-1.  binary64:
+    element e from the state of counter e, the top 53 bits (2u - 1,
+    u = (z >> 11) 2^-53).  binary32: two elements per state, element e from
+    the state of counter e >> 1 and the 24-bit field z >> 40 (e even) or
+    (z >> 8) & 0xFFFFFF (e odd), value (f - 2^23) 2^-23.  Both exact."""
+    e = np.arange(start, start + count, dtype=np.uint64)
     if np.dtype(dtype) == np.float32:
-        w = (z >> np.uint64(40)).astype(np.int64) - (1 << 23)
-        return (w.astype(np.float64) * 2.0 ** -23).astype(np.float32)
+        with np.errstate(over="ignore"):
+            z = splitmix64(seed, e >> np.uint64(1))
+        f = np.where(e & np.uint64(1), (z >> np.uint64(8)) & np.uint64(0xFFFFFF), z >> np.uint64(40))
+        return ((f.astype(np.int64) - (1 << 23)).astype(np.float64) * 2.0 ** -23).astype(np.float32)
+    with np.errstate(over="ignore"):
+        z = splitmix64(seed, e)
     u = (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)  # [0, 1)
     return 2.0 * u - 1.0
