@@ -127,7 +127,7 @@ sb_status run_fill_uniform(sb_handle* h, sb_dtype dt, void* out, int64_t count, 
     else
         hipLaunchKernelGGL(fill_uniform_f32_kernel, dim3((unsigned)std::min<int64_t>(4096, (count + 32767) / 32768)),
                            dim3(256), 0, h->stream, static_cast<float*>(out), count, seed, counter0);
-    return check_launch(h, "fill_uniform_kernel");
+    return check_launch(h, dt == SB_F64 ? "fill_uniform_f64_kernel" : "fill_uniform_f32_kernel");
 }
 
 // ---- batched materialisation of GEMV requests -----------------------------
