@@ -33,7 +33,7 @@
 #define SB_GEMVMX_UNROLL_FP8 8
 #endif
 #ifndef SB_GEMVMX_UNROLL_FP4
-#define SB_GEMVMX_UNROLL_FP4 4
+#define SB_GEMVMX_UNROLL_FP4 8
 #endif
 #ifndef SB_GEMVMX_MIN_WAVES
 #define SB_GEMVMX_MIN_WAVES 4
