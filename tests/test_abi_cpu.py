@@ -289,6 +289,48 @@ def test_batched_resolve_encode_on_host(L):
     assert max(loads) <= max(share, min(loads) + biggest)
 
 
+def test_batched_items_dealt_evenly_large_batch(L):
+    """A batch with more work items than workgroups: the items are dealt in
+    alternating rounds, largest first; every tile is run exactly once and no
+    workgroup ends above another by more than the largest item."""
+    import struct
+
+    import numpy as np
+
+    import paper_2108_02025_amd as sb
+    rng = np.random.default_rng(3)
+    count = 300
+    arr = (sb.sb_gemv_desc * count)()
+    for k in range(count):
+        m, n = (int(v) for v in np.exp(rng.uniform(np.log(64), np.log(8192), 2)))
+        dt = 1 if k % 2 else 2
+        arr[k] = _desc(sb, dt, m, n, A_ + (k << 31), C_ + (k << 20), scales=(X_ + (k << 20)) if dt == 2 else 0)
+    img = ctypes.c_size_t(0)
+    L.sb_gemv_batched_table_bytes(arr, count, ctypes.byref(img))
+    buf = (ctypes.c_ubyte * img.value)()
+    assert L.sb_gemv_batched_encode(arr, count, ctypes.c_void_p(1 << 44), buf, img.value) == 0
+    _, ntiles, total_cost, nitems, items_off, lists_off, grid = struct.unpack_from("<qqqqqqi", buf, 0)
+    assert nitems > grid == 1024
+    lists = struct.unpack_from(f"<{grid + 1}i", buf, lists_off)
+    recs = [struct.unpack_from("<iiii8q", buf, 64 + 144 * k) for k in range(count)]
+    tiles = [r[9] * r[3] for r in recs]          # row tiles x splits
+    cost = [r[11] for r in recs]                 # per-tile cost
+    seen = [np.zeros(t, dtype=np.int32) for t in tiles]
+    loads, biggest = [], 0
+    for b in range(grid):
+        load, prev = 0, (-1, -1)
+        for j in range(lists[b], lists[b + 1]):
+            prob, cnt, first = struct.unpack_from("<iiq", buf, items_off + 16 * j)
+            assert (prob, first) > prev            # problem and tile order within a group
+            prev = (prob, first)
+            seen[prob][first:first + cnt] += 1
+            load += cnt * cost[prob]
+            biggest = max(biggest, cnt * cost[prob])
+        loads.append(load)
+    assert all(np.all(v == 1) for v in seen) and sum(tiles) == ntiles
+    assert sum(loads) == total_cost and max(loads) - min(loads) <= biggest
+
+
 def test_batched_validation(L):
     import paper_2108_02025_amd as sb
     bad = [
