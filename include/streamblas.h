@@ -259,8 +259,10 @@ sb_status sb_dot2_f32(sb_handle* handle, int64_t n, const float* x, const float*
  * a launch, so many row-major problems c += A x share one persistent launch.
  * Each problem is cut into tiles of rows_per_tile rows by one column chunk
  * (split chunks per row; split > 1 is split-K: per-chunk partial sums are
- * added in chunk order, then the initial c); a fixed grid of workgroups
- * takes contiguous ranges of the numbered tiles.  A problem's result depends
+ * added in chunk order, then the initial c).  Runs of consecutive tiles of
+ * one problem form work items, which the encoder deals to the workgroups of
+ * a fixed grid, largest first in rounds of alternating direction, so the
+ * workgroups' shares differ by at most one item.  A problem's result depends
  * only on the problem and its configuration, so it is bit-identical alone and
  * in any mix.  The same per-row arithmetic as sb_gemv / sb_gemv_q is used.
  *
@@ -270,7 +272,8 @@ sb_status sb_dot2_f32(sb_handle* handle, int64_t n, const float* x, const float*
  *          c_i += s_i * sum_j q_ij x_j.
  *   group  lanes cooperating on a row: 4, 8, 16, 32 or 64 (0: automatic).
  *   rows_per_tile  a multiple of 4 * (64 / group) (0: automatic, about
- *          256 KiB of A per tile; the tile height never changes a row's result).
+ *          256 KiB of A per tile and at most 8 row passes of a workgroup;
+ *          the tile height never changes a row's result).
  *   split  column chunks; each chunk's x must fit 32 KiB of LDS (0: automatic).
  * Outputs of different problems must not overlap.  Problems with m = 0 or
  * n = 0 are skipped.
@@ -287,8 +290,9 @@ typedef struct {
     void* c;
 } sb_gemv_desc;
 
-/* Device bytes of the batch table (header, problem records, split counters
- * and split scratch) for these descriptors; *image_bytes (if not NULL)
+/* Device bytes of the batch table (header, problem records, work items and
+ * the per-workgroup item lists, split counters and split scratch) for these
+ * descriptors; *image_bytes (if not NULL)
  * receives the size of the part sb_gemv_batched_encode writes.  Returns
  * (size_t)-1 for invalid descriptors. */
 size_t sb_gemv_batched_table_bytes(const sb_gemv_desc* descs, int32_t count, size_t* image_bytes);
@@ -305,9 +309,11 @@ sb_status sb_gemv_batched_encode(const sb_gemv_desc* descs, int32_t count, void*
                                  void* host_image, size_t image_bytes);
 
 /* Launch the persistent kernel over the table at dev_table on the handle's
- * stream (grid workgroups; 0 = 1024).  The tile count is read from the
- * table, so a captured launch can be replayed over new tables written to
- * the same address.  The table stays valid for further launches. */
+ * stream (grid workgroups; 0 = 1024, the grid the items are dealt to; a
+ * smaller grid runs several workgroups' lists per workgroup).  Everything
+ * the kernel needs is read from the table, so a captured launch can be
+ * replayed over new tables written to the same address.  The table stays
+ * valid for further launches. */
 sb_status sb_gemv_batched_run(sb_handle* handle, const void* dev_table, int32_t grid);
 
 /* Encode, copy the table into the handle's workspace (needs
