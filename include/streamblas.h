@@ -349,7 +349,8 @@ sb_status sb_plan_destroy(sb_plan* plan);
  * is (f - 2^23) * 2^-23 with f = z_(e>>1) >> 40 for even e and
  * (z_(e>>1) >> 8) & 0xFFFFFF for odd e (exact in binary32, no binary64
  * arithmetic).  Both lie in [-1, 1).  out must be aligned to the element
- * size; count >= 0.
+ * size; count >= 0; for SB_F32 the counters counter0 .. counter0 + count - 1
+ * must not wrap past 2^64 (SB_EINVAL).
  */
 sb_status sb_fill_uniform(sb_handle* handle, sb_dtype dtype, void* out, int64_t count, uint64_t seed,
                           uint64_t counter0);

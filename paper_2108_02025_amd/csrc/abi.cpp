@@ -473,6 +473,8 @@ sb_status sb_fill_uniform(sb_handle* handle, sb_dtype dtype, void* out, int64_t 
     if (count < 0 || count > kMaxBytes / 8) return fail(handle, SB_EINVAL, "sb_fill_uniform: bad count");
     if (count > 0 && (!out || misaligned(out, esize_of(dtype))))
         return fail(handle, SB_EINVAL, "sb_fill_uniform: NULL or misaligned output");
+    if (dtype == SB_F32 && count > 0 && counter0 > ~(uint64_t)0 - (uint64_t)(count - 1))
+        return fail(handle, SB_EINVAL, "sb_fill_uniform: binary32 counters counter0 .. counter0 + count - 1 wrap past 2^64");
     SB_GUARD_BEGIN
     return sb::run_fill_uniform(handle, dtype, out, count, seed, counter0);
     SB_GUARD_END

@@ -331,6 +331,16 @@ def test_batched_items_dealt_evenly_large_batch(L):
     assert sum(loads) == total_cost and max(loads) - min(loads) <= biggest
 
 
+def test_fill_counter_range(L, h):
+    """Binary32 fills take two values per counter pair, so their counter
+    range may not wrap past 2^64; binary64 fills may."""
+    out = ctypes.c_void_p(FAKE)
+    top = (1 << 64) - 1
+    assert L.sb_fill_uniform(h, 1, out, 2, ctypes.c_uint64(top), ctypes.c_uint64(top)) == -1
+    assert b"wrap" in L.sb_last_error(h)
+    assert L.sb_fill_uniform(h, 1, out, 0, ctypes.c_uint64(0), ctypes.c_uint64(top)) == 0
+
+
 def test_batched_validation(L):
     import paper_2108_02025_amd as sb
     bad = [
