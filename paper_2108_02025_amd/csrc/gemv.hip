@@ -47,6 +47,11 @@ namespace sb {
 #ifndef SB_GEMV_N_WAVES_PER_CU
 #define SB_GEMV_N_WAVES_PER_CU 32
 #endif
+// x above 80 KiB (one workgroup per compute unit): 8 waves, each streaming
+// one row with 16 loads in flight per lane, measured faster than 16 waves.
+#ifndef SB_GEMV_N_NT_HUGE
+#define SB_GEMV_N_NT_HUGE 512
+#endif
 #ifndef SB_GEMV_N_SPLIT_MIN_BYTES
 #define SB_GEMV_N_SPLIT_MIN_BYTES (32ll << 20)
 #endif
@@ -210,7 +215,7 @@ static void shape_gemv_n(GemvNPlan& p, int esize, int64_t rows)
 {
     const int W = 16 / esize;
     p.lds = (size_t)round_up(p.KC * esize, 16);
-    p.NT = p.lds > 80 * 1024 ? 1024 : (p.lds > 40 * 1024 ? 512 : 256);
+    p.NT = p.lds > 80 * 1024 ? SB_GEMV_N_NT_HUGE : (p.lds > 40 * 1024 ? 512 : 256);
     const int64_t waves_per_block = p.NT / 64;
     const int64_t bpc = std::max<int64_t>(1, std::min<int64_t>(kLdsPerCU / (int64_t)p.lds,
                                                               SB_GEMV_N_WAVES_PER_CU / waves_per_block));

@@ -37,15 +37,15 @@ namespace sb {
 #ifndef SB_GEMV2_LOAD_NT
 #define SB_GEMV2_LOAD_NT 1
 #endif
-// Workgroups are sized so that one round fills the chip (16 waves per
-// compute unit at the kernel's register use): measured faster than two
-// rounds, whose extra workgroup starts and row-band partials cost more than
-// the load balance they buy.
+// Workgroups are sized so that one round fills the chip: measured faster
+// than two rounds, whose extra workgroup starts and row-band partials cost
+// more than the load balance they buy.  Eight waves per compute unit (one
+// workgroup of at most eight waves) beat sixteen: fewer rows stream at once.
 #ifndef SB_GEMV2_WAVES_PER_CU
-#define SB_GEMV2_WAVES_PER_CU 16
+#define SB_GEMV2_WAVES_PER_CU 8
 #endif
 #ifndef SB_GEMV2_MAX_WAVES
-#define SB_GEMV2_MAX_WAVES 16
+#define SB_GEMV2_MAX_WAVES 8
 #endif
 constexpr bool kGemv2NT = SB_GEMV2_LOAD_NT;
 #ifndef SB_GEMV2_ROWS

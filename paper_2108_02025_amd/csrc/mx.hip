@@ -45,13 +45,28 @@
 #define SB_GEMVMX_WAVES_PER_CU 32
 #endif
 #ifndef SB_GEMVMX_NT_BIG
-#define SB_GEMVMX_NT_BIG 512
+#define SB_GEMVMX_NT_BIG 1024
+#endif
+// x above 40 KiB: one workgroup of 1024 threads per compute unit.
+#ifndef SB_GEMVMX_BIG_WGS_PER_CU
+#define SB_GEMVMX_BIG_WGS_PER_CU 1
+#endif
+#ifndef SB_GEMVMX_UNROLL_BIG
+#define SB_GEMVMX_UNROLL_BIG 4
 #endif
 #ifndef SB_GEMVMX_STAGE_MAX
 #define SB_GEMVMX_STAGE_MAX (128 * 1024)
 #endif
 
 namespace sb {
+
+// 16-byte loads in flight per lane: a 1024-thread workgroup (x above 40 KiB,
+// one workgroup per compute unit) keeps fewer per lane than the 256-thread
+// ones of shorter rows, several of which share a compute unit.
+constexpr int mx_unroll(bool fp4, int nt)
+{
+    return nt >= 1024 ? SB_GEMVMX_UNROLL_BIG : (fp4 ? SB_GEMVMX_UNROLL_FP4 : SB_GEMVMX_UNROLL_FP8);
+}
 
 constexpr bool kGemvMxNT = SB_GEMVMX_LOAD_NT;
 
@@ -223,7 +238,7 @@ struct GemvMxArgs {
 template <bool FP4, int G, int NT>
 __global__ __launch_bounds__(NT, SB_GEMVMX_MIN_WAVES) void gemv_mx_kernel(GemvMxArgs a)
 {
-    constexpr int U = FP4 ? SB_GEMVMX_UNROLL_FP4 : SB_GEMVMX_UNROLL_FP8;
+    constexpr int U = mx_unroll(FP4, NT);
     constexpr int NW = NT / kWave, GW = kWave / G;
     extern __shared__ __align__(16) unsigned char smem[];
     float* xs = reinterpret_cast<float*>(smem);
@@ -294,12 +309,14 @@ static GemvMxPlan plan_gemv_mx(bool fp4, int64_t m, int64_t n)
         p.nsplit = ceil_div(n, p.KC);
     }
     p.lds = (size_t)(round_up(p.KC, P) * 4);  // chunk-major x: whole vectors
-    p.NT = p.lds > 80 * 1024 ? 1024 : (p.lds > 40 * 1024 ? SB_GEMVMX_NT_BIG : 256);
+    const bool big = p.lds > 40 * 1024;
+    p.NT = p.lds > 80 * 1024 ? 1024 : (big ? SB_GEMVMX_NT_BIG : 256);
     const int64_t wpb = p.NT / 64;
-    const int64_t bpc =
-        std::max<int64_t>(1, std::min<int64_t>((160 * 1024) / (int64_t)p.lds, SB_GEMVMX_WAVES_PER_CU / wpb));
+    const int64_t bpc = std::max<int64_t>(
+        1, std::min<int64_t>((160 * 1024) / (int64_t)p.lds,
+                             big ? SB_GEMVMX_BIG_WGS_PER_CU : SB_GEMVMX_WAVES_PER_CU / wpb));
     const int64_t nvec = ceil_div(p.KC, P);
-    const int64_t U = fp4 ? SB_GEMVMX_UNROLL_FP4 : SB_GEMVMX_UNROLL_FP8;
+    const int64_t U = mx_unroll(fp4, p.NT);
     int G = 64;
     while (G > 4 && nvec < (int64_t)G * U) G >>= 1;
     p.G = G;

@@ -23,7 +23,7 @@
 
 // Build-time launch constants (overridable with -D for tuning sweeps).
 #ifndef SB_GEMVQ_UNROLL_BF16
-#define SB_GEMVQ_UNROLL_BF16 2
+#define SB_GEMVQ_UNROLL_BF16 4
 #endif
 #ifndef SB_GEMVQ_UNROLL_E4M3
 #define SB_GEMVQ_UNROLL_E4M3 8
@@ -42,6 +42,18 @@
 #endif
 #ifndef SB_GEMVQ_WAVES_PER_CU
 #define SB_GEMVQ_WAVES_PER_CU 32
+#endif
+// x above 40 KiB: threads per workgroup, and workgroups per compute unit.
+// One workgroup per unit (x staged once per unit, half as many rows
+// streaming at once) measured faster than two.
+#ifndef SB_GEMVQ_NT_BIG_BF16
+#define SB_GEMVQ_NT_BIG_BF16 512
+#endif
+#ifndef SB_GEMVQ_NT_BIG_E4M3
+#define SB_GEMVQ_NT_BIG_E4M3 512
+#endif
+#ifndef SB_GEMVQ_BIG_WGS_PER_CU
+#define SB_GEMVQ_BIG_WGS_PER_CU 1
 #endif
 
 namespace sb {
@@ -171,9 +183,12 @@ static GemvQPlan plan_gemv_q(sb_dtype q, int64_t m, int64_t n, int R)
         p.nsplit = ceil_div(n, p.KC);
     }
     p.lds = (size_t)round_up(p.KC * 4, 16);
-    p.NT = p.lds > 80 * 1024 ? 1024 : (p.lds > 40 * 1024 ? 512 : 256);
+    const bool big = p.lds > 40 * 1024;
+    p.NT = p.lds > 80 * 1024 ? 1024 : (big ? (q == SB_BF16 ? SB_GEMVQ_NT_BIG_BF16 : SB_GEMVQ_NT_BIG_E4M3) : 256);
     const int64_t wpb = p.NT / 64;
-    const int64_t bpc = std::max<int64_t>(1, std::min<int64_t>((160 * 1024) / (int64_t)p.lds, SB_GEMVQ_WAVES_PER_CU / wpb));
+    const int64_t bpc = std::max<int64_t>(
+        1, std::min<int64_t>((160 * 1024) / (int64_t)p.lds,
+                             big ? SB_GEMVQ_BIG_WGS_PER_CU : SB_GEMVQ_WAVES_PER_CU / wpb));
     const int64_t nvec = ceil_div(p.KC, P);
     int G = 64;
     const int64_t U = q == SB_BF16 ? SB_GEMVQ_UNROLL_BF16 : SB_GEMVQ_UNROLL_E4M3;

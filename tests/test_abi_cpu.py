@@ -150,7 +150,8 @@ def test_gemv2_validation_and_workspace(L, h):
     assert g2(n=0, lda=1, A=None, x=None, y=None, c=None, d=None) == 0
     ws = L.sb_workspace_bytes
     # 16384 x 16384 binary64: 8 column bands of 2048 and 32 row bands of 512
-    assert ws(None, 6, 0, 0, 0, 16384, 16384) == 8 * 16384 * 8 + 32 * 16384 * 8
+    # 8-wave bands of 1024 columns (16 bands), 16 row bands of 1024 rows
+    assert ws(None, 6, 0, 0, 0, 16384, 16384) == 16 * 16384 * 8 + 16 * 16384 * 8
     assert ws(None, 6, 0, 1, 0, 16384, 16384) == ws(None, 6, 0, 0, 0, 16384, 16384)
     assert ws(None, 6, 0, 0, 0, 64, 64) == 0       # one band each way: direct update
     assert ws(None, 6, 2, 0, 0, 64, 64) == (1 << 64) - 1
