@@ -58,7 +58,9 @@ def test_gemv_1024_uniform_bound(sb, op, layout):
 @pytest.mark.parametrize("op", [0, 1])
 @pytest.mark.parametrize("m,n", [(1, 1), (1, 7), (7, 1), (2, 3), (3, 2), (63, 65), (64, 64), (65, 63),
                                  (127, 129), (129, 4093), (4093, 129), (5, 33000), (33000, 5),
-                                 (300, 40000), (17, 70001)])
+                                 (300, 40000), (17, 70001),
+                                 # launch-shape boundaries: x just above 40 KiB, 80 KiB, 128 KiB
+                                 (37, 10241), (21, 20483), (13, 16384), (11, 16387)])
 def test_gemv_edge_sizes(sb, dt, op, m, n):
     npd = NP[dt]
     A, x, c0 = workloads.gemv_inputs(m, n, seed=m * 7 + n, dist="normal", op_t=bool(op), dtype=npd)

@@ -161,7 +161,8 @@ def test_gemv_q_integer_exact_and_shapes(sb, q):
     enc = oracle.bf16_from_f32 if q == "bf16" else oracle.e4m3_from_f32
     cdt = np.uint16 if q == "bf16" else np.uint8
     rng = np.random.default_rng(71)
-    for m, n in ((1, 1), (3, 17), (100, 1000), (513, 4099), (64, 70001)):
+    # 10241 and 20483 columns put x just above 40 KiB and 80 KiB (launch-shape boundaries)
+    for m, n in ((1, 1), (3, 17), (100, 1000), (513, 4099), (64, 70001), (37, 10241), (9, 20483)):
         Aint = rng.integers(-8, 9, (m, n)).astype(np.float32)
         xs = rng.integers(-8, 9, n).astype(np.float32)
         table = {v: enc(float(v)) for v in range(-8, 9)}

@@ -115,7 +115,8 @@ def run_gemv_mx(sb, codes, scales, q, x, c0, **pad):
 
 
 @pytest.mark.parametrize("q", QS)
-@pytest.mark.parametrize("m,n", [(1, 7), (3, 32), (40, 1000), (257, 4096), (70, 33000), (1000, 777)])
+@pytest.mark.parametrize("m,n", [(1, 7), (3, 32), (40, 1000), (257, 4096), (70, 33000), (1000, 777),
+                                 (37, 10241), (9, 20483)])   # x just above 40 KiB and 80 KiB
 def test_gemv_mx_bound(sb, q, m, n):
     A, x, c0 = workloads.gemv_inputs(m, n, seed=m + 3 * n, dist="normal", dtype=np.float32)
     codes, scales = oracle.quantize_mx(A, q)
