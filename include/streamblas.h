@@ -363,7 +363,8 @@ sb_status sb_fill_uniform(sb_handle* handle, sb_dtype dtype, void* out, int64_t 
  * SB_F32 stores binary32 A; SB_BF16 stores the bfloat16 codes and per-row
  * scales that sb_quantize_rows would make from that binary32 A (bit for
  * bit; with n = 0 every scale is 1).  One launch on the handle's stream; the descriptors are copied into
- * the workspace first (sb_generate_batched_bytes bytes).
+ * the workspace first (sb_generate_batched_bytes bytes).  Work items are
+ * blocks of rows of about 4096 values (a single row when rows are longer).
  */
 typedef struct {
     int32_t dtype;

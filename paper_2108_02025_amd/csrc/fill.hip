@@ -132,17 +132,24 @@ sb_status run_fill_uniform(sb_handle* h, sb_dtype dt, void* out, int64_t count, 
 
 // ---- batched materialisation of GEMV requests -----------------------------
 //
-// One launch makes the operands of many requests: every row of every A is a
-// work item (binary32 rows are generated in place; bfloat16 rows are
-// generated, reduced to their amax and encoded, exactly as sb_fill_uniform
-// followed by sb_quantize_rows would produce them), plus one item per
-// request for x (counters m*n ... m*n + n - 1) and the zeroed c.
+// One launch makes the operands of many requests: every block of rpi rows
+// of every A is a work item (binary32 rows are generated in place; bfloat16
+// rows are generated, reduced to their amax and encoded, exactly as
+// sb_fill_uniform followed by sb_quantize_rows would produce them), plus one
+// item per request for x (counters m*n ... m*n + n - 1) and the zeroed c.
+// rpi is 1 for rows of SB_GEN_ITEM_ELEMS values or more and grows as rows
+// get shorter, so that no item is much smaller than that many values: the
+// cost of starting an item (finding its request, a chain of dependent
+// loads) is then spread over a useful amount of work.
+#ifndef SB_GEN_ITEM_ELEMS
+#define SB_GEN_ITEM_ELEMS 4096
+#endif
 
 struct GenHeader {
     int64_t count, nitems, pad[6];
 };
 struct GenRec {
-    int32_t dtype, pad;
+    int32_t dtype, rpi;  // rpi: rows per work item
     int64_t m, n, lda;
     uint64_t seed;
     void* A;
@@ -153,10 +160,10 @@ struct GenRec {
 };
 static_assert(sizeof(GenHeader) == 64 && sizeof(GenRec) == 80, "generator table layout");
 
-// One wave per work item (four items per workgroup): rows are short (the
-// serving trace's median is a few hundred values), so the item's overhead —
-// finding its request and, for bfloat16, reducing the row's amax — stays
-// inside the wave, with no workgroup barriers.  A bfloat16 row of up to
+// One wave per work item (four items per workgroup): items are small (the
+// serving trace's median row is a few hundred values), so an item's
+// overhead — finding its request and, for bfloat16, reducing each row's
+// amax — stays inside the wave, with no workgroup barriers.  A bfloat16 row of up to
 // kStashW values keeps its values in the wave's share of LDS between the
 // amax pass and the encoding pass; longer rows are generated twice.  The
 // row scale is a power of two, so dividing by it equals multiplying by its
@@ -165,6 +172,38 @@ static_assert(sizeof(GenHeader) == 64 && sizeof(GenRec) == 80, "generator table 
 #define SB_GEN_STASH 2048
 #endif
 constexpr int64_t kStashW = SB_GEN_STASH;  // 8 KiB per wave, 32 KiB per workgroup
+
+// One bfloat16 row: generate it, reduce its amax, encode it with the row
+// scale (rows of up to kStashW values are generated once, their values kept
+// in the wave's LDS stash between the two passes).
+__device__ __forceinline__ void bf16_row(const GenRec& r, int64_t row, uint64_t c0, float* st, int lane)
+{
+    const bool kept = r.n <= kStashW;
+    float amax = 0.0f;
+    f32_stream<kWave>(r.seed, c0, r.n, lane, [&](int64_t j, float v) {
+        if (kept) st[j] = v;
+        const float a = fabsf(v);
+        if (a == a && a > amax) amax = a;
+    });
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, kWave));
+    const float s = row_scale(true, amax);
+    const float inv = s >= 0x1.0p-126f ? 1.0f / s : 0.0f;
+    if (lane == 0) r.scales[row] = s;
+    uint16_t* Qr = static_cast<uint16_t*>(r.A) + row * r.lda;
+    auto enc = [&](int64_t j, float v) { Qr[j] = bf16_encode(inv != 0.0f ? v * inv : v / s); };
+    if (kept) {
+        // the elements this lane stashed in the first pass
+        const int64_t n = r.n;
+        for_pairs<kWave>(c0, n, lane, [&](uint64_t, int64_t j) {
+            if (j >= 0) enc(j, st[j]);
+            if (j + 1 < n) enc(j + 1, st[j + 1]);
+        });
+    } else {
+        f32_stream<kWave>(r.seed, c0, r.n, lane, enc);
+    }
+}
+
 __global__ __launch_bounds__(256) void generate_kernel(const unsigned char* table)
 {
     __shared__ float stash[256 / kWave][kStashW];
@@ -181,39 +220,26 @@ __global__ __launch_bounds__(256) void generate_kernel(const unsigned char* tabl
             else hi = mid - 1;
         }
         const GenRec r = recs[lo];
-        const int64_t row = item - r.item0;
+        const int64_t blk = item - r.item0;
         // bfloat16 rows exist even when n = 0: their scale is 1, as the
         // quantiser gives a row whose largest magnitude is 0
-        if (row < ((r.n > 0 || r.dtype == SB_BF16) ? r.m : 0)) {
-            const uint64_t c0 = (uint64_t)(row * r.n);
-            if (r.dtype == SB_F32) {
-                float* Ar = static_cast<float*>(r.A) + row * r.lda;
-                f32_stream<kWave>(r.seed, c0, r.n, lane, [&](int64_t j, float v) { Ar[j] = v; });
+        const int64_t rows = (r.n > 0 || r.dtype == SB_BF16) ? r.m : 0;
+        if (blk * r.rpi < rows) {
+            const int64_t r0 = blk * r.rpi, r1 = min(rows, r0 + r.rpi);
+            if (r.dtype == SB_F32 && r.lda == r.n) {
+                // consecutive rows are consecutive counters and addresses
+                float* Ab = static_cast<float*>(r.A) + r0 * r.n;
+                f32_stream<kWave>(r.seed, (uint64_t)(r0 * r.n), (r1 - r0) * r.n, lane,
+                                  [&](int64_t j, float v) { Ab[j] = v; });
             } else {
-                float* st = stash[threadIdx.x / kWave];
-                const bool kept = r.n <= kStashW;
-                float amax = 0.0f;
-                f32_stream<kWave>(r.seed, c0, r.n, lane, [&](int64_t j, float v) {
-                    if (kept) st[j] = v;
-                    const float a = fabsf(v);
-                    if (a == a && a > amax) amax = a;
-                });
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, kWave));
-                const float s = row_scale(true, amax);
-                const float inv = s >= 0x1.0p-126f ? 1.0f / s : 0.0f;
-                if (lane == 0) r.scales[row] = s;
-                uint16_t* Qr = static_cast<uint16_t*>(r.A) + row * r.lda;
-                auto enc = [&](int64_t j, float v) { Qr[j] = bf16_encode(inv != 0.0f ? v * inv : v / s); };
-                if (kept) {
-                    // the elements this lane stashed in the first pass
-                    const int64_t n = r.n;
-                    for_pairs<kWave>(c0, n, lane, [&](uint64_t, int64_t j) {
-                        if (j >= 0) enc(j, st[j]);
-                        if (j + 1 < n) enc(j + 1, st[j + 1]);
-                    });
-                } else {
-                    f32_stream<kWave>(r.seed, c0, r.n, lane, enc);
+                for (int64_t row = r0; row < r1; ++row) {
+                    const uint64_t c0 = (uint64_t)(row * r.n);
+                    if (r.dtype == SB_F32) {
+                        float* Ar = static_cast<float*>(r.A) + row * r.lda;
+                        f32_stream<kWave>(r.seed, c0, r.n, lane, [&](int64_t j, float v) { Ar[j] = v; });
+                    } else {
+                        bf16_row(r, row, c0, stash[threadIdx.x / kWave], lane);
+                    }
                 }
             }
         } else {
@@ -266,7 +292,10 @@ sb_status sb_generate_batched(sb_handle* handle, const sb_gen_desc* descs, int32
             r.x = d.x;
             r.c = d.c;
             r.item0 = items;
-            items += ((d.n > 0 || d.dtype == SB_BF16) ? d.m : 0) + 1;  // the rows of A, then x and c
+            const int64_t rows = (d.n > 0 || d.dtype == SB_BF16) ? d.m : 0;
+            r.rpi = (int32_t)std::max<int64_t>(1, std::min<int64_t>(SB_GEN_ITEM_ELEMS / std::max<int64_t>(d.n, 1),
+                                                                     std::max<int64_t>(rows, 1)));
+            items += (rows + r.rpi - 1) / r.rpi + 1;  // the row blocks of A, then x and c
             (void)es;
         }
         hdr->count = count;

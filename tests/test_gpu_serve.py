@@ -129,8 +129,10 @@ def test_generate_batched_matches_fill_and_quantise(sb):
     import ctypes
 
     from paper_2108_02025_amd.serve import GEN_DESC, Request, device_bytes, materialise
+    # short rows are dealt in blocks of several rows per work item (ragged last blocks)
     shapes = [("f32", 5, 7), ("bf16", 64, 8192), ("bf16", 300, 1000), ("f32", 1000, 300), ("bf16", 3, 0),
-              ("f32", 0, 5), ("bf16", 1, 1)]
+              ("f32", 0, 5), ("bf16", 1, 1), ("f32", 700, 64), ("bf16", 513, 33), ("f32", 129, 31),
+              ("bf16", 2, 5000), ("f32", 3, 4097)]
     stage = torch.empty(8192 * 8192, dtype=torch.float32, device="cuda")
     gen = np.zeros(len(shapes), dtype=GEN_DESC)
     bufs, refs = [], []
@@ -154,6 +156,39 @@ def test_generate_batched_matches_fill_and_quantise(sb):
     torch.cuda.synchronize()
     for (kind, m, n), b, ref in zip(shapes, bufs, refs):
         assert torch.equal(b, ref), (kind, m, n)
+
+
+def test_generate_batched_padded_rows(sb):
+    """With lda > n each row holds the same values as in the packed layout
+    and the padding is left untouched."""
+    import ctypes
+
+    from paper_2108_02025_amd.serve import GEN_DESC, Request, device_bytes, materialise
+    up = lambda v: (v + 255) // 256 * 256  # noqa: E731
+    stage = torch.empty(1 << 20, dtype=torch.float32, device="cuda")
+    for kind, m, n, pad in (("f32", 37, 100, 3), ("bf16", 37, 100, 5), ("f32", 300, 40, 1), ("bf16", 200, 21, 2)):
+        es = 4 if kind == "f32" else 2
+        lda = n + pad
+        r = Request(0, 0.0, kind, m, n, 77)
+        ref = torch.full((device_bytes(kind, m, n),), 0x5A, dtype=torch.uint8, device="cuda")
+        materialise(ref, 0, kind, m, n, r.seed, stage)
+        a, s_, x = up(es * m * lda), up(4 * m) if kind == "bf16" else 0, up(4 * n)
+        b = torch.full((a + s_ + x + up(4 * m),), 0x5A, dtype=torch.uint8, device="cuda")
+        base = b.data_ptr()
+        gen = np.zeros(1, dtype=GEN_DESC)
+        gen[0] = (2 if kind == "bf16" else 1, 0, m, n, lda, r.seed, base, base + a if s_ else 0, base + a + s_,
+                  base + a + s_ + x)
+        L = sb.load()
+        h = sb.Handle()
+        h.prepare(int(L.sb_generate_batched_bytes(1)))
+        h.check(L.sb_generate_batched(h.h, ctypes.c_void_p(gen.ctypes.data), 1))
+        torch.cuda.synchronize()
+        got, want = host(b), host(ref)
+        A = got[:es * m * lda].reshape(m, lda * es)
+        assert np.array_equal(A[:, :n * es], want[:es * m * n].reshape(m, n * es)), (kind, m, n, lda)
+        assert (A[:, n * es:] == 0x5A).all() and (got[es * m * lda:a] == 0x5A).all()
+        a0 = up(es * m * n)
+        assert np.array_equal(got[a:a + s_ + x + 4 * m], want[a0:a0 + s_ + x + 4 * m]), (kind, m, n, lda)
 
 
 def test_tuner_quick_and_tuned_serving(sb, tmp_path):
