@@ -431,7 +431,7 @@ static sb_status layout(const sb_gemv_desc* d, int32_t count, BatLayout& L, char
 
 // Deal the work items (in problem and tile order in L.items) to the
 // workgroups, largest first (close to the longest-processing-time-first
-// rule, in linear time after the sort).
+// rule, in linear time after sorting at most two runs per problem).
 // Writes the items grouped by workgroup, each group still in problem and
 // tile order (so consecutive tiles of one problem reuse the staged x), and
 // the grid + 1 group offsets.
@@ -444,10 +444,31 @@ static void deal_items(const BatLayout& L, BatItem* out, int32_t* lists)
         for (int32_t b = 0; b <= grid; ++b) lists[b] = (int32_t)std::min<size_t>((size_t)b, n);
         return;
     }
-    // (-cost, index): ascending order is largest first, ties in item order
-    std::vector<std::pair<int64_t, uint32_t>> order(n);
-    for (size_t j = 0; j < n; ++j) order[j] = {-(L.items[j].count * L.tile_cost[L.items[j].problem]), (uint32_t)j};
-    std::sort(order.begin(), order.end());
+    // The items in (-cost, index) order (largest first, ties in item order).
+    // A problem's items are consecutive and cost the same except its last
+    // one, so that order is a sequence of runs of consecutive items: sort the
+    // runs by (-cost, first index) rather than the items themselves (runs of
+    // equal cost cover disjoint index ranges, so the order is the same).
+    struct Run {
+        int64_t neg_cost;
+        size_t first, len;
+    };
+    std::vector<Run> runs;
+    for (size_t j = 0; j < n;) {
+        const int32_t p = L.items[j].problem;
+        const int64_t c = L.items[j].count * L.tile_cost[p];
+        size_t k = j + 1;
+        while (k < n && L.items[k].problem == p && L.items[k].count * L.tile_cost[p] == c) ++k;
+        runs.push_back(Run{-c, j, k - j});
+        j = k;
+    }
+    std::sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) {
+        return a.neg_cost != b.neg_cost ? a.neg_cost < b.neg_cost : a.first < b.first;
+    });
+    std::vector<uint32_t> order(n);
+    size_t at = 0;
+    for (const Run& r : runs)
+        for (size_t j = r.first; j < r.first + r.len; ++j) order[at++] = (uint32_t)j;
     // Largest first in rounds of `grid` items, alternating direction (the
     // snake order): round 0 gives workgroup b the (b+1)-th largest item,
     // round 1 pairs it with the (2*grid-b)-th, and so on, so each round
@@ -456,7 +477,7 @@ static void deal_items(const BatLayout& L, BatItem* out, int32_t* lists)
     std::vector<int32_t> owner(n);
     for (size_t k = 0; k < n; ++k) {
         const size_t r = k / (size_t)grid, pos = k % (size_t)grid;
-        owner[order[k].second] = (int32_t)((r & 1) ? (size_t)grid - 1 - pos : pos);
+        owner[order[k]] = (int32_t)((r & 1) ? (size_t)grid - 1 - pos : pos);
     }
     std::vector<int32_t> fill(grid + 1, 0);
     for (size_t j = 0; j < n; ++j) ++fill[owner[j] + 1];

@@ -214,6 +214,21 @@ GEN_DESC = np.dtype([("dtype", "<i4"), ("reserved", "<i4"), ("m", "<i8"), ("n", 
 assert GEMV_DESC.itemsize == 72 and GEN_DESC.itemsize == 72
 
 
+_STREAMS: dict[int, tuple[torch.cuda.Stream, torch.cuda.Stream]] = {}
+
+
+def serving_streams(device: torch.device) -> tuple[torch.cuda.Stream, torch.cuda.Stream]:
+    """The execution and generation streams of a device, created once per
+    process and shared by every Server on it.  HIP spreads streams over a few
+    hardware queues in creation order; a fresh pair per Server could land on
+    one queue, where the generation launches and the batched launches would
+    run one after another instead of side by side."""
+    idx = device.index or 0
+    if idx not in _STREAMS:
+        _STREAMS[idx] = (torch.cuda.Stream(device=device), torch.cuda.Stream(device=device))
+    return _STREAMS[idx]
+
+
 class Server:
     """See the module docstring.  `tuning` maps (kind, m, n) to a
     configuration dict for the batched kernel (or None for automatic)."""
@@ -233,8 +248,7 @@ class Server:
         self.use_graphs = use_graphs
         self.tuning = tuning
         self.sample_every = sample_every
-        self.exec_stream = torch.cuda.Stream(device=self.device)
-        self.gen_stream = torch.cuda.Stream(device=self.device)
+        self.exec_stream, self.gen_stream = serving_streams(self.device)
         self.gen_handle = Handle(self.device.index)
         self.tables = [BatchTable(table_bytes, self.device) for _ in range(max_inflight)]
         self.graphs: list[torch.cuda.CUDAGraph | None] = [None] * max_inflight
