@@ -123,6 +123,15 @@ def test_serve_graphs_off_same_bits(sb):
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_servers_share_their_streams(sb):
+    """Every Server on a device uses the process's one pair of execution and
+    generation streams (two different streams)."""
+    from paper_2108_02025_amd.serve import Server
+    a, b = Server(budget_bytes=32 << 20, table_bytes=1 << 20), Server(budget_bytes=64 << 20, table_bytes=1 << 20)
+    assert a.exec_stream is b.exec_stream and a.gen_stream is b.gen_stream
+    assert a.exec_stream.cuda_stream != a.gen_stream.cuda_stream
+
+
 def test_generate_batched_matches_fill_and_quantise(sb):
     """One sb_generate_batched launch makes the same operands, bit for bit,
     as sb_fill_uniform followed by sb_quantize_rows."""
