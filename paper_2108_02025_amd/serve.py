@@ -250,6 +250,8 @@ class Server:
         self.sample_every = sample_every
         self.exec_stream, self.gen_stream = serving_streams(self.device)
         self.gen_handle = Handle(self.device.index)
+        with torch.cuda.stream(self.gen_stream):
+            self.gen_handle.prepare(1 << 16)  # bound to the generation stream from here on
         self.tables = [BatchTable(table_bytes, self.device) for _ in range(max_inflight)]
         self.graphs: list[torch.cuda.CUDAGraph | None] = [None] * max_inflight
 
@@ -301,10 +303,14 @@ class Server:
         torch.cuda.synchronize()
 
     def _generate(self, gen: np.ndarray) -> None:
+        """One sb_generate_batched launch on the generation stream."""
         from . import load
         L = load()
         h = self.gen_handle
-        h.prepare(int(L.sb_generate_batched_bytes(len(gen))))
+        need = int(L.sb_generate_batched_bytes(len(gen)))
+        if h._ws is None or h._ws.numel() < need:
+            with torch.cuda.stream(self.gen_stream):
+                h.prepare(max(need, 1 << 16))
         h.check(L.sb_generate_batched(h.h, ctypes.c_void_p(gen.ctypes.data), len(gen)))
 
     def run(self, trace: list[Request], warm_requests: int = 512) -> Stats:
@@ -337,6 +343,30 @@ class Server:
             for i, r in enumerate(trace):
                 c = self.tuning(r.kind, r.m, r.n) or {}
                 cfg[i] = (c.get("group", 0), c.get("rows_per_tile", 0), c.get("split", 0))
+        # Every request's generation and GEMV descriptors, built once with
+        # addresses relative to its operand block; a turn of the loop gathers
+        # the rows it needs and adds the blocks' device addresses.
+        rel = np.zeros((N, 4), dtype=np.uint64)  # A, scales, x, c
+        rel[:, 1] = np.where(bf16, a_bytes, 0)
+        rel[:, 2] = a_bytes + s_bytes
+        rel[:, 3] = a_bytes + s_bytes + x_bytes
+        has_s = bf16.astype(np.uint64)
+        gen_all = np.zeros(N, dtype=GEN_DESC)
+        gen_all["dtype"] = np.where(bf16, 2, 1)
+        gen_all["m"], gen_all["n"], gen_all["lda"], gen_all["seed"] = m, n, n, seed
+        desc_all = np.zeros(N, dtype=GEMV_DESC)
+        desc_all["dtype"] = np.where(bf16, 2, 1)
+        desc_all["group"], desc_all["rows_per_tile"], desc_all["split"] = cfg[:, 0], cfg[:, 1], cfg[:, 2]
+        desc_all["m"], desc_all["n"], desc_all["lda"] = m, n, n
+
+        def addresses(table, ids):
+            base = (self.base + offset[ids]).astype(np.uint64)
+            table["A"] = base
+            table["scales"] = (base + rel[ids, 1]) * has_s[ids]
+            table["x"] = base + rel[ids, 2]
+            table["c"] = base + rel[ids, 3]
+            return table
+
         offset = np.full(N, -1, dtype=np.int64)
         t_admit = np.full(N, np.nan)
         t_launch = np.full(N, np.nan)
@@ -382,33 +412,16 @@ class Server:
             if admitted:
                 ids = np.array(admitted)
                 t_admit[ids] = time.perf_counter() - t0
-                base = self.base + offset[ids]
-                gen = np.zeros(len(ids), dtype=GEN_DESC)
-                gen["dtype"] = np.where(bf16[ids], 2, 1)
-                gen["m"], gen["n"], gen["lda"], gen["seed"] = m[ids], n[ids], n[ids], seed[ids]
-                gen["A"] = base
-                gen["scales"] = np.where(bf16[ids], base + a_bytes[ids], 0)
-                gen["x"] = base + a_bytes[ids] + s_bytes[ids]
-                gen["c"] = base + a_bytes[ids] + s_bytes[ids] + x_bytes[ids]
-                with torch.cuda.stream(self.gen_stream):
-                    self._generate(gen)
-                    gen_event = torch.cuda.Event()
-                    gen_event.record()
+                self._generate(addresses(gen_all[ids], ids))
+                gen_event = torch.cuda.Event()
+                gen_event.record(self.gen_stream)
                 ready.extend(admitted)
             # continuous batching: launch whatever is ready when a table is free
             if ready and free_tables:
                 k = free_tables.popleft()
                 ids = np.array(ready[: self.max_batch])
                 ready = ready[self.max_batch:]
-                base = self.base + offset[ids]
-                d = np.zeros(len(ids), dtype=GEMV_DESC)
-                d["dtype"] = np.where(bf16[ids], 2, 1)
-                d["group"], d["rows_per_tile"], d["split"] = cfg[ids, 0], cfg[ids, 1], cfg[ids, 2]
-                d["m"], d["n"], d["lda"] = m[ids], n[ids], n[ids]
-                d["A"] = base
-                d["scales"] = np.where(bf16[ids], base + a_bytes[ids], 0)
-                d["x"] = base + a_bytes[ids] + s_bytes[ids]
-                d["c"] = base + a_bytes[ids] + s_bytes[ids] + x_bytes[ids]
+                d = addresses(desc_all[ids], ids)
                 with torch.cuda.stream(self.exec_stream):
                     self.exec_stream.wait_event(gen_event)
                     start = torch.cuda.Event(enable_timing=True)
