@@ -369,7 +369,8 @@ def main():
 
     import paper_2108_02025_amd as sb
     sb.load()
-    assert torch.cuda.is_available(), "no GPU visible"
+    if not torch.cuda.is_available():
+        sys.exit("bench.py: no GPU visible")
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     sel = set(args.ops.split(",")) if args.ops else None
