@@ -22,7 +22,12 @@ by the step time.  Per-operation times come from HIP events recorded on the
 stream the library launches on, one between consecutive operations, created
 without the system-scope fence (``--fenced-events`` uses default events).
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu] [--ops a,b]
+Besides the step, the JSON line reports the HBM read/copy ceilings, small
+problem latencies (``small``), the GEMVs on the skewed shapes 262144x256,
+256x262144, 65536x4096 and 65537x4093 in binary64 and binary32
+(``skewed``), the serving trace (``serving``) and the CPU oracle baseline.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu] [--no-serve] [--no-small] [--no-skewed] [--ops a,b]
 """
 from __future__ import annotations
 
@@ -346,6 +351,43 @@ def small_problems(sb, torch, dev):
     return res
 
 
+def skewed_shapes(sb, torch, dev, reps=10):
+    """Per-call time of the GEMVs on the skewed shapes (tall-skinny
+    262144x256, short-wide 256x262144, 65536x4096 and 65537x4093 with packed
+    rows) in binary64 and binary32, normal(0,1) entries: median of `reps`
+    event-timed calls, each after a 2 GiB write that evicts x from the
+    caches."""
+    ev = HipEvents(torch)
+    junk = torch.empty(1 << 28, dtype=torch.float64, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(12)
+    res = {}
+    for dt, es, tname in ((torch.float64, 8, "f64"), (torch.float32, 4, "f32")):
+        for m, n in ((262144, 256), (256, 262144), (65536, 4096), (65537, 4093)):
+            A = torch.randn((m, n), generator=g, device=dev, dtype=dt)
+            for op, label, xl, cl in ((sb.SB_N, "gemv_n", n, m), (sb.SB_T, "gemv_t", m, n)):
+                x = torch.randn(xl, generator=g, device=dev, dtype=dt)
+                c = torch.randn(cl, generator=g, device=dev, dtype=dt)
+                nb = es * (m * n + xl + 2 * cl)
+                sb.sb_gemv(A, x, c, op=op)
+                t = []
+                for _ in range(reps):
+                    junk.fill_(0.5)
+                    a = ev.record()
+                    sb.sb_gemv(A, x, c, op=op)
+                    b = ev.record()
+                    torch.cuda.synchronize()
+                    t.append(1e3 * ev.ms(a, b))
+                ev.close()
+                us = sorted(t)[len(t) // 2]
+                res[f"{label}_{tname}_{m}x{n}"] = {"us": round(us, 2), "GB/s": round(nb / us / 1e3, 1),
+                                                   "frac_hbm": round(nb / us / 1e3 / PEAK_HBM_GBS, 4)}
+            del A
+    del junk
+    log("skewed shapes: " + ", ".join(f"{k} {v['GB/s']} GB/s" for k, v in res.items()))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -356,6 +398,7 @@ def main():
     ap.add_argument("--no-probes", action="store_true", help="skip the HBM read/copy ceiling probes")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
     ap.add_argument("--no-small", action="store_true", help="skip the small-problem latencies")
+    ap.add_argument("--no-skewed", action="store_true", help="skip the skewed-shape GEMVs")
     ap.add_argument("--fenced-events", action="store_true",
                     help="time with default HIP events (system-scope release at every event)")
     args = ap.parse_args()
@@ -439,6 +482,8 @@ def main():
     }
     if not args.no_small:
         out["small"] = small_problems(sb, torch, dev)
+    if not args.no_skewed:
+        out["skewed"] = skewed_shapes(sb, torch, dev)
     if not args.no_serve:
         from paper_2108_02025_amd.serve import Server, make_trace
         from paper_2108_02025_amd.tuner import TuningTable

@@ -130,7 +130,7 @@ __device__ __attribute__((noinline)) void bat_rows(const BatProblem& p, int64_t 
         if constexpr (DT == SB_F64 || DT == SB_F32) {
             typedef typename std::conditional<DT == SB_F64, double, float>::type T;
             const T* Ar = static_cast<const T*>(p.A) + row * p.lda + k0;
-            T t = row_dot<T, G, kBatUnrollPlain, AL, true>(Ar, klen, reinterpret_cast<const T*>(xs_raw), l);
+            T t = row_dot<T, G, kBatUnrollPlain, AL, true, false>(Ar, klen, reinterpret_cast<const T*>(xs_raw), l);
             t = group_sum<G>(t);
             if (l == 0) {
                 if (p.S > 1) static_cast<T*>(p.partial)[s * p.m + row] = t;
@@ -141,7 +141,7 @@ __device__ __attribute__((noinline)) void bat_rows(const BatProblem& p, int64_t 
             typedef typename C::code_t code_t;
             constexpr int U = DT == SB_BF16 ? kBatUnrollBf16 : kBatUnrollE4m3;
             float t[1];
-            tile_dot<C, G, U, 1, true>(static_cast<const code_t*>(p.A) + row * p.lda + k0, p.lda, klen,
+            tile_dot<C, G, U, 1, true, false>(static_cast<const code_t*>(p.A) + row * p.lda + k0, p.lda, klen,
                                        reinterpret_cast<const float*>(xs_raw), l, t);
             float v = group_sum<G>(t[0]);
             if (l == 0) {

@@ -129,7 +129,9 @@ __global__ __launch_bounds__(NT) void gemv_t_kernel(GemvTArgs<T> a)
 {
     constexpr int W = ALIGNED ? Vec<T>::W : 1;
     typedef typename std::conditional<ALIGNED, typename Vec<T>::type, T>::type V;
-    constexpr int U = kUnrollT;
+    // rows in flight per wave: element loads (rows not 16-byte aligned) move
+    // fewer bytes each, so keep more of them in flight
+    constexpr int U = ALIGNED ? kUnrollT : 16 / sizeof(T) * kUnrollT;
     constexpr int NW = NT / kWave;
     constexpr int CW = kWave * W;
     __shared__ T red[NW][CW];
@@ -163,14 +165,27 @@ __global__ __launch_bounds__(NT) void gemv_t_kernel(GemvTArgs<T> a)
                 }
             }
         }
-        for (; i < i1; i += NW) {
-            const V av = ld_stream<kGemvNT>(reinterpret_cast<const V*>(a.A + i * a.ld + j0));
-            const T xv = a.x[i];
-            if constexpr (W == 1) {
-                acc[0] += av * xv;
-            } else {
+        if (i < i1) {
+            // fewer than U rows remain for this wave: one predicated batch,
+            // added in row order as above
+            V av[U];
+            T xv[U];
 #pragma unroll
-                for (int q = 0; q < W; ++q) acc[q] += av[q] * xv;
+            for (int u = 0; u < U; ++u) {
+                const bool in = i + u * NW < i1;
+                av[u] = in ? ld_stream<kGemvNT>(reinterpret_cast<const V*>(a.A + (i + u * NW) * a.ld + j0)) : (V)0;
+                xv[u] = in ? a.x[i + u * NW] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (i + u * NW < i1) {
+                    if constexpr (W == 1) {
+                        acc[0] += av[u] * xv[u];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < W; ++q) acc[q] += av[u][q] * xv[u];
+                    }
+                }
             }
         }
     } else if (j0 < a.cols) {

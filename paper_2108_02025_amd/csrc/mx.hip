@@ -219,7 +219,20 @@ __device__ __forceinline__ float mx_row_dot(const uint8_t* Qr, const uint8_t* Sr
             __builtin_amdgcn_sched_barrier(0);
         }
     }
-    for (; v < nv; v += G) step(ld_stream<kGemvMxNT>(Qv + v), Sr[(v * P) >> 5], v, 0);
+    if (v < nv) {
+        // fewer than U vectors remain for this lane: one predicated batch
+        v4u wv[U];
+        uint32_t sc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool in = v + u * G < nv;
+            wv[u] = in ? ld_stream<kGemvMxNT>(Qv + v + u * G) : v4u{0, 0, 0, 0};
+            sc[u] = in ? Sr[((v + u * G) * P) >> 5] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (v + u * G < nv) step(wv[u], sc[u], v + u * G, 0);
+    }
     for (int64_t e = nv * P + l; e < klen; e += G)
         acc[1] += mx_scaled(C::one(Qr, e) * xs[xs_slot<P>(e, NVC)], Sr[e >> 5]);
     return (acc[0] + acc[1]) + (acc[2] + acc[3]);

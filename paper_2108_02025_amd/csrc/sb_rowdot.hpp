@@ -17,7 +17,11 @@ namespace sb {
 // Plain binary64 / binary32 row segment.  ALIGNED: the row start is 16-byte
 // aligned (true for every row when A and ld*sizeof(T) are), so x can be read
 // from LDS as vectors; otherwise up to W-1 leading elements are peeled.
-template <typename T, int G, int U, bool ALIGNED, bool NTL>
+// BATCH_TAIL: the vectors left after the full batches of U (fewer than U
+// per lane) are loaded as one predicated batch, all in flight together;
+// otherwise one at a time (fewer registers).  The additions happen in the
+// same order either way.
+template <typename T, int G, int U, bool ALIGNED, bool NTL, bool BATCH_TAIL = true>
 __device__ __forceinline__ T row_dot(const T* Ar, int64_t klen, const T* xs, int l)
 {
     typedef typename Vec<T>::type V;
@@ -49,7 +53,23 @@ __device__ __forceinline__ T row_dot(const T* Ar, int64_t klen, const T* xs, int
             }
         }
     }
-    for (; v < nv; v += G) {
+    if (BATCH_TAIL && v < nv) {
+        // fewer than U vectors remain for this lane: one predicated batch
+        // (all its loads in flight together), added in the same order
+        V av[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) av[u] = v + u * G < nv ? ld_stream<NTL>(Av + v + u * G) : (V)0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (v + u * G < nv) {
+                const int64_t e = (v + u * G) * W;
+#pragma unroll
+                for (int q = 0; q < W; ++q) acc[q] += av[u][q] * xb[e + q];
+            }
+        }
+        v += U * G;
+    }
+    for (; v < nv; v += G) {  // not taken after a batched tail
         const V av = ld_stream<NTL>(Av + v);
         const int64_t e = v * W;
 #pragma unroll
@@ -108,7 +128,7 @@ template <> struct Codes<false> {
 // codes apart) with the staged x, for lane l of a group of G lanes.  All R
 // rows must share the same 16-byte alignment.  A lane's additions happen in
 // the same order for any U and R, so the result does not depend on them.
-template <class C, int G, int U, int R, bool NTL>
+template <class C, int G, int U, int R, bool NTL, bool BATCH_TAIL = true>
 __device__ __forceinline__ void tile_dot(const typename C::code_t* Q0, int64_t ldq, int64_t klen,
                                          const float* xs, int l, float (&t)[R])
 {
@@ -176,7 +196,30 @@ __device__ __forceinline__ void tile_dot(const typename C::code_t* Q0, int64_t l
     };
     if (xal) main_loop(std::true_type{});
     else main_loop(std::false_type{});
-    for (; v < nv; v += G) {
+    if (BATCH_TAIL && v < nv) {
+        // fewer than U vectors remain for this lane: one predicated batch
+        v4u wv[U][R];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) wv[u][r] = v + u * G < nv ? ld_stream<NTL>(Qv[r] + v + u * G) : v4u{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (v + u * G < nv) {
+                const float* xe = xb + (v + u * G) * P;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    float f[P];
+                    C::unpack(wv[u][r], f);
+#pragma unroll
+                    for (int q = 0; q < P; ++q) acc[r][q & 3] += f[q] * xe[q];
+                }
+            }
+        }
+        v += U * G;
+    }
+    for (; v < nv; v += G) {  // not taken after a batched tail
         const float* xe = xb + v * P;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
