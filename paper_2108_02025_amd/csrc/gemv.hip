@@ -115,6 +115,16 @@ __global__ __launch_bounds__(256) void split_finish_kernel(int64_t len, int64_t 
 }
 
 template <typename T>
+struct GemvTElemArgs {
+    int64_t rows, cols, ld;
+    const T* A;
+    const T* x;
+    T* c;
+    T* partial;  // nsplit x cols, or nullptr when nsplit == 1
+    int64_t RS;
+};
+
+template <typename T>
 struct GemvTArgs {
     int64_t rows, cols, ld;
     const T* A;
@@ -212,6 +222,50 @@ __global__ __launch_bounds__(NT) void gemv_t_kernel(GemvTArgs<T> a)
             }
         }
     }
+}
+
+// Column-axpy for rows that are not 16-byte aligned (element loads): each
+// wave owns 64 consecutive columns and walks every row of its split, the
+// four waves of a workgroup side by side, so that the cache lines a row's
+// 256-column stretch shares with its neighbours at the edges are fetched by
+// one workgroup (row starts then fall anywhere in a line).  A lane adds its
+// column's products in row order.
+template <typename T>
+__global__ __launch_bounds__(256) void gemv_t_elem_kernel(GemvTElemArgs<T> a)
+{
+    constexpr int U = 32;  // rows in flight per wave
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t j = (int64_t)blockIdx.x * 256 + w * kWave + lane;
+    const int64_t s = blockIdx.y;
+    const int64_t i0 = s * a.RS, i1 = min(a.rows, i0 + a.RS);
+    if (j >= a.cols) return;  // no barriers below
+    const T* Aj = a.A + j;
+    T acc = 0;
+    int64_t i = i0;
+    for (; i + U - 1 < i1; i += U) {
+        T av[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            av[u] = ld_stream<kGemvNT>(Aj + (i + u) * a.ld);
+            xv[u] = a.x[i + u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += av[u] * xv[u];
+    }
+    if (i < i1) {
+        T av[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool in = i + u < i1;
+            av[u] = in ? ld_stream<kGemvNT>(Aj + (i + u) * a.ld) : T(0);
+            xv[u] = in ? a.x[i + u] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i + u < i1) acc += av[u] * xv[u];
+    }
+    if (a.partial) a.partial[s * a.cols + j] = acc;
+    else a.c[j] = a.c[j] + acc;
 }
 
 // ---------------------------------------------------------------- plans ---
@@ -378,7 +432,11 @@ static sb_status gemv_t_typed(sb_handle* h, int64_t rows, int64_t cols, const T*
     const bool al = aligned16(A) && ((ld * (int64_t)sizeof(T)) % 16 == 0);
     const int64_t CW = 64 * (al ? 16 / (int64_t)sizeof(T) : 1);
     const dim3 grid((unsigned)ceil_div(cols, CW), (unsigned)p.nsplit);
-    if (p.NT == 1024) {
+    if (!al && p.NT == 256) {
+        GemvTElemArgs<T> e{rows, cols, ld, A, x, c, a.partial, p.RS};
+        hipLaunchKernelGGL(gemv_t_elem_kernel<T>, dim3((unsigned)ceil_div(cols, 256), (unsigned)p.nsplit), dim3(256),
+                           0, h->stream, e);
+    } else if (p.NT == 1024) {
         if (al) hipLaunchKernelGGL((gemv_t_kernel<T, 1024, true>), grid, dim3(1024), 0, h->stream, a);
         else hipLaunchKernelGGL((gemv_t_kernel<T, 1024, false>), grid, dim3(1024), 0, h->stream, a);
     } else {

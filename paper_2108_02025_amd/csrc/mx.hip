@@ -203,7 +203,10 @@ __device__ __forceinline__ float mx_row_dot(const uint8_t* Qr, const uint8_t* Sr
         acc[slot] += mx_scaled((part[0] + part[1]) + (part[2] + part[3]), sc);
     };
     int64_t v = l;
-    for (; v + (U - 1) * G < nv; v += U * G) {
+    // full batches (as many as every lane of the group has), then the rest
+    // in one predicated batch
+    const int64_t vfull = nv / (U * G) * (U * G);
+    for (; v < vfull; v += U * G) {
         v4u wv[U];
         uint32_t sc[U];
 #pragma unroll
@@ -231,7 +234,7 @@ __device__ __forceinline__ float mx_row_dot(const uint8_t* Qr, const uint8_t* Sr
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (v + u * G < nv) step(wv[u], sc[u], v + u * G, 0);
+            if (v + u * G < nv) step(wv[u], sc[u], v + u * G, u & 3);
     }
     for (int64_t e = nv * P + l; e < klen; e += G)
         acc[1] += mx_scaled(C::one(Qr, e) * xs[xs_slot<P>(e, NVC)], Sr[e >> 5]);

@@ -38,7 +38,10 @@ __device__ __forceinline__ T row_dot(const T* Ar, int64_t klen, const T* xs, int
     const V* Av = reinterpret_cast<const V*>(Ar + head);
     const T* xb = xs + head;
     int64_t v = l;
-    for (; v + (U - 1) * G < nv; v += U * G) {
+    // Full batches: with BATCH_TAIL as many as every lane of the group has
+    // (the same count for the whole wave), the rest in one predicated batch.
+    const int64_t vfull = BATCH_TAIL ? nv / (U * G) * (U * G) : nv - (U - 1) * G;
+    for (; v < vfull && v + (U - 1) * G < nv; v += U * G) {
         V av[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) av[u] = ld_stream<NTL>(Av + v + u * G);
@@ -150,11 +153,14 @@ __device__ __forceinline__ void tile_dot(const typename C::code_t* Q0, int64_t l
 #pragma unroll
     for (int r = 0; r < R; ++r) Qv[r] = reinterpret_cast<const v4u*>(Q0 + r * ldq + head);
     int64_t v = l;
+    // Full batches: with BATCH_TAIL as many as every lane of the group has
+    // (the same count for the whole wave), the rest in one predicated batch.
+    const int64_t vfull = BATCH_TAIL ? nv / (U * G) * (U * G) : nv - (U - 1) * G;
     // Main loop: U loads per row in flight, then one straight-line step per
     // load (the x-alignment choice is hoisted so each step is one block).
     auto main_loop = [&](auto xal_tag) {
         constexpr bool XAL = decltype(xal_tag)::value;
-        for (; v + (U - 1) * G < nv; v += U * G) {
+        for (; v < vfull && v + (U - 1) * G < nv; v += U * G) {
             v4u wv[U][R];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
