@@ -105,6 +105,25 @@ __global__ __launch_bounds__(NT) void gemv_n_kernel(GemvNArgs<T> a)
 }
 
 // out[i] = out[i] + sum over splits of partial[s * len + i], splits in order.
+// Deep splits (more than kWaveFinishSplits): one wave per output; lane l adds
+// splits l, l + 64, ... in order (loads 8 ahead), then the lanes' sums are
+// combined by a butterfly, a fixed order, so that no thread waits on a long
+// chain of dependent loads (512 splits took 25-29 us one thread per output).
+constexpr int64_t kWaveFinishSplits = 32;
+template <typename T>
+__global__ __launch_bounds__(256) void split_finish_wave_kernel(int64_t len, int64_t nsplit,
+                                                                const T* partial, T* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;  // wave-uniform
+    const int lane = threadIdx.x & (kWave - 1);
+    if (i >= len) return;
+    T t = lane < nsplit ? ordered_split_sum<8>(partial + lane * len + i, (nsplit - lane + kWave - 1) / kWave,
+                                               kWave * len)
+                        : T(0);
+    t = group_sum<kWave>(t);
+    if (lane == 0) out[i] = out[i] + t;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void split_finish_kernel(int64_t len, int64_t nsplit,
                                                            const T* partial, T* out)
@@ -398,6 +417,18 @@ static bool dispatch_n(int NT, int G, const GemvNArgs<T>& a, dim3 grid, size_t l
     return false;
 }
 
+// out[i] += the nsplit partial sums of output i (len outputs).
+template <typename T>
+static void launch_split_finish(hipStream_t st, int64_t len, int64_t nsplit, const T* partial, T* out)
+{
+    if (nsplit > kWaveFinishSplits)
+        hipLaunchKernelGGL(split_finish_wave_kernel<T>, dim3((unsigned)ceil_div(len, 256 / kWave)), dim3(256), 0, st,
+                           len, nsplit, partial, out);
+    else
+        hipLaunchKernelGGL(split_finish_kernel<T>, dim3((unsigned)ceil_div(len, 256)), dim3(256), 0, st, len,
+                           nsplit, partial, out);
+}
+
 template <typename T>
 static sb_status gemv_n_typed(sb_handle* h, int64_t rows, int64_t cols, const T* A, int64_t ld,
                               const T* x, T* c)
@@ -416,8 +447,7 @@ static sb_status gemv_n_typed(sb_handle* h, int64_t rows, int64_t cols, const T*
     if (!ok) return fail(h, SB_EINTERNAL, "no gemv_n instance for NT=%d G=%d", p.NT, p.G);
     sb_status st = check_launch(h, "gemv_n_kernel");
     if (st != SB_OK || p.nsplit == 1) return st;
-    hipLaunchKernelGGL(split_finish_kernel<T>, dim3((unsigned)ceil_div(rows, 256)), dim3(256), 0,
-                       h->stream, rows, p.nsplit, static_cast<const T*>(h->ws), c);
+    launch_split_finish<T>(h->stream, rows, p.nsplit, static_cast<const T*>(h->ws), c);
     return check_launch(h, "split_finish_kernel");
 }
 
@@ -445,8 +475,7 @@ static sb_status gemv_t_typed(sb_handle* h, int64_t rows, int64_t cols, const T*
     }
     sb_status st = check_launch(h, "gemv_t_kernel");
     if (st != SB_OK || p.nsplit == 1) return st;
-    hipLaunchKernelGGL(split_finish_kernel<T>, dim3((unsigned)ceil_div(cols, 256)), dim3(256), 0,
-                       h->stream, cols, p.nsplit, static_cast<const T*>(h->ws), c);
+    launch_split_finish<T>(h->stream, cols, p.nsplit, static_cast<const T*>(h->ws), c);
     return check_launch(h, "split_finish_kernel");
 }
 
