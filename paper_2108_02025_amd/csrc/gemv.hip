@@ -19,8 +19,9 @@
 //    Used for row-major T and column-major N.
 //
 // Splits (of columns for row-dot, of rows for col-axpy) write partial sums
-// to the workspace and a second kernel adds them in split order, then adds
-// the initial output.  No atomics anywhere: every output has one owner, and
+// to the workspace and a second kernel adds them in split order (above 32
+// splits: 64 in-order partial chains combined by a fixed butterfly), then
+// adds the initial output.  No atomics anywhere: every output has one owner, and
 // the summation order depends only on the shape, so results are
 // reproducible bit for bit.
 #include <algorithm>
