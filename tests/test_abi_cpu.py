@@ -293,7 +293,8 @@ def test_batched_resolve_encode_on_host(L):
 def test_batched_items_dealt_evenly_large_batch(L):
     """A batch with more work items than workgroups: the items are dealt in
     alternating rounds, largest first; every tile is run exactly once and no
-    workgroup ends above another by more than the largest item."""
+    workgroup ends above another by more than the largest item.  The deal is
+    exactly the snake over the items ordered by (-cost, creation index)."""
     import struct
 
     import numpy as np
@@ -317,19 +318,25 @@ def test_batched_items_dealt_evenly_large_batch(L):
     tiles = [r[9] * r[3] for r in recs]          # row tiles x splits
     cost = [r[11] for r in recs]                 # per-tile cost
     seen = [np.zeros(t, dtype=np.int32) for t in tiles]
-    loads, biggest = [], 0
+    loads, biggest, dealt = [], 0, {}
     for b in range(grid):
         load, prev = 0, (-1, -1)
         for j in range(lists[b], lists[b + 1]):
             prob, cnt, first = struct.unpack_from("<iiq", buf, items_off + 16 * j)
             assert (prob, first) > prev            # problem and tile order within a group
             prev = (prob, first)
+            dealt[prob, first] = (cnt, b)
             seen[prob][first:first + cnt] += 1
             load += cnt * cost[prob]
             biggest = max(biggest, cnt * cost[prob])
         loads.append(load)
     assert all(np.all(v == 1) for v in seen) and sum(tiles) == ntiles
     assert sum(loads) == total_cost and max(loads) - min(loads) <= biggest
+    created = sorted(dealt)                        # creation order: problem, then tile
+    order = sorted(range(len(created)), key=lambda j: (-dealt[created[j]][0] * cost[created[j][0]], j))
+    for k, j in enumerate(order):
+        rnd, pos = divmod(k, grid)
+        assert dealt[created[j]][1] == (grid - 1 - pos if rnd & 1 else pos)
 
 
 def test_fill_counter_range(L, h):
