@@ -195,27 +195,14 @@ __global__ __launch_bounds__(NT) void gemv_t_kernel(GemvTArgs<T> a)
                 }
             }
         }
-        if (i < i1) {
-            // fewer than U rows remain for this wave: one predicated batch,
-            // added in row order as above
-            V av[U];
-            T xv[U];
+        for (; i < i1; i += NW) {
+            const V av = ld_stream<kGemvNT>(reinterpret_cast<const V*>(a.A + i * a.ld + j0));
+            const T xv = a.x[i];
+            if constexpr (W == 1) {
+                acc[0] += av * xv;
+            } else {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool in = i + u * NW < i1;
-                av[u] = in ? ld_stream<kGemvNT>(reinterpret_cast<const V*>(a.A + (i + u * NW) * a.ld + j0)) : (V)0;
-                xv[u] = in ? a.x[i + u * NW] : T(0);
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (i + u * NW < i1) {
-                    if constexpr (W == 1) {
-                        acc[0] += av[u] * xv[u];
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < W; ++q) acc[q] += av[u][q] * xv[u];
-                    }
-                }
+                for (int q = 0; q < W; ++q) acc[q] += av[q] * xv;
             }
         }
     } else if (j0 < a.cols) {
