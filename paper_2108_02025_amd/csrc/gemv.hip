@@ -60,6 +60,12 @@ namespace sb {
 #define SB_GEMV_T_SMALL_SPLITS 2
 #endif
 constexpr int kUnrollN = SB_GEMV_N_UNROLL;  // 16-byte loads in flight per lane and row
+// x above 80 KiB (8 waves per compute unit, whole rows of 10240+ binary64
+// or 20480+ binary32 values): 32 loads in flight per lane
+#ifndef SB_GEMV_N_UNROLL_HUGE
+#define SB_GEMV_N_UNROLL_HUGE 32
+#endif
+constexpr int kUnrollNHuge = SB_GEMV_N_UNROLL_HUGE;
 constexpr int kUnrollT = SB_GEMV_T_UNROLL;  // rows in flight per wave
 constexpr bool kGemvNT = SB_GEMV_LOAD_NT;
 
@@ -74,10 +80,9 @@ struct GemvNArgs {
     int64_t RB;
 };
 
-template <typename T, int G, int NT, bool ALIGNED>
+template <typename T, int G, int NT, bool ALIGNED, int U = kUnrollN>
 __global__ __launch_bounds__(NT) void gemv_n_kernel(GemvNArgs<T> a)
 {
-    constexpr int U = kUnrollN;
     constexpr int NW = NT / kWave, GW = kWave / G;
     extern __shared__ __align__(16) unsigned char smem[];
     T* xs = reinterpret_cast<T*>(smem);
@@ -369,16 +374,16 @@ GemvTPlan plan_gemv_t(int esize, int64_t rows, int64_t cols, int64_t small_split
 
 // ------------------------------------------------------------- launchers ---
 
-template <typename T, int G, int NT, bool AL>
+template <typename T, int G, int NT, bool AL, int U = kUnrollN>
 static void launch_n(const GemvNArgs<T>& a, dim3 grid, size_t lds, hipStream_t st)
 {
     static const bool attr_set = [] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemv_n_kernel<T, G, NT, AL>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemv_n_kernel<T, G, NT, AL, U>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsPerCU);
         return true;
     }();
     (void)attr_set;
-    hipLaunchKernelGGL((gemv_n_kernel<T, G, NT, AL>), grid, dim3(NT), lds, st, a);
+    hipLaunchKernelGGL((gemv_n_kernel<T, G, NT, AL, U>), grid, dim3(NT), lds, st, a);
 }
 
 template <typename T, int NT, bool AL>
@@ -430,8 +435,15 @@ static sb_status gemv_n_typed(sb_handle* h, int64_t rows, int64_t cols, const T*
     GemvNArgs<T> a{rows, cols, ld, A, x, c, p.nsplit > 1 ? static_cast<T*>(claim_ws(h)) : nullptr, p.KC, p.RB};
     const bool al = aligned16(A) && ((ld * (int64_t)sizeof(T)) % 16 == 0);
     const dim3 grid((unsigned)ceil_div(rows, p.RB), (unsigned)p.nsplit);
-    const bool ok = al ? dispatch_n<T, true>(p.NT, p.G, a, grid, p.lds, h->stream)
-                       : dispatch_n<T, false>(p.NT, p.G, a, grid, p.lds, h->stream);
+    bool ok = true;
+    if (p.lds > 80 * 1024 && p.NT == SB_GEMV_N_NT_HUGE && p.G == 64) {
+        // whole rows with x above 80 KiB: more loads in flight per lane
+        if (al) launch_n<T, 64, SB_GEMV_N_NT_HUGE, true, kUnrollNHuge>(a, grid, p.lds, h->stream);
+        else launch_n<T, 64, SB_GEMV_N_NT_HUGE, false, kUnrollNHuge>(a, grid, p.lds, h->stream);
+    } else {
+        ok = al ? dispatch_n<T, true>(p.NT, p.G, a, grid, p.lds, h->stream)
+                : dispatch_n<T, false>(p.NT, p.G, a, grid, p.lds, h->stream);
+    }
     if (!ok) return fail(h, SB_EINTERNAL, "no gemv_n instance for NT=%d G=%d", p.NT, p.G);
     sb_status st = check_launch(h, "gemv_n_kernel");
     if (st != SB_OK || p.nsplit == 1) return st;
