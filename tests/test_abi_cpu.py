@@ -368,3 +368,21 @@ def test_batched_validation(L):
     empty = (sb.sb_gemv_desc * 1)(_desc(sb, 1, 0, 10, 0, 0, x=0))
     # header, one record, no items, 1025 list offsets, rounded up to 64
     assert L.sb_gemv_batched_table_bytes(empty, 1, None) == (64 + 144 + 4 * 1025 + 63) // 64 * 64
+
+
+def test_dot2_tree_matches_library_plan(L):
+    """The tests' statement of the compensated DOT's tree (tests/dot2_tree.py)
+    launches the same number of workgroups as the library (read back through
+    the workspace it asks for: one (sum, error) pair of binary32 per
+    workgroup, none for the single-workgroup form)."""
+    import dot2_tree
+    for n in (1, 1000, 32768, 32769, 65536, 100003, 1 << 20, (1 << 24) - 5, 1 << 24, 1 << 27, 3 << 27):
+        p = dot2_tree.plan(n)
+        ws = L.sb_workspace_bytes(None, 4, 1, 0, 0, 1, n)
+        assert ws == (0 if p["small"] else 8 * p["nblocks"]), n
+        if not p["small"]:
+            assert p["chunk"] % 1024 == 0 and (p["nblocks"] - 1) * p["chunk"] < n <= p["nblocks"] * p["chunk"]
+    assert dot2_tree.plan(1 << 27)["nblocks"] == 1024 and dot2_tree.plan(1 << 27)["chunk"] == 131072
+    # 128 vectors per lane (+1 tail), 3 + 6 + 3 in the workgroup, 4 + 6 + 3 in
+    # the second stage, alpha and its final sum
+    assert dot2_tree.path_length(1 << 27) == 129 + 12 + 13 + 2

@@ -9,6 +9,7 @@ import pytest
 import torch
 
 import oracle
+import dot2_tree
 import workloads
 from gpu_util import U32, U64, assert_within, dev, gamma, gemv_bound, host
 
@@ -81,9 +82,9 @@ def test_dot2_across_cutoff(sb):
         got = float(host(ad)[0])
         ex = oracle.dot_exact_f32(x, y, 0.75)
         ab = oracle.dot_exact_f32(x, y, 0.75, absval=True)
-        g = gamma(200, U32)
-        # Dot2's bound (Ogita, Rump and Oishi): u|s| + gamma_L^2 sum|x y|,
-        # plus the final rounding to binary32
+        g = gamma(dot2_tree.path_length(n), U32)
+        # Dot2's bound (Ogita, Rump and Oishi): u|s| + gamma_L^2 sum|x y| with
+        # L the launch's longest addition path, plus the final rounding to binary32
         assert abs(got - ex) <= 2 * U32 * abs(ex) + g * g * ab, (n, got, ex)
 
 

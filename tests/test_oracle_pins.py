@@ -421,6 +421,32 @@ def test_quantize_rows_properties(orc):
                 assert err.max() <= amax[i] * 2.0 ** -4 + 2.0 ** -9 * s[i]
 
 
+def test_quantize_rows_special_values(orc):
+    """Rows holding NaN, infinities, signed zeros and subnormal magnitudes:
+    scales and codes equal the values written by hand from the per-row scale
+    rule (tests/golden/quantize_special_rows.txt): amax over non-NaN entries,
+    s = 1 for amax 0 or infinite, subnormal scales kept, E4M3 saturation of
+    infinities and of a largest entry pushed past 448 by a rounded scale."""
+    from goldens import quantize_special_rows
+    rows, exp = quantize_special_rows()
+    for q, fmt in ((orc.Q_BF16, "bf16"), (orc.Q_E4M3, "e4m3")):
+        codes, s = orc.quantize_rows(rows, q)
+        want_s, want_q = exp[fmt]
+        assert np.array_equal(s.view(np.uint32), want_s), (fmt, s.view(np.uint32), want_s)
+        assert np.array_equal(codes, want_q), (fmt, codes, want_q)
+        # the same rows inside longer rows of zeros: zeros change neither
+        # amax nor the other codes, and encode to +0
+        wide = np.zeros((rows.shape[0], 300), np.float32)
+        pos = [0, 37, 128, 255, 299]
+        wide[:, pos] = rows
+        codes_w, s_w = orc.quantize_rows(wide, q)
+        assert np.array_equal(s_w.view(np.uint32), want_s)
+        assert np.array_equal(codes_w[:, pos], want_q)
+        rest = np.ones(300, bool)
+        rest[pos] = False
+        assert not codes_w[:, rest].any()
+
+
 def test_gemv_q_integer_exact(orc):
     """Unit scales and integer codes: every partial sum is an exact integer."""
     rng = np.random.default_rng(61)
