@@ -140,6 +140,31 @@ sb_status sb_gemv(sb_handle* handle, sb_dtype dtype, sb_layout layout, sb_op op,
                   const void* x, void* c);
 
 /*
+ * GEMV that allocates nothing, for callers that cannot allocate device
+ * memory or lend the library a workspace: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * checks, kernels and result bits as sb_gemv on the same handle, but the
+ * split partial sums go to a static device array of SB_NOALLOC_SCRATCH_BYTES
+ * inside the library instead of the handle's workspace, which is neither
+ * needed nor touched (batched plans on the handle stay valid).
+ *   - One array per GPU: that of the device of the handle's stream.  Its
+ *     device address is looked up (no allocation) on the first call that
+ *     needs it on that device; the array lives until the process ends.
+ *   - Every call on a GPU shares that GPU's array.  Calls that may overlap
+ *     on one GPU (on different streams, or from several host threads) race
+ *     and give wrong results: serialise them.  Calls in order on one stream
+ *     are safe; the array keeps the last call's partial sums and nothing in
+ *     it needs clearing (every partial sum is written before it is read).
+ *   - A shape whose partial sums need more than SB_NOALLOC_SCRATCH_BYTES
+ *     (sb_workspace_bytes of kind SB_KIND_GEMV) returns SB_ENOMEM before any
+ *     HIP call.  Every other error is as for sb_gemv.
+ */
+#define SB_NOALLOC_SCRATCH_BYTES ((size_t)4 << 20)
+sb_status sb_gemv_noalloc(sb_handle* handle, sb_dtype dtype, sb_layout layout, sb_op op,
+                          int64_t m, int64_t n, const void* A, int64_t lda,
+                          const void* x, void* c);
+
+/*
  * Two-sided GEMV: c += A x and d += A^T y in one pass over A.  An extension
  * of the section 3.1 GEMV definition for callers that need both products of
  * one matrix (as in bidiagonalisation, or the BLAS Technical Forum's fused

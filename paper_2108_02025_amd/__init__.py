@@ -24,7 +24,7 @@ __all__ = [
     "SB_KIND_GEMV", "SB_KIND_DOT", "SB_KIND_GER", "SB_KIND_GEMV_Q", "SB_KIND_DOT2", "SB_KIND_GEMV2", "sb_gemv2",
     "StreamBlasError", "load", "lib_path", "Handle", "handle_for",
     "sb_version", "sb_status_string", "sb_workspace_bytes",
-    "sb_gemv", "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32",
+    "sb_gemv", "sb_gemv_noalloc", "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32",
     "sb_stream_read", "sb_stream_copy", "sb_gemv_desc", "GemvProblem", "make_descs", "sb_gemv_batched",
     "sb_gemv_batched_resolve", "sb_gemv_batched_table_bytes", "BatchTable", "sb_fill_uniform",
     "SB_CUTOFF_DOT_SMALL_BYTES", "SB_CUTOFF_GEMV_T_SMALL_SPLITS", "sb_set_cutoff", "sb_get_cutoff",
@@ -85,6 +85,7 @@ def load():
     L.sb_workspace_bytes.argtypes = [P, I32, I32, I32, I32, I64, I64]
     L.sb_workspace_bytes.restype = SZ
     L.sb_gemv.argtypes = [P, I32, I32, I32, I64, I64, P, I64, P, P]
+    L.sb_gemv_noalloc.argtypes = [P, I32, I32, I32, I64, I64, P, I64, P, P]
     L.sb_dot.argtypes = [P, I32, I64, P, P, P]
     L.sb_gemv2.argtypes = [P, I32, I32, I64, I64, P, I64, P, P, P, P]
     L.sb_ger.argtypes = [P, I32, I32, I64, I64, P, P, P, I64]
@@ -109,7 +110,7 @@ def load():
     L.sb_stream_read.argtypes = [P, P, SZ]
     L.sb_stream_copy.argtypes = [P, P, P, SZ]
     for f in ("sb_fill_uniform", "sb_generate_batched", "sb_gemv_batched_resolve", "sb_gemv_batched_encode", "sb_gemv_batched_run", "sb_gemv_batched",
-              "sb_stream_read", "sb_stream_copy", "sb_handle_create", "sb_handle_destroy", "sb_set_stream", "sb_set_workspace", "sb_set_cutoff", "sb_get_cutoff", "sb_gemv", "sb_gemv2",
+              "sb_stream_read", "sb_stream_copy", "sb_handle_create", "sb_handle_destroy", "sb_set_stream", "sb_set_workspace", "sb_set_cutoff", "sb_get_cutoff", "sb_gemv", "sb_gemv_noalloc", "sb_gemv2",
               "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32", "sb_quantize_mx", "sb_gemv_mx",
               "sb_plan_create", "sb_plan_run", "sb_plan_destroy"):
         getattr(L, f).restype = I32
@@ -247,6 +248,26 @@ def sb_gemv(A: torch.Tensor, x: torch.Tensor, c: torch.Tensor, op: int = SB_N) -
     h = handle_for(A)
     h.prepare(sb_workspace_bytes(SB_KIND_GEMV, dt, layout, op, m, n, h))
     h.check(load().sb_gemv(h.h, dt, layout, op, m, n, _ptr(A), ld, _ptr(x), _ptr(c)))
+    return c
+
+
+def sb_gemv_noalloc(A: torch.Tensor, x: torch.Tensor, c: torch.Tensor, op: int = SB_N) -> torch.Tensor:
+    """c += op(A) x in place through the entry point that allocates nothing:
+    the library's static per-GPU scratch replaces the workspace, and this
+    wrapper allocates no device memory either (it only points the handle at
+    the current stream)."""
+    _device_check(A, x, c)
+    _vec(x), _vec(c)
+    dt = _dtype(A)
+    if x.dtype != A.dtype or c.dtype != A.dtype:
+        raise TypeError("A, x and c must share a dtype")
+    layout, ld = _matrix_layout(A)
+    m, n = A.shape
+    if x.numel() != (n if op == SB_N else m) or c.numel() != (m if op == SB_N else n):
+        raise ValueError("x / c lengths do not match op(A)")
+    h = handle_for(A)
+    h.prepare(0)
+    h.check(load().sb_gemv_noalloc(h.h, dt, layout, op, m, n, _ptr(A), ld, _ptr(x), _ptr(c)))
     return c
 
 

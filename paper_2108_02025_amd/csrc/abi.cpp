@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "sb_internal.hpp"
@@ -105,6 +106,111 @@ using sb::fail;
     }                                                                             \
     catch (const std::bad_alloc&) { return fail(handle, SB_EINTERNAL, "out of host memory"); } \
     catch (...) { return fail(handle, SB_EINTERNAL, "unexpected C++ exception"); }
+
+// ---- GEMV argument checks shared by sb_gemv and sb_gemv_noalloc ----------
+
+namespace {
+
+struct GemvCall {
+    sb_status st;
+    bool empty;          // nothing to read or write
+    sb_dtype dtype;
+    bool row_dot;        // kernel N on the row-major view, else kernel T
+    int64_t rows, cols;  // the row-major view
+};
+
+GemvCall check_gemv(const char* fn, sb_handle* handle, sb_dtype dtype, sb_layout layout, sb_op op, int64_t m,
+                    int64_t n, const void* A, int64_t lda, const void* x, void* c)
+{
+    GemvCall g{SB_OK, false, dtype, false, 0, 0};
+    auto bad = [&](sb_status st) { g.st = st; return g; };
+    if (narrow(dtype)) return bad(fail(handle, SB_EUNSUPPORTED, "%s: narrow storage needs sb_gemv_q", fn));
+    if (dtype != SB_F64 && dtype != SB_F32) return bad(fail(handle, SB_EINVAL, "%s: bad dtype %d", fn, (int)dtype));
+    if (layout != SB_ROW_MAJOR && layout != SB_COL_MAJOR)
+        return bad(fail(handle, SB_EINVAL, "%s: bad layout %d", fn, (int)layout));
+    if (op != SB_N && op != SB_T) return bad(fail(handle, SB_EINVAL, "%s: bad op %d", fn, (int)op));
+    if (m < 0 || n < 0)
+        return bad(fail(handle, SB_EINVAL, "%s: negative size m=%lld n=%lld", fn, (long long)m, (long long)n));
+    g.rows = layout == SB_ROW_MAJOR ? m : n;
+    g.cols = layout == SB_ROW_MAJOR ? n : m;
+    if (lda < (g.cols > 1 ? g.cols : 1))
+        return bad(fail(handle, SB_EINVAL, "%s: lda=%lld below %lld", fn, (long long)lda,
+                        (long long)(g.cols > 1 ? g.cols : 1)));
+    const int es = esize_of(dtype);
+    const int64_t a_el = span_elems(g.rows, g.cols, lda);
+    int64_t a_bytes;
+    if (a_el < 0 || !mul_ok(a_el, es, &a_bytes) || a_bytes > kMaxBytes)
+        return bad(fail(handle, SB_EINVAL, "%s: matrix extent overflows", fn));
+    const int64_t lx = op == SB_N ? n : m, lc = op == SB_N ? m : n;
+    g.row_dot = (layout == SB_ROW_MAJOR) == (op == SB_N);
+    // An empty output or an empty reduction reads and writes nothing.
+    if (lc == 0 || lx == 0) {
+        g.empty = true;
+        return g;
+    }
+    if (!A || !x || !c) return bad(fail(handle, SB_EINVAL, "%s: NULL pointer with non-zero extent", fn));
+    if (misaligned(A, es) || misaligned(x, es) || misaligned(c, es))
+        return bad(fail(handle, SB_EINVAL, "%s: pointer not aligned to the element size", fn));
+    const Range rc = range_of(c, lc, es);
+    if (overlap(rc, range_of(A, a_el, es)) || overlap(rc, range_of(x, lx, es)))
+        return bad(fail(handle, SB_EINVAL, "%s: c overlaps A or x", fn));
+    return g;
+}
+
+// Workspace bytes of a checked, non-empty GEMV with the handle's tuning.
+size_t gemv_ws_bytes(const sb_handle* handle, const GemvCall& g)
+{
+    const int es = esize_of(g.dtype);
+    return g.row_dot ? sb::plan_gemv_n(es, g.rows, g.cols).ws
+                     : sb::plan_gemv_t(es, g.rows, g.cols, handle->gemv_t_small_splits).ws;
+}
+
+sb_status run_checked_gemv(sb_handle* h, const GemvCall& g, const void* A, int64_t lda, const void* x, void* c)
+{
+    return g.row_dot ? sb::run_gemv_n(h, g.dtype, g.rows, g.cols, A, lda, x, c)
+                     : sb::run_gemv_t(h, g.dtype, g.rows, g.cols, A, lda, x, c);
+}
+
+// ---- the static scratch of sb_gemv_noalloc -------------------------------
+//
+// One array per GPU in this library's device code, used by sb_gemv_noalloc
+// in place of a workspace.  In host code the name `noalloc_scratch_array`
+// is only a host-side stand-in: its device address is looked up once per
+// device with hipGetSymbolAddress (with that device current) and only that
+// address is ever handed to kernels.
+
+constexpr size_t kNoAllocScratchBytes = SB_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char noalloc_scratch_array[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of the scratch on the device of the handle's stream.
+sb_status noalloc_scratch(sb_handle* h, void** out)
+{
+    int dev = -1, cur = -1;
+    hipError_t e = hipStreamGetDevice(h->stream, &dev);
+    if (e != hipSuccess) return fail(h, SB_EDEVICE, "sb_gemv_noalloc: hipStreamGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(h, SB_EDEVICE, "sb_gemv_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+        void* p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch_array));
+        const hipError_t e_restore = (cur >= 0 && cur != dev) ? hipSetDevice(cur) : hipSuccess;
+        if (e != hipSuccess)
+            return fail(h, SB_EDEVICE, "sb_gemv_noalloc: scratch address on device %d: %s", dev, hipGetErrorString(e));
+        if (e_restore != hipSuccess)
+            return fail(h, SB_EDEVICE, "sb_gemv_noalloc: restoring device %d: %s", cur, hipGetErrorString(e_restore));
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return SB_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -232,33 +338,40 @@ sb_status sb_gemv(sb_handle* handle, sb_dtype dtype, sb_layout layout, sb_op op,
 {
     if (!handle) return fail(nullptr, SB_EINVAL, "sb_gemv: NULL handle");
     SB_GUARD_BEGIN
-    if (narrow(dtype))
-        return fail(handle, SB_EUNSUPPORTED, "sb_gemv: narrow storage needs sb_gemv_q");
-    if (dtype != SB_F64 && dtype != SB_F32) return fail(handle, SB_EINVAL, "sb_gemv: bad dtype %d", (int)dtype);
-    if (layout != SB_ROW_MAJOR && layout != SB_COL_MAJOR) return fail(handle, SB_EINVAL, "sb_gemv: bad layout %d", (int)layout);
-    if (op != SB_N && op != SB_T) return fail(handle, SB_EINVAL, "sb_gemv: bad op %d", (int)op);
-    if (m < 0 || n < 0) return fail(handle, SB_EINVAL, "sb_gemv: negative size m=%lld n=%lld", (long long)m, (long long)n);
-    const int64_t rows = layout == SB_ROW_MAJOR ? m : n, cols = layout == SB_ROW_MAJOR ? n : m;
-    if (lda < (cols > 1 ? cols : 1))
-        return fail(handle, SB_EINVAL, "sb_gemv: lda=%lld below %lld", (long long)lda, (long long)(cols > 1 ? cols : 1));
-    const int es = esize_of(dtype);
-    const int64_t a_el = span_elems(rows, cols, lda);
-    int64_t a_bytes;
-    if (a_el < 0 || !mul_ok(a_el, es, &a_bytes) || a_bytes > kMaxBytes)
-        return fail(handle, SB_EINVAL, "sb_gemv: matrix extent overflows");
-    const int64_t lx = op == SB_N ? n : m, lc = op == SB_N ? m : n;
-    // An empty output or an empty reduction reads and writes nothing.
-    if (lc == 0 || lx == 0) return SB_OK;
-    if (!A || !x || !c)
-        return fail(handle, SB_EINVAL, "sb_gemv: NULL pointer with non-zero extent");
-    if (misaligned(A, es) || misaligned(x, es) || misaligned(c, es))
-        return fail(handle, SB_EINVAL, "sb_gemv: pointer not aligned to the element size");
-    const Range rc = range_of(c, lc, es);
-    if (overlap(rc, range_of(A, a_el, es)) || overlap(rc, range_of(x, lx, es)))
-        return fail(handle, SB_EINVAL, "sb_gemv: c overlaps A or x");
-    const bool row_dot = (layout == SB_ROW_MAJOR) == (op == SB_N);
-    return row_dot ? sb::run_gemv_n(handle, dtype, rows, cols, A, lda, x, c)
-                   : sb::run_gemv_t(handle, dtype, rows, cols, A, lda, x, c);
+    const GemvCall g = check_gemv("sb_gemv", handle, dtype, layout, op, m, n, A, lda, x, c);
+    if (g.st != SB_OK || g.empty) return g.st;
+    return run_checked_gemv(handle, g, A, lda, x, c);
+    SB_GUARD_END
+}
+
+sb_status sb_gemv_noalloc(sb_handle* handle, sb_dtype dtype, sb_layout layout, sb_op op, int64_t m, int64_t n,
+                          const void* A, int64_t lda, const void* x, void* c)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_gemv_noalloc: NULL handle");
+    SB_GUARD_BEGIN
+    const GemvCall g = check_gemv("sb_gemv_noalloc", handle, dtype, layout, op, m, n, A, lda, x, c);
+    if (g.st != SB_OK || g.empty) return g.st;
+    const size_t need = gemv_ws_bytes(handle, g);
+    if (need > kNoAllocScratchBytes)
+        return fail(handle, SB_ENOMEM,
+                    "sb_gemv_noalloc: this shape needs %zu bytes of split partial sums; the static scratch holds %zu",
+                    need, (size_t)kNoAllocScratchBytes);
+    // The same call on a copy of the handle whose workspace is this device's
+    // static scratch: the caller's workspace (and any plan in it) is untouched.
+    sb_handle view = *handle;
+    if (need > 0) {
+        void* p = nullptr;
+        const sb_status st = noalloc_scratch(handle, &p);
+        if (st != SB_OK) return st;
+        view.ws = p;
+        view.ws_bytes = kNoAllocScratchBytes;
+    } else {
+        view.ws = nullptr;
+        view.ws_bytes = 0;
+    }
+    const sb_status st = run_checked_gemv(&view, g, A, lda, x, c);
+    if (st != SB_OK) memcpy(handle->err, view.err, sizeof(handle->err));
+    return st;
     SB_GUARD_END
 }
 

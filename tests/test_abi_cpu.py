@@ -386,3 +386,19 @@ def test_dot2_tree_matches_library_plan(L):
     # 128 vectors per lane (+1 tail), 3 + 6 + 3 in the workgroup, 4 + 6 + 3 in
     # the second stage, alpha and its final sum
     assert dot2_tree.path_length(1 << 27) == 129 + 12 + 13 + 2
+
+
+def test_gemv_noalloc_checks_before_any_hip_call(L, h):
+    """sb_gemv_noalloc validates like sb_gemv and refuses a shape whose split
+    partial sums exceed its static scratch (4 MiB) before any HIP call."""
+    A, X, C = 1 << 44, 1 << 45, (1 << 45) + (1 << 40)
+    assert L.sb_gemv_noalloc(h, 0, 0, 0, 65536, 262144, A, 262144, X, C) == -2
+    assert b"static scratch" in L.sb_last_error(h)
+    assert L.sb_workspace_bytes(h, 0, 0, 0, 0, 65536, 262144) > (4 << 20)
+    assert L.sb_gemv_noalloc(h, 2, 0, 0, 10, 10, A, 10, X, C) == -4      # narrow storage
+    assert L.sb_gemv_noalloc(h, 9, 0, 0, 10, 10, A, 10, X, C) == -1      # bad dtype
+    assert L.sb_gemv_noalloc(h, 0, 0, 0, 10, 10, A, 9, X, C) == -1       # lda below n
+    assert L.sb_gemv_noalloc(h, 0, 0, 0, 10, 10, A, 10, X, A + 8) == -1  # c overlaps A
+    assert b"sb_gemv_noalloc" in L.sb_last_error(h)
+    assert L.sb_gemv_noalloc(h, 0, 0, 0, 0, 10, A, 10, X, C) == 0        # empty output: nothing to do
+    assert L.sb_gemv_noalloc(None, 0, 0, 0, 10, 10, A, 10, X, C) == -1
