@@ -105,22 +105,26 @@ def build_ops(sb, torch, dev, sel):
         A = uni((M, N), 201)
     if want("gemv_n_f64"):
         x, c = uni((N,), 2011), uni((M,), 2012)
-        ops.append(("gemv_n_f64", 8 * (M * N + N + 2 * M), 2 * M * N, lambda: sb.sb_gemv(A, x, c, op=sb.SB_N)))
+        ops.append(("gemv_n_f64", 8 * (M * N + N + 2 * M), 2 * M * N, lambda: sb.sb_gemv(A, x, c, op=sb.SB_N),
+                    {"kind": "gemv", "A": A, "x": x, "c": c, "op": 0}))
     if want("gemv_t_f64"):
         xt, ct = uni((M,), 2013), uni((N,), 2014)
-        ops.append(("gemv_t_f64", 8 * (M * N + M + 2 * N), 2 * M * N, lambda: sb.sb_gemv(A, xt, ct, op=sb.SB_T)))
+        ops.append(("gemv_t_f64", 8 * (M * N + M + 2 * N), 2 * M * N, lambda: sb.sb_gemv(A, xt, ct, op=sb.SB_T),
+                    {"kind": "gemv", "A": A, "x": xt, "c": ct, "op": 1}))
     if want("gemv2_f64"):
         x2, y2, c2, d2 = uni((N,), 2015), uni((M,), 2016), uni((M,), 2017), uni((N,), 2018)
         ops.append(("gemv2_f64", 8 * (M * N + N + M + 2 * M + 2 * N), 4 * M * N,
-                    lambda: sb.sb_gemv2(A, x2, y2, c2, d2)))
+                    lambda: sb.sb_gemv2(A, x2, y2, c2, d2), {"kind": "gemv2", "A": A, "x": x2, "y": y2, "c": c2, "d": d2}))
     if want("dot_f64"):
         log("drawing DOT vectors n=2^28")
         dx, dy, da = uni((nd,), 2021), uni((nd,), 2022), uni((1,), 2023)
-        ops.append(("dot_f64", 8 * (2 * nd + 2), 2 * nd, lambda: sb.sb_dot(dx, dy, da)))
+        ops.append(("dot_f64", 8 * (2 * nd + 2), 2 * nd, lambda: sb.sb_dot(dx, dy, da),
+                    {"kind": "dot", "x": dx, "y": dy, "a": da}))
     if want("ger_f64"):
         log("drawing GER operands 16384x16384")
         gx, gy, gC = uni((M,), 2031), uni((N,), 2032), uni((M, N), 2033)
-        ops.append(("ger_f64", 8 * (2 * M * N + M + N), 2 * M * N, lambda: sb.sb_ger(gx, gy, gC)))
+        ops.append(("ger_f64", 8 * (2 * M * N + M + N), 2 * M * N, lambda: sb.sb_ger(gx, gy, gC),
+                    {"kind": "ger", "x": gx, "y": gy, "C": gC}))
     for q, name, es in ((sb.SB_BF16, "gemv_q_bf16", 2), (sb.SB_FP8_E4M3, "gemv_q_e4m3", 1)):
         if not want(name):
             continue
@@ -134,7 +138,8 @@ def build_ops(sb, torch, dev, sel):
         xq = torch.randn(N, generator=g, device=dev, dtype=torch.float32)
         cq = torch.zeros(M, dtype=torch.float32, device=dev)
         ops.append((name, es * M * N + 4 * N + 8 * M + 4 * M, 2 * M * N,
-                    (lambda Aq=Aq, s=s, xq=xq, cq=cq, q=q: sb.sb_gemv_q(Aq, s, xq, cq, q))))
+                    (lambda Aq=Aq, s=s, xq=xq, cq=cq, q=q: sb.sb_gemv_q(Aq, s, xq, cq, q)),
+                    {"kind": "gemv_q", "A": A, "Q": Aq, "s": s, "x": xq, "c": cq, "q": q}))
     for q, name, rb in ((sb.SB_MXFP8_E4M3, "gemv_mx_fp8", N), (sb.SB_MXFP4_E2M1, "gemv_mx_fp4", N // 2)):
         if not want(name):
             continue
@@ -147,14 +152,16 @@ def build_ops(sb, torch, dev, sel):
         xm = torch.randn(N, generator=g, device=dev, dtype=torch.float32)
         cm = torch.zeros(M, dtype=torch.float32, device=dev)
         ops.append((name, M * rb + M * (N // 32) + 4 * N + 8 * M, 2 * M * N,
-                    (lambda Q=Q, S=S, xm=xm, cm=cm, q=q: sb.sb_gemv_mx(Q, S, xm, cm, q))))
+                    (lambda Q=Q, S=S, xm=xm, cm=cm, q=q: sb.sb_gemv_mx(Q, S, xm, cm, q)),
+                    {"kind": "gemv_mx", "A": A, "Q": Q, "S": S, "x": xm, "c": cm, "q": q}))
     if want("dot2_f32"):
         log("generating ill-conditioned pairs n=2^27 (cond 1e8)")
         import workloads
         hx, hy, ha, cond = workloads.illcond_dot_inputs(n2, seed=402)
         ex, ey = torch.from_numpy(hx).to(dev), torch.from_numpy(hy).to(dev)
         ea = torch.zeros(1, dtype=torch.float32, device=dev)
-        ops.append(("dot2_f32", 4 * (2 * n2 + 2), 2 * n2, lambda: sb.sb_dot2_f32(ex, ey, ea)))
+        ops.append(("dot2_f32", 4 * (2 * n2 + 2), 2 * n2, lambda: sb.sb_dot2_f32(ex, ey, ea),
+                    {"kind": "dot2", "x": ex, "y": ey, "hx": hx, "hy": hy, "cond": cond}))
     torch.cuda.synchronize()
     return ops
 
@@ -227,7 +234,7 @@ def time_ops(torch, ops, steps, fence=False):
     torch.cuda.synchronize()
     marks = [ev.record()]
     for _ in range(steps):
-        for name, _, _, fn in ops:
+        for name, _, _, fn, *_ in ops:
             fn()
             marks.append(ev.record())
     torch.cuda.synchronize()
@@ -322,6 +329,136 @@ def cpu_baseline(step_bytes, thread_counts=(1,)):
     return out
 
 
+def error_stats(sb, torch, ops, rows=4096, mx_rows=1024):
+    """Errors of one fresh call of each step operation on the step's own
+    device operands, against the CPU oracle (part of the oracle leg; the
+    outputs are restored afterwards).  Per operation:
+      max_err_over_bound  max over outputs of |got - oracle| / bound, with
+                          the per-entry bound 2 gamma_{K+1}(u)(|c0| + sum|a||x|)
+                          (binary64 u = 2^-53, binary32 2^-24);
+      normwise            ||got - ref|| / ||ref||;
+    GER must equal the oracle bit for bit (bitwise_equal).  The quantised and
+    MX GEMVs are checked on their first `rows` / `mx_rows` rows: against the
+    oracle on the decoded codes (bound as above in binary32, with |s q| <=
+    1.125|a| + s 2^-9 for the row-scaled formats) and, normwise, against the
+    binary64 product of the unquantised matrix.  Dot2 reports the relative
+    errors of Dot2, the plain binary32 DOT and the plain binary64 DOT on the
+    same pairs against the exact dot."""
+    import numpy as np
+
+    import oracle
+
+    oracle.build()
+
+    def g(k, u):
+        return k * u / (1 - k * u)
+
+    def h(t):
+        return t.detach().cpu().numpy()
+
+    def summarise(got, ref, bound):
+        got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+        err = np.abs(got - ref)
+        return {"max_err_over_bound": float((err / bound).max()), "max_abs_err": float(err.max()),
+                "normwise": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+
+    res = {}
+    for name, _, _, fn, ctx in ops:
+        k = ctx["kind"]
+        t0 = time.perf_counter()
+        if k == "gemv":
+            c0 = ctx["c"].clone()
+            fn()
+            got = h(ctx["c"])
+            A, x, c0h = h(ctx["A"]), h(ctx["x"]), h(c0)
+            ref = oracle.gemv(A, x, c0h, op=ctx["op"])
+            mag = (np.abs(A) @ np.abs(x)) if ctx["op"] == 0 else (np.abs(x) @ np.abs(A))
+            K = A.shape[1] if ctx["op"] == 0 else A.shape[0]
+            res[name] = summarise(got, ref, 2 * g(K + 1, 2.0 ** -53) * (np.abs(c0h) + mag))
+            ctx["c"].copy_(c0)
+        elif k == "gemv2":
+            c0, d0 = ctx["c"].clone(), ctx["d"].clone()
+            fn()
+            A, x, y = h(ctx["A"]), h(ctx["x"]), h(ctx["y"])
+            rc, rd = oracle.gemv2(A, x, y, h(c0), h(d0))
+            bc = 2 * g(A.shape[1] + 1, 2.0 ** -53) * (np.abs(h(c0)) + np.abs(A) @ np.abs(x))
+            bd = 2 * g(A.shape[0] + 1, 2.0 ** -53) * (np.abs(h(d0)) + np.abs(y) @ np.abs(A))
+            sc, sd = summarise(h(ctx["c"]), rc, bc), summarise(h(ctx["d"]), rd, bd)
+            res[name] = {"c": sc, "d": sd}
+            ctx["c"].copy_(c0)
+            ctx["d"].copy_(d0)
+        elif k == "dot":
+            a0 = ctx["a"].clone()
+            fn()
+            x, y = h(ctx["x"]), h(ctx["y"])
+            ref = oracle.dot(x, y, float(h(a0)[0]))
+            bound = 2 * g(x.size + 1, 2.0 ** -53) * (abs(float(h(a0)[0])) + float(np.abs(x) @ np.abs(y)))
+            got = float(h(ctx["a"])[0])
+            res[name] = {"max_err_over_bound": abs(got - ref) / bound, "rel_err": abs(got - ref) / abs(ref)}
+            ctx["a"].copy_(a0)
+        elif k == "ger":
+            C0 = ctx["C"].clone()
+            fn()
+            ref = oracle.ger(h(ctx["x"]), h(ctx["y"]), h(C0))
+            res[name] = {"bitwise_equal": bool(np.array_equal(h(ctx["C"]).view(np.uint64), ref.view(np.uint64)))}
+            ctx["C"].copy_(C0)
+            del C0, ref
+        elif k in ("gemv_q", "gemv_mx"):
+            c0 = ctx["c"].clone()
+            ctx["c"].zero_()
+            fn()
+            r = rows if k == "gemv_q" else mx_rows
+            got = h(ctx["c"])[:r].astype(np.float64)
+            x = h(ctx["x"])
+            ax = np.abs(x)
+            A32 = h(ctx["A"][:r]).astype(np.float32)
+            if k == "gemv_q":
+                bf = ctx["q"] == sb.SB_BF16
+                codes = h(ctx["Q"][:r]).view(np.uint16 if bf else np.uint8)
+                sc = h(ctx["s"][:r])
+                oq = oracle.Q_BF16 if bf else oracle.Q_E4M3
+                r1 = oracle.gemv_q(codes, sc, x, np.zeros(r), oq)
+                # sum of |s q x| over the decoded codes: the codes with their sign bits cleared
+                mag = oracle.gemv_q(codes & (0x7FFF if bf else 0x7F), sc, ax, np.zeros(r), oq)
+            else:
+                n = A32.shape[1]
+                oq = oracle.Q_MXFP8 if ctx["q"] == sb.SB_MXFP8_E4M3 else oracle.Q_MXFP4
+                codes = h(ctx["Q"][:r])[:, :oracle.mx_row_bytes(oq, n)]
+                S = h(ctx["S"][:r])
+                r1 = oracle.gemv_mx(codes, S, x, np.zeros(r), oq, n)
+                mag = oracle.gemv_mx(codes & (0x7F if oq == oracle.Q_MXFP8 else 0x77), S, ax, np.zeros(r), oq, n)
+            K = A32.shape[1]
+            e = summarise(got, r1, 2 * g(K + 2, 2.0 ** -24) * mag)
+            r2 = oracle.gemv(A32, x, np.zeros(r))
+            e["normwise_vs_unquantised_f64"] = float(np.linalg.norm(got - r2) / np.linalg.norm(r2))
+            e["rows"] = r
+            res[name] = e
+            ctx["c"].copy_(c0)
+        elif k == "dot2":
+            hx, hy = ctx["hx"], ctx["hy"]
+            ex = oracle.dot_exact_f32(hx, hy)
+            ab = oracle.dot_exact_f32(hx, hy, absval=True)
+            out = {}
+            a = torch.zeros(1, dtype=torch.float32, device=ctx["x"].device)
+            sb.sb_dot2_f32(ctx["x"], ctx["y"], a)
+            out["dot2_f32"] = float(h(a)[0])
+            a = torch.zeros(1, dtype=torch.float32, device=ctx["x"].device)
+            sb.sb_dot(ctx["x"], ctx["y"], a)
+            out["plain_f32"] = float(h(a)[0])
+            a = torch.zeros(1, dtype=torch.float64, device=ctx["x"].device)
+            sb.sb_dot(ctx["x"].double(), ctx["y"].double(), a)
+            out["plain_f64"] = float(h(a)[0])
+            u = 2.0 ** -24
+            L = 156   # longest addition path of the 2^27 launch (1024 workgroups, 128 vectors per lane)
+            res[name] = {"cond": 2 * ab / abs(ex), "path_length": L,
+                         "worst_case_rel_bound": (u * abs(ex) + g(L, u) ** 2 * ab) / abs(ex),
+                         **{f"rel_err_{kk}": abs(v - ex) / abs(ex) for kk, v in out.items()}}
+        res[name]["check_s"] = round(time.perf_counter() - t0, 2)
+        log(f"errors {name}: {res[name]}")
+    torch.cuda.synchronize()
+    return res
+
+
 def small_problems(sb, torch, dev):
     """Per-call GPU time of small problems (50 back-to-back calls replayed
     from one graph, median of 5), with the library's default cutoffs."""
@@ -347,6 +484,26 @@ def small_problems(sb, torch, dev):
     x, y, a = uni(16384, torch.float32), uni(16384, torch.float32), uni(1, torch.float32)
     us = per_call_us(lambda: sb.sb_dot2_f32(x, y, a))
     res["dot2_f32_16384"] = {"us": round(us, 2), "GB/s": round(8 * 16384 / us / 1e3, 1)}
+    # 1024^2 binary64 GEMV-N from cold caches: a 1 GiB write (4x the
+    # last-level cache and the L2s together) before every event-timed call
+    m = n = 1024
+    A, x, c = uni((m, n)), uni(n), uni(m)
+    junk = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    ev = HipEvents(torch)
+    t = []
+    for _ in range(21):
+        junk.fill_(0.25)
+        e0 = ev.record()
+        sb.sb_gemv(A, x, c)
+        e1 = ev.record()
+        torch.cuda.synchronize()
+        t.append(1e3 * ev.ms(e0, e1))
+    ev.close()
+    del junk
+    us = sorted(t[1:])[len(t) // 2]
+    nb = 8 * (m * n + n + 2 * m)
+    res["gemv_n_f64_1024x1024_cold"] = {"us": round(us, 2), "GB/s": round(nb / us / 1e3, 1),
+                                        "note": "per call after a 1 GiB write, HIP events, median of 20"}
     log("small problems: " + ", ".join(f"{k} {v['us']} us" for k, v in res.items()))
     return res
 
@@ -388,6 +545,20 @@ def skewed_shapes(sb, torch, dev, reps=10):
     return res
 
 
+def host_info() -> dict:
+    """The host CPU the oracle baseline ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "cpus_online": os.cpu_count(), "cpus_usable": len(os.sched_getaffinity(0))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -425,7 +596,7 @@ def main():
     log(f"ops: {names}; warmup {args.warmup}, steps {args.steps}")
 
     for _ in range(args.warmup):
-        for _, _, _, fn in ops:
+        for _, _, _, fn, *_ in ops:
             fn()
     torch.cuda.synchronize()
     log("warmup done")
@@ -434,12 +605,12 @@ def main():
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step")
 
     per = {}
-    for name, nbytes, flops, _ in ops:
+    for name, nbytes, flops, *_ in ops:
         us = us_per[name]
         per[name] = {"us": round(us, 2), "GB/s": round(nbytes / us / 1e3, 1),
                      "frac_hbm": round(nbytes / us / 1e3 / PEAK_HBM_GBS, 4),
                      "TFLOP/s": round(flops / us / 1e6, 3), "bytes": nbytes}
-    step_bytes = {name: nbytes for name, nbytes, _, _ in ops}
+    step_bytes = {name: nbytes for name, nbytes, *_ in ops}
     value = sum(step_bytes.values()) / (ms_step * 1e-3) / 1e9
     dom = max(per, key=lambda k: per[k]["us"])
     roof = {"bound": "hbm", "kernel": dom, "achieved": per[dom]["GB/s"], "peak": PEAK_HBM_GBS,
@@ -451,10 +622,10 @@ def main():
     extras = {}
     if not args.no_probes:
         probes = build_probes(sb, torch, dev)
-        for _, _, _, fn in probes:
+        for _, _, _, fn, *_ in probes:
             fn()
         p_us, _ = time_ops(torch, probes, max(3, args.steps // 2), args.fenced_events)
-        ceil = {name: round(nb / p_us[name] / 1e3, 1) for name, nb, _, _ in probes}
+        ceil = {name: round(nb / p_us[name] / 1e3, 1) for name, nb, *_ in probes}
         extras["hbm_ceiling_GBs"] = {"read": ceil["probe_read"], "copy": ceil["probe_copy"]}
         for name in per:
             ref = ceil["probe_copy"] if name == "ger_f64" else ceil["probe_read"]
@@ -489,27 +660,37 @@ def main():
         from paper_2108_02025_amd.tuner import TuningTable
         tuning = TuningTable.load()
         serving = {"tuned": tuning is not None}
-        for label, budget, dots in (("budget_4GiB", 4 << 30, 0.0), ("budget_512MiB", 512 << 20, 0.0),
-                                    ("budget_4GiB_with_25pct_dot", 4 << 30, 0.25)):
-            trace = make_trace(4096, rate=1e5, seed=501, dot_fraction=dots, dot_hi=1 << 16)
+        for label, budget, rate, dots in (("budget_4GiB", 4 << 30, 1e5, 0.0),
+                                          ("budget_512MiB", 512 << 20, 1e5, 0.0),
+                                          ("budget_4GiB_with_25pct_dot", 4 << 30, 1e5, 0.25),
+                                          ("budget_4GiB_rate_25k", 4 << 30, 2.5e4, 0.0),
+                                          ("budget_4GiB_rate_400k", 4 << 30, 4e5, 0.0)):
+            trace = make_trace(4096, rate=rate, seed=501, dot_fraction=dots, dot_hi=1 << 16)
             server = Server(budget_bytes=budget, tuning=tuning, sample_every=256)  # results unchecked here
             st = server.run(trace)
-            serving[label] = st.as_dict()
+            serving[label] = {"offered_rate": rate, **st.as_dict()}
             log(f"serving {label}: p50 {st.p50_ms:.2f} ms, p99 {st.p99_ms:.2f} ms, "
-                f"{st.achieved_rate:.0f} req/s, aggregate {st.aggregate_GBs:.1f} GB/s, "
-                f"device-busy {st.device_busy_GBs:.1f} GB/s, {st.batches} batches")
+                f"{st.achieved_rate:.0f} req/s of {rate:.0f}, aggregate {st.aggregate_GBs:.1f} GB/s, "
+                f"device-busy {st.device_busy_GBs:.1f} GB/s, {st.batches} batches, {st.rounds} rounds, "
+                f"longest queue {st.max_queue}")
             del server
-        out["serving"] = {"trace": "4096 requests, Poisson 1e5 req/s, m,n log-uniform [64,8192], "
+        out["serving"] = {"trace": "4096 requests, Poisson arrivals at offered_rate, m,n log-uniform [64,8192], "
                                    "f32 / bf16-A 50:50, uniform[-1,1), c0 = 0 (the _with_25pct_dot run "
                                    "turns a quarter of them into f32 DOTs of length log-uniform [64,65536])",
                           **serving}
+    out["host"] = host_info()
     if not args.no_cpu:
+        log("checking every step operation against the CPU oracle")
+        out["errors"] = error_stats(sb, torch, ops)
         log("timing the CPU oracle baseline")
+        # The GPU machine allots 16 host threads to its one GPU, whatever the
+        # machine has: the all-core figure uses at most that many.
         cores = min(16, len(os.sched_getaffinity(0)))
         res = cpu_baseline(step_bytes, (1, cores) if cores > 1 else (1,))
         out["cpu_baseline"] = res[0]
         if cores > 1:
-            out["cpu_baseline_all_cores"] = res[1]
+            out["cpu_baseline_all_cores"] = {**res[1], "cap": "16 threads: the host share of one GPU on this "
+                                                               "machine class"}
     print(json.dumps(out), flush=True)
 
 

@@ -4,21 +4,23 @@ streaming core).
 Requests c = A x (A m x n, binary32 or bfloat16-A with per-row scales, x and
 c binary32) and DOT requests alpha = x . y (binary32; served as the one-row
 GEMV whose row is x, which is the same sum) arrive on a trace.  The host
-loop:
+loop (Scheduler, driven here by GpuExecutor and the wall clock):
 
-  1. releases each request at its arrival time into a FIFO queue;
-  2. admits the queue head when its operands fit the HBM budget (a first-fit
-     pool carved from one device buffer); admission never skips the head, so
-     no request starves;
+  1. releases each request at its arrival time into a FIFO queue, and drops
+     queued requests that were cancelled or whose admission deadline passed;
+  2. admits the queue head while its operands fit the HBM budget (a
+     first-fit pool carved from one device buffer) and the admission round
+     stays under a byte cap; admission never skips the head, so no request
+     starves;
   3. materialises the operands of every request admitted in a round with
      one launch of the batched generator on a generation stream: A and x
      from SplitMix64 counters (seeded per request), c zeroed, bfloat16 rows
      scaled and encoded in the same kernel;
-  4. whenever fewer than `max_inflight` batches are on the GPU, packs every
-     materialised request into the next batch, writes its table and replays
-     a captured launch of the batched persistent kernel (one HIP graph per
-     table, tables double-buffered so a new batch is written while the
-     previous one runs);
+  4. whenever one of `max_inflight` tables is free, packs the admitted
+     requests into the next batch (at most one generation round still
+     running, under a byte cap), writes its table and replays a captured
+     launch of the batched persistent kernel (one HIP graph per table) on
+     the execution stream, behind that round's generation event;
   5. polls the batches' completion events, stamps completions and frees
      their memory, which lets queued requests in.
 
@@ -57,6 +59,7 @@ class Request:
     n: int
     seed: int
     op: str = "gemv"   # "dot": alpha = x . y, the one-row binary32 GEMV (m = 1)
+    deadline: float = math.inf   # trace time by which it must be admitted, else it expires unserved
     t_admit: float = math.nan
     t_launch: float = math.nan
     t_done: float = math.nan
@@ -214,6 +217,288 @@ GEN_DESC = np.dtype([("dtype", "<i4"), ("reserved", "<i4"), ("m", "<i8"), ("n", 
 assert GEMV_DESC.itemsize == 72 and GEN_DESC.itemsize == 72
 
 
+# ------------------------------------------------------------------ policy --
+
+class Scheduler:
+    """The serving loop's host policy, independent of the device.  It sees
+    the device through an executor (generate / launch / finished) and time
+    through a clock (now / idle), so the same code drives the GPU and a
+    simulated device in tests.
+
+    Per turn of the loop:
+      1. requests whose arrival time has passed join a FIFO queue; queued
+         requests whose deadline has passed, or that were cancelled, leave
+         it unserved;
+      2. admission: the queue head is admitted while its device bytes fit
+         the pool and the round's byte cap; a request larger than the whole
+         budget is rejected; the head is never skipped, so no request
+         starves behind smaller ones.  The round's operands are generated by
+         one executor call;
+      3. batching: while a table is free, the admitted requests go into the
+         next batch in admission order, up to max_batch requests and
+         max_batch_bytes.  A batch takes the requests whose generation has
+         finished and, after them, those of the next generation round still
+         running (its launch waits for that round on the device), never a
+         later round: a batch never waits for generation admitted after its
+         requests, so a backlog drains with generation and execution
+         overlapped instead of each batch waiting for the newest round;
+      4. finished batches free their requests' memory and their table.
+    Requests are completed in batch order; each request's result depends
+    only on the request.
+    """
+
+    def __init__(self, dev_bytes: np.ndarray, budget: int, max_batch: int = 512, max_inflight: int = 2,
+                 max_round_bytes: int = 256 << 20, max_batch_bytes: int = 512 << 20):
+        self.dev_bytes = np.asarray(dev_bytes, dtype=np.int64)
+        N = len(self.dev_bytes)
+        self.budget = int(budget)
+        self.max_batch = max_batch
+        self.max_round_bytes = int(max_round_bytes)
+        self.max_batch_bytes = int(max_batch_bytes)
+        self.pool = Pool(self.budget)
+        self.queue: collections.deque[int] = collections.deque()
+        self.ready: collections.deque[int] = collections.deque()   # admitted, not yet in a batch
+        self.rounds: collections.deque = collections.deque()       # (round id, token) still generating
+        self.round_token: dict[int, object] = {}
+        self.round_of = np.full(N, -1, dtype=np.int64)
+        self.gen_done = -1                                          # every round <= this has finished
+        self.n_rounds = 0
+        self.inflight: collections.deque = collections.deque()     # (token, ids, table)
+        self.free_tables = collections.deque(range(max_inflight))
+        self.offset = np.full(N, -1, dtype=np.int64)
+        self.t_admit = np.full(N, np.nan)
+        self.t_launch = np.full(N, np.nan)
+        self.t_done = np.full(N, np.nan)
+        self.deadline = np.full(N, np.inf)
+        self.cancelled = np.zeros(N, dtype=bool)
+        self.status = np.zeros(N, dtype=np.int8)   # 0 pending, 1 done, 2 rejected, 3 expired or cancelled
+        self.finished = 0
+        self.batches = 0
+        self.max_queue = 0
+        self._cancel_pending = False
+        self._deadlines = False
+
+    # -- requests leaving the queue unserved --------------------------------
+    def cancel(self, i: int) -> bool:
+        """Cancel request i if it has not been admitted yet (it then leaves
+        the queue unserved); returns whether it was."""
+        if self.status[i] != 0 or self.offset[i] >= 0:
+            return False
+        self.cancelled[i] = True
+        self._cancel_pending = True
+        return True
+
+    def _drop(self, i: int, status: int) -> None:
+        self.status[i] = status
+        self.t_done[i] = np.inf
+        self.finished += 1
+
+    def _expire(self, now: float) -> bool:
+        if not self.queue or not (self._cancel_pending or self._deadlines):
+            return False
+        self._cancel_pending = False
+        q = self.queue
+        gone = [i for i in q if self.cancelled[i] or self.deadline[i] < now]
+        if not gone:
+            return False
+        keep = set(gone)
+        self.queue = collections.deque(i for i in q if i not in keep)
+        for i in gone:
+            self._drop(i, 3)
+        return True
+
+    # -- admission ------------------------------------------------------------
+    def admit(self, now: float) -> list[int]:
+        admitted, nbytes = [], 0
+        while self.queue:
+            i = self.queue[0]
+            b = int(self.dev_bytes[i])
+            if b > self.budget:
+                self.queue.popleft()
+                self._drop(i, 2)
+                continue
+            if admitted and nbytes + b > self.max_round_bytes:
+                break
+            off = self.pool.alloc(b)
+            if off is None:
+                break
+            self.queue.popleft()
+            self.offset[i] = off
+            admitted.append(i)
+            nbytes += b
+        if admitted:
+            self.t_admit[admitted] = now
+        return admitted
+
+    # -- batching -------------------------------------------------------------
+    def next_batch(self) -> tuple[list[int], object]:
+        """Ids of the next batch and the generation token its launch must wait
+        for (None when every request in it has been generated)."""
+        ids, nbytes, wait_round = [], 0, None
+        for i in self.ready:
+            r = int(self.round_of[i])
+            if r > self.gen_done:
+                if wait_round is None:
+                    wait_round = r
+                elif r != wait_round:
+                    break
+            b = int(self.dev_bytes[i])
+            if ids and (len(ids) >= self.max_batch or nbytes + b > self.max_batch_bytes):
+                break
+            ids.append(i)
+            nbytes += b
+        for _ in ids:
+            self.ready.popleft()
+        return ids, (self.round_token[wait_round] if wait_round is not None else None)
+
+    # -- the loop -------------------------------------------------------------
+    def serve(self, arrival: np.ndarray, executor, clock) -> None:
+        N = len(arrival)
+        nxt = 0
+        self._deadlines = bool(np.isfinite(self.deadline).any())
+        while self.finished < N:
+            busy = False
+            now = clock.now()
+            upto = int(np.searchsorted(arrival, now, side="right"))
+            if upto > nxt:
+                self.queue.extend(range(nxt, upto))
+                nxt = upto
+                self.max_queue = max(self.max_queue, len(self.queue))
+            busy |= self._expire(now)
+            ids = self.admit(now)
+            if ids:
+                busy = True
+                tok = executor.generate(np.array(ids), self.offset)
+                self.round_of[ids] = self.n_rounds
+                self.rounds.append((self.n_rounds, tok))
+                self.round_token[self.n_rounds] = tok
+                self.ready.extend(ids)
+                self.n_rounds += 1
+            while self.rounds and executor.finished(self.rounds[0][1]):
+                self.gen_done = self.rounds.popleft()[0]
+                del self.round_token[self.gen_done]
+            while self.free_tables and self.ready:
+                batch, wait = self.next_batch()
+                if not batch:
+                    break
+                busy = True
+                k = self.free_tables.popleft()
+                b = np.array(batch)
+                tok = executor.launch(b, self.offset, k, wait)
+                self.t_launch[b] = clock.now()
+                self.inflight.append((tok, b, k))
+                self.batches += 1
+            while self.inflight and executor.finished(self.inflight[0][0]):
+                tok, b, k = self.inflight.popleft()
+                self.t_done[b] = clock.now()
+                self.status[b] = 1
+                for i in b:
+                    self.pool.free(int(self.offset[i]), int(self.dev_bytes[i]))
+                self.finished += len(b)
+                self.free_tables.append(k)
+                busy = True
+            if not busy:
+                clock.idle(arrival[nxt] if nxt < N else np.inf, executor)
+
+
+class WallClock:
+    """Seconds since the first call; idle() spins (the loop polls)."""
+
+    def __init__(self):
+        self.t0 = None
+
+    def now(self) -> float:
+        if self.t0 is None:
+            self.t0 = time.perf_counter()
+        return time.perf_counter() - self.t0
+
+    def idle(self, next_arrival: float, executor) -> None:
+        return None
+
+
+# ----------------------------------------------------------------- device --
+
+class GpuExecutor:
+    """The device side of the serving loop: operand generation on the
+    generation stream, batched launches (captured graphs over
+    double-buffered tables) on the execution stream, completion through
+    events."""
+
+    def __init__(self, server: "Server", desc_all: np.ndarray, gen_all: np.ndarray, rel: np.ndarray,
+                 has_s: np.ndarray, result_at: np.ndarray, c_rel: np.ndarray, m: np.ndarray):
+        self.s = server
+        self.desc_all, self.gen_all, self.rel, self.has_s = desc_all, gen_all, rel, has_s
+        self.result_at, self.c_rel, self.m = result_at, c_rel, m
+        self.busy_events = []
+
+    def _addresses(self, table, ids, offset):
+        base = (self.s.base + offset[ids]).astype(np.uint64)
+        table["A"] = base
+        table["scales"] = (base + self.rel[ids, 1]) * self.has_s[ids]
+        table["x"] = base + self.rel[ids, 2]
+        table["c"] = base + self.rel[ids, 3]
+        return table
+
+    def generate(self, ids, offset):
+        self.s._generate(self._addresses(self.gen_all[ids], ids, offset))
+        ev = torch.cuda.Event()
+        ev.record(self.s.gen_stream)
+        return ev
+
+    def launch(self, ids, offset, k, wait):
+        s = self.s
+        d = self._addresses(self.desc_all[ids], ids, offset)
+        with torch.cuda.stream(s.exec_stream):
+            if wait is not None:
+                s.exec_stream.wait_event(wait)
+            start = torch.cuda.Event(enable_timing=True)
+            end = torch.cuda.Event(enable_timing=True)
+            s.tables[k].encode_descs(d.ctypes.data, len(ids))
+            start.record()
+            if s.use_graphs:
+                s._graph_for(k).replay()
+            else:
+                s.tables[k].run()
+            end.record()
+            for i in ids[self.result_at[ids] >= 0]:
+                c_off = int(offset[i] + self.c_rel[i])
+                s.results[self.result_at[i]:self.result_at[i] + self.m[i]].copy_(
+                    s.buf[c_off:c_off + 4 * int(self.m[i])].view(torch.float32))
+            fin = torch.cuda.Event()
+            fin.record()
+        self.busy_events.append((start, end))
+        return fin
+
+    def finished(self, ev) -> bool:
+        return ev.query()
+
+
+@dataclasses.dataclass
+class Stats:
+    n: int
+    rejected: int
+    span_s: float
+    achieved_rate: float
+    p50_ms: float
+    p99_ms: float
+    p999_ms: float
+    queue_p50_ms: float
+    materialise_p50_ms: float
+    execute_p50_ms: float
+    aggregate_GBs: float
+    device_busy_GBs: float
+    batches: int
+    mean_batch: float
+    total_bytes: int
+    dot_requests: int = 0
+    expired: int = 0
+    rounds: int = 0
+    max_queue: int = 0
+
+    def as_dict(self) -> dict:
+        return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in dataclasses.asdict(self).items()}
+
+
 _STREAMS: dict[int, tuple[torch.cuda.Stream, torch.cuda.Stream]] = {}
 
 
@@ -230,12 +515,16 @@ def serving_streams(device: torch.device) -> tuple[torch.cuda.Stream, torch.cuda
 
 
 class Server:
-    """See the module docstring.  `tuning` maps (kind, m, n) to a
-    configuration dict for the batched kernel (or None for automatic)."""
+    """Continuous-batching GEMV server on one GPU (see the module docstring
+    and Scheduler).  `tuning` maps (kind, m, n) to a configuration dict for
+    the batched kernel (or None for automatic).  `executor_class` is the
+    device side of the loop (GpuExecutor)."""
+
+    executor_class = GpuExecutor
 
     def __init__(self, budget_bytes: int = 4 << 30, max_batch: int = 512, max_inflight: int = 2,
                  use_graphs: bool = True, tuning=None, sample_every: int = 16, table_bytes: int = 96 << 20,
-                 device=None):
+                 device=None, max_round_bytes: int = 256 << 20, max_batch_bytes: int = 512 << 20):
         from . import Handle
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
@@ -245,6 +534,8 @@ class Server:
         self.stage = torch.empty(8192 * 8192, dtype=torch.float32, device=self.device)
         self.max_batch = max_batch
         self.max_inflight = max_inflight
+        self.max_round_bytes = max_round_bytes
+        self.max_batch_bytes = max_batch_bytes
         self.use_graphs = use_graphs
         self.tuning = tuning
         self.sample_every = sample_every
@@ -254,6 +545,7 @@ class Server:
             self.gen_handle.prepare(1 << 16)  # bound to the generation stream from here on
         self.tables = [BatchTable(table_bytes, self.device) for _ in range(max_inflight)]
         self.graphs: list[torch.cuda.CUDAGraph | None] = [None] * max_inflight
+        self.scheduler: Scheduler | None = None
 
     # -- graph of one table's launch ------------------------------------
     def _graph_for(self, k: int) -> torch.cuda.CUDAGraph:
@@ -316,13 +608,19 @@ class Server:
     def run(self, trace: list[Request], warm_requests: int = 512) -> Stats:
         """Serve `trace` and return its statistics.  Before the clock starts,
         warm_up() runs every kernel once and a short untimed trace of
-        `warm_requests` requests (other seeds) goes through the same loop:
-        the first turns of a fresh loop pay one-off costs (lazily loaded
-        runtime kernels, first launches of the graphs, workspace growth)
-        that otherwise start the measured trace with a backlog."""
+        `warm_requests` requests (other seeds, the measured trace's shape
+        range, the same rate) goes through the same loop: the first turns of
+        a fresh loop pay one-off costs (lazily loaded runtime kernels, first
+        launches of the graphs, workspace growth, the first touch of the
+        pool's pages) that otherwise start the measured trace with a
+        backlog."""
         self.warm_up()
-        if warm_requests > 0:
-            warm = make_trace(warm_requests, rate=1e5, seed=0x5EED, hi=4096, dot_fraction=0.25)
+        if warm_requests > 0 and trace:
+            lo = min(min(r.m, r.n) for r in trace if r.op == "gemv") if any(r.op == "gemv" for r in trace) else 64
+            hi = max(max(r.m, r.n) for r in trace if r.op == "gemv") if any(r.op == "gemv" for r in trace) else 64
+            span = trace[-1].arrival - trace[0].arrival
+            rate = (len(trace) - 1) / span if span > 0 else 1e5
+            warm = make_trace(warm_requests, rate=rate, seed=0x5EED, lo=lo, hi=hi, dot_fraction=0.25)
             self._serve(warm, warm=True)
         return self._serve(trace)
 
@@ -359,123 +657,26 @@ class Server:
         desc_all["group"], desc_all["rows_per_tile"], desc_all["split"] = cfg[:, 0], cfg[:, 1], cfg[:, 2]
         desc_all["m"], desc_all["n"], desc_all["lda"] = m, n, n
 
-        def addresses(table, ids):
-            base = (self.base + offset[ids]).astype(np.uint64)
-            table["A"] = base
-            table["scales"] = (base + rel[ids, 1]) * has_s[ids]
-            table["x"] = base + rel[ids, 2]
-            table["c"] = base + rel[ids, 3]
-            return table
-
-        offset = np.full(N, -1, dtype=np.int64)
-        t_admit = np.full(N, np.nan)
-        t_launch = np.full(N, np.nan)
-        t_done = np.full(N, np.nan)
         sampled = np.flatnonzero(np.arange(N) % self.sample_every == 0)
         result_at = np.full(N, -1, dtype=np.int64)
         result_at[sampled] = np.concatenate([[0], np.cumsum(m[sampled])[:-1]]) if len(sampled) else []
         self.results = torch.empty(max(1, int(m[sampled].sum())), dtype=torch.float32, device=self.device)
 
-        pool = Pool(self.budget)
-        queue: collections.deque[int] = collections.deque()
-        ready: list[int] = []
-        inflight: collections.deque = collections.deque()
-        free_tables = collections.deque(range(len(self.tables)))
-        gen_event = None
-        done = rejected = 0
-        nxt = 0
-        batch_id = 0
-        busy_events = []
+        sched = Scheduler(dev_bytes, self.budget, self.max_batch, self.max_inflight, self.max_round_bytes,
+                          self.max_batch_bytes)
+        sched.deadline[:] = [r.deadline for r in trace]
+        ex = self.executor_class(self, desc_all, gen_all, rel, has_s, result_at, rel[:, 3].astype(np.int64), m)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        while done + rejected < N:
-            now = time.perf_counter() - t0
-            upto = int(np.searchsorted(arrival, now, side="right"))
-            if upto > nxt:
-                queue.extend(range(nxt, upto))
-                nxt = upto
-            # admission: FIFO, by device memory
-            admitted = []
-            while queue:
-                i = queue[0]
-                if dev_bytes[i] > self.budget:
-                    queue.popleft()
-                    rejected += 1
-                    t_done[i] = np.inf
-                    continue
-                off = pool.alloc(int(dev_bytes[i]))
-                if off is None:
-                    break
-                queue.popleft()
-                offset[i] = off
-                admitted.append(i)
-            if admitted:
-                ids = np.array(admitted)
-                t_admit[ids] = time.perf_counter() - t0
-                self._generate(addresses(gen_all[ids], ids))
-                gen_event = torch.cuda.Event()
-                gen_event.record(self.gen_stream)
-                ready.extend(admitted)
-            # continuous batching: launch whatever is ready when a table is free
-            if ready and free_tables:
-                k = free_tables.popleft()
-                ids = np.array(ready[: self.max_batch])
-                ready = ready[self.max_batch:]
-                d = addresses(desc_all[ids], ids)
-                with torch.cuda.stream(self.exec_stream):
-                    self.exec_stream.wait_event(gen_event)
-                    start = torch.cuda.Event(enable_timing=True)
-                    end = torch.cuda.Event(enable_timing=True)
-                    self.tables[k].encode_descs(d.ctypes.data, len(ids))
-                    start.record()
-                    if self.use_graphs:
-                        self._graph_for(k).replay()
-                    else:
-                        self.tables[k].run()
-                    end.record()
-                    for i in ids[result_at[ids] >= 0]:
-                        c_off = int(offset[i] + a_bytes[i] + s_bytes[i] + x_bytes[i])
-                        self.results[result_at[i]:result_at[i] + m[i]].copy_(
-                            self.buf[c_off:c_off + 4 * int(m[i])].view(torch.float32))
-                    fin = torch.cuda.Event()
-                    fin.record()
-                t_launch[ids] = time.perf_counter() - t0
-                inflight.append((fin, ids, k))
-                busy_events.append((start, end))
-                batch_id += 1
-            # completions
-            while inflight and inflight[0][0].query():
-                fin, ids, k = inflight.popleft()
-                t_done[ids] = time.perf_counter() - t0
-                for i in ids:
-                    pool.free(int(offset[i]), int(dev_bytes[i]))
-                done += len(ids)
-                free_tables.append(k)
+        sched.serve(arrival, ex, WallClock())
         torch.cuda.synchronize()
         if warm:
             return None
+        self.scheduler = sched
         for i, r in enumerate(trace):
-            r.t_admit, r.t_launch, r.t_done = float(t_admit[i]), float(t_launch[i]), float(t_done[i])
-            r.offset, r.result_at = int(offset[i]), int(result_at[i])
-        return self._stats(trace, busy_events, batch_id, rejected)
+            r.t_admit, r.t_launch, r.t_done = float(sched.t_admit[i]), float(sched.t_launch[i]), float(sched.t_done[i])
+            r.offset, r.result_at = int(sched.offset[i]), int(result_at[i])
+        return stats_of(trace, sched, ex.busy_events)
 
-    def _stats(self, trace, busy_events, nbatches, rejected) -> Stats:
-        ok = [r for r in trace if math.isfinite(r.t_done)]
-        lat = np.array([r.t_done - r.arrival for r in ok])
-        q = np.array([r.t_admit - r.arrival for r in ok])
-        mat = np.array([r.t_launch - r.t_admit for r in ok])
-        ex = np.array([r.t_done - r.t_launch for r in ok])
-        total = sum(r.algorithmic_bytes for r in ok)
-        span = max(r.t_done for r in ok) - min(r.arrival for r in ok)
-        busy = sum(a.elapsed_time(b) for a, b in busy_events) * 1e-3
-        pct = lambda a, p: float(np.percentile(a, p)) * 1e3  # noqa: E731
-        return Stats(
-            n=len(ok), rejected=rejected, span_s=span, achieved_rate=len(ok) / span,
-            p50_ms=pct(lat, 50), p99_ms=pct(lat, 99), p999_ms=pct(lat, 99.9),
-            queue_p50_ms=pct(q, 50), materialise_p50_ms=pct(mat, 50), execute_p50_ms=pct(ex, 50),
-            aggregate_GBs=total / span / 1e9, device_busy_GBs=total / busy / 1e9 if busy > 0 else math.nan,
-            batches=nbatches, mean_batch=len(ok) / max(nbatches, 1), total_bytes=total,
-            dot_requests=sum(r.op == "dot" for r in ok))
 
     def result_of(self, r: Request) -> torch.Tensor:
         return self.results[r.result_at:r.result_at + r.m]
@@ -489,3 +690,28 @@ class Server:
         sb_gemv_batched([P])
         torch.cuda.synchronize()
         return P.c.clone()
+
+
+def stats_of(trace: list[Request], sched: Scheduler, busy_events=()) -> Stats:
+    """Latency and throughput of a served trace (completion minus scheduled
+    arrival; aggregate bytes over last completion minus first arrival)."""
+    ok = [r for r in trace if math.isfinite(r.t_done)]
+    lat = np.array([r.t_done - r.arrival for r in ok])
+    q = np.array([r.t_admit - r.arrival for r in ok])
+    mat = np.array([r.t_launch - r.t_admit for r in ok])
+    ex = np.array([r.t_done - r.t_launch for r in ok])
+    total = sum(r.algorithmic_bytes for r in ok)
+    span = max(r.t_done for r in ok) - min(r.arrival for r in ok) if ok else math.nan
+    busy = sum(a.elapsed_time(b) for a, b in busy_events) * 1e-3
+    pct = (lambda a, p: float(np.percentile(a, p)) * 1e3 if len(a) else math.nan)  # noqa: E731
+    return Stats(
+        n=len(ok), rejected=int((sched.status == 2).sum()), span_s=span,
+        achieved_rate=len(ok) / span if ok and span > 0 else math.nan,
+        p50_ms=pct(lat, 50), p99_ms=pct(lat, 99), p999_ms=pct(lat, 99.9),
+        queue_p50_ms=pct(q, 50), materialise_p50_ms=pct(mat, 50), execute_p50_ms=pct(ex, 50),
+        aggregate_GBs=total / span / 1e9 if ok and span > 0 else math.nan,
+        device_busy_GBs=total / busy / 1e9 if busy > 0 else math.nan,
+        batches=sched.batches, mean_batch=len(ok) / max(sched.batches, 1), total_bytes=total,
+        dot_requests=sum(r.op == "dot" for r in ok), expired=int((sched.status == 3).sum()),
+        rounds=sched.n_rounds, max_queue=sched.max_queue)
+

@@ -215,3 +215,54 @@ def test_tuner_quick_and_tuned_serving(sb, tmp_path):
     st = server.run(trace)
     assert st.n == 200
     assert check_sampled(sb, server, trace) == 50
+
+
+def test_nan_poisoned_request_leaves_every_other_result_unchanged(sb):
+    """A request whose x holds a NaN (written after its operands are
+    generated, on the generation stream) yields NaN everywhere and leaves
+    the bits of every other request of the trace, batched with it,
+    unchanged: the batched kernel shares no arithmetic between problems."""
+    from paper_2108_02025_amd.serve import GpuExecutor, Server, make_trace
+
+    trace0 = make_trace(160, rate=4e4, seed=31, lo=64, hi=1024)
+    victim = next(r.id for r in trace0[40:] if r.kind == "f32" and r.m >= 8)
+
+    class PoisonExecutor(GpuExecutor):
+        def generate(self, ids, offset):
+            ev = super().generate(ids, offset)
+            if victim in ids and not getattr(self, "poisoned", False):
+                x_off = int(offset[victim] + self.rel[victim, 2])
+                with torch.cuda.stream(self.s.gen_stream):
+                    self.s.buf[x_off:x_off + 4].view(torch.float32).fill_(float("nan"))
+                ev = torch.cuda.Event()
+                ev.record(self.s.gen_stream)
+                self.poisoned = True
+            return ev
+
+    class PoisonServer(Server):
+        executor_class = PoisonExecutor
+
+    def trace_with_burst():
+        """The same trace each time, with the victim arriving together with
+        its six neighbours so that they share an admission round and a batch."""
+        tr = make_trace(160, rate=4e4, seed=31, lo=64, hi=1024)
+        for r in tr[victim - 3:victim + 4]:
+            r.arrival = tr[victim - 3].arrival
+        return tr
+
+    outs = []
+    for cls in (Server, PoisonServer):
+        trace = trace_with_burst()
+        server = cls(budget_bytes=256 << 20, sample_every=1)
+        st = server.run(trace, warm_requests=0)
+        assert st.n == 160
+        outs.append((host(server.results).copy(), trace))
+    (clean, t0), (poisoned, t1) = outs
+    v = t1[victim]
+    sl = slice(v.result_at, v.result_at + v.m)
+    assert np.isnan(poisoned[sl]).all() and not np.isnan(clean[sl]).any()
+    rest = np.ones(clean.size, bool)
+    rest[sl] = False
+    assert np.array_equal(clean[rest].view(np.uint32), poisoned[rest].view(np.uint32))
+    # the victim shared its batch with other requests
+    assert sum(1 for r in t1 if r.t_launch == v.t_launch) > 1
