@@ -46,7 +46,7 @@ TRAFFIC = os.path.join(HERE, "profiles", "hbm_traffic.json")
 KERNEL_SOURCES = {
     "gemv_n_f64": ["gemv.hip", "sb_rowdot.hpp", "sb_device.hpp"],
     "gemv_t_f64": ["gemv.hip", "sb_device.hpp"],
-    "gemv2_f64": ["gemv2.hip", "sb_device.hpp"],
+    "gemv2_f64": ["gemv2.hip", "sb_wave.hpp", "sb_device.hpp"],
     "dot_f64": ["dot.hip", "sb_device.hpp"],
     "ger_f64": ["ger.hip", "sb_device.hpp"],
     "gemv_q_bf16": ["quant.hip", "sb_rowdot.hpp", "sb_quant.hpp", "sb_device.hpp"],
@@ -173,8 +173,10 @@ def build_probes(sb, torch, dev):
     src.fill_(1.0)
     half = src[: 1 << 28]
     dst = torch.empty(1 << 28, dtype=torch.float64, device=dev)   # 2 GiB
+    upd = src[: 1 << 28].view(16384, 16384)                       # GER's matrix shape, 2 GiB
     return [("probe_read", 8 << 29, 0, lambda: sb.sb_stream_read(src)),
-            ("probe_copy", 2 * (8 << 28), 0, lambda: sb.sb_stream_copy(half, dst))]
+            ("probe_copy", 2 * (8 << 28), 0, lambda: sb.sb_stream_copy(half, dst)),
+            ("probe_update", 2 * (8 << 28), 0, lambda: sb.sb_stream_update(upd))]
 
 
 class HipEvents:
@@ -626,11 +628,15 @@ def main():
             fn()
         p_us, _ = time_ops(torch, probes, max(3, args.steps // 2), args.fenced_events)
         ceil = {name: round(nb / p_us[name] / 1e3, 1) for name, nb, *_ in probes}
-        extras["hbm_ceiling_GBs"] = {"read": ceil["probe_read"], "copy": ceil["probe_copy"]}
+        extras["hbm_ceiling_GBs"] = {"read": ceil["probe_read"], "copy": ceil["probe_copy"],
+                                     "update_ger_pattern": ceil["probe_update"]}
         for name in per:
-            ref = ceil["probe_copy"] if name == "ger_f64" else ceil["probe_read"]
+            # GER against the read-and-rewrite probe with its own access
+            # pattern; everything else against the streaming read
+            ref = ceil["probe_update"] if name == "ger_f64" else ceil["probe_read"]
             per[name]["frac_ceiling"] = round(per[name]["GB/s"] / ref, 4)
-        log(f"probes: read {ceil['probe_read']} GB/s, copy {ceil['probe_copy']} GB/s")
+        log(f"probes: read {ceil['probe_read']} GB/s, copy {ceil['probe_copy']} GB/s, "
+            f"update (GER pattern) {ceil['probe_update']} GB/s")
     if all(k in per for k in ("gemv_n_f64", "gemv_t_f64", "gemv2_f64")):
         extras["gemv2_speedup_over_two_calls"] = round(
             (per["gemv_n_f64"]["us"] + per["gemv_t_f64"]["us"]) / per["gemv2_f64"]["us"], 3)

@@ -420,6 +420,18 @@ sb_status sb_generate_batched(sb_handle* handle, const sb_gen_desc* descs, int32
 sb_status sb_stream_read(sb_handle* handle, const void* src, size_t bytes);
 sb_status sb_stream_copy(sb_handle* handle, const void* src, void* dst, size_t bytes);
 
+/*
+ * Read-and-rewrite probe with GER's access pattern: the rows x cols
+ * row-major binary64 matrix C (leading dimension ldc >= cols, 8-byte
+ * aligned) is read and written back unchanged, in place, by the GER kernel
+ * with its arithmetic replaced by an XOR with a zero mask, in GER's launch
+ * shape (section 4.2, Algorithm 2's row-by-row update).  It moves exactly the
+ * bytes of C that GER moves, so its rate is the ceiling of GER's read +
+ * write stream.  Needs no workspace.  SB_EINVAL for a NULL or misaligned C
+ * or a bad size; nothing is launched for an empty matrix.
+ */
+sb_status sb_stream_update(sb_handle* handle, void* C, int64_t rows, int64_t cols, int64_t ldc);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,7 @@ __all__ = [
     "StreamBlasError", "load", "lib_path", "Handle", "handle_for",
     "sb_version", "sb_status_string", "sb_workspace_bytes",
     "sb_gemv", "sb_gemv_noalloc", "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32",
-    "sb_stream_read", "sb_stream_copy", "sb_gemv_desc", "GemvProblem", "make_descs", "sb_gemv_batched",
+    "sb_stream_read", "sb_stream_copy", "sb_stream_update", "sb_gemv_desc", "GemvProblem", "make_descs", "sb_gemv_batched",
     "sb_gemv_batched_resolve", "sb_gemv_batched_table_bytes", "BatchTable", "sb_fill_uniform",
     "SB_CUTOFF_DOT_SMALL_BYTES", "SB_CUTOFF_GEMV_T_SMALL_SPLITS", "sb_set_cutoff", "sb_get_cutoff",
     "SB_MXFP8_E4M3", "SB_MXFP4_E2M1", "SB_KIND_GEMV_MX", "mx_buffers", "sb_quantize_mx", "sb_gemv_mx",
@@ -109,8 +109,9 @@ def load():
     L.sb_generate_batched.argtypes = [P, P, I32]
     L.sb_stream_read.argtypes = [P, P, SZ]
     L.sb_stream_copy.argtypes = [P, P, P, SZ]
+    L.sb_stream_update.argtypes = [P, P, I64, I64, I64]
     for f in ("sb_fill_uniform", "sb_generate_batched", "sb_gemv_batched_resolve", "sb_gemv_batched_encode", "sb_gemv_batched_run", "sb_gemv_batched",
-              "sb_stream_read", "sb_stream_copy", "sb_handle_create", "sb_handle_destroy", "sb_set_stream", "sb_set_workspace", "sb_set_cutoff", "sb_get_cutoff", "sb_gemv", "sb_gemv_noalloc", "sb_gemv2",
+              "sb_stream_read", "sb_stream_copy", "sb_stream_update", "sb_handle_create", "sb_handle_destroy", "sb_set_stream", "sb_set_workspace", "sb_set_cutoff", "sb_get_cutoff", "sb_gemv", "sb_gemv_noalloc", "sb_gemv2",
               "sb_dot", "sb_ger", "sb_quantize_rows", "sb_gemv_q", "sb_dot2_f32", "sb_quantize_mx", "sb_gemv_mx",
               "sb_plan_create", "sb_plan_run", "sb_plan_destroy"):
         getattr(L, f).restype = I32
@@ -461,6 +462,19 @@ def sb_stream_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
     h = handle_for(src)
     h.prepare(0)
     h.check(load().sb_stream_copy(h.h, _ptr(src), _ptr(dst), nbytes))
+
+
+def sb_stream_update(C: torch.Tensor) -> None:
+    """Measurement probe: read and rewrite a row-major float64 matrix in
+    place with GER's access pattern (its value does not change)."""
+    if not C.is_cuda or C.dtype != torch.float64 or C.dim() != 2:
+        raise ValueError("C must be a 2-D float64 device tensor")
+    layout, ld = _matrix_layout(C)
+    if layout != SB_ROW_MAJOR:
+        raise ValueError("C must be row-major")
+    h = handle_for(C)
+    h.prepare(0)
+    h.check(load().sb_stream_update(h.h, _ptr(C), C.shape[0], C.shape[1], ld))
 
 
 class GemvProblem:

@@ -624,4 +624,20 @@ sb_status sb_stream_copy(sb_handle* handle, const void* src, void* dst, size_t b
     SB_GUARD_END
 }
 
+sb_status sb_stream_update(sb_handle* handle, void* C, int64_t rows, int64_t cols, int64_t ldc)
+{
+    if (!handle) return fail(nullptr, SB_EINVAL, "sb_stream_update: NULL handle");
+    if (rows < 0 || cols < 0 || ldc < (cols > 1 ? cols : 1))
+        return fail(handle, SB_EINVAL, "sb_stream_update: bad size or leading dimension");
+    const int64_t el = span_elems(rows, cols, ldc);
+    int64_t bytes;
+    if (el < 0 || !mul_ok(el, 8, &bytes) || bytes > kMaxBytes)
+        return fail(handle, SB_EINVAL, "sb_stream_update: extent overflows");
+    if (rows == 0 || cols == 0) return SB_OK;
+    if (!C || misaligned(C, 8)) return fail(handle, SB_EINVAL, "sb_stream_update: NULL or misaligned matrix");
+    SB_GUARD_BEGIN
+    return sb::run_stream_update(handle, C, rows, cols, ldc);
+    SB_GUARD_END
+}
+
 }  // extern "C"

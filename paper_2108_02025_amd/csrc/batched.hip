@@ -7,9 +7,11 @@
 // columns (KC covering all of n unless the problem is split along its
 // columns), and runs of consecutive tiles of one problem form work items.
 // The host deals the items to the workgroups of a persistent grid, largest
-// first, each to the workgroup with the least work so far (the
-// longest-processing-time-first rule), so the workgroups finish together
-// whatever the mix of shapes, without any counter traffic on the device.
+// first, in rounds of one item per workgroup whose direction alternates
+// (round 0 gives workgroup b the (b+1)-th largest item, round 1 the
+// (2*grid-b)-th, and so on): no workgroup ends more than one item's cost
+// above another, whatever the mix of shapes, and the device needs no
+// counter traffic to share the work.
 // A tile stages its x chunk in LDS (kept if the workgroup's next tile uses
 // the same chunk) and runs the same per-row dot products as the single-call
 // kernels.
@@ -48,7 +50,7 @@ constexpr int64_t kBatLds = 32 * 1024;     // x chunk bytes per tile
 #define SB_BAT_TILE_BYTES (256 * 1024)
 #endif
 #ifndef SB_BAT_ITEMS_PER_WG
-#define SB_BAT_ITEMS_PER_WG 4
+#define SB_BAT_ITEMS_PER_WG 8
 #endif
 #ifndef SB_BAT_MAX_PASSES
 #define SB_BAT_MAX_PASSES 8
@@ -77,7 +79,13 @@ constexpr int64_t kBatTileBytes = SB_BAT_TILE_BYTES;  // largest automatic tile 
 #endif
 constexpr int kBatUnrollPlain = SB_BAT_UNROLL_PLAIN, kBatUnrollBf16 = SB_BAT_UNROLL_BF16,
               kBatUnrollE4m3 = SB_BAT_UNROLL_E4M3;
-constexpr int kBatGrid = SB_BAT_GRID;  // default persistent grid: 4 workgroups per CU
+// The items are dealt to 1024 workgroups, two rounds of the two that fit a
+// compute unit: in the serving loop the operand generator runs beside the
+// batched kernel, and finer lists let the batched workgroups fill whatever
+// the generator leaves free (serving at 4e5 requests/s: 1.26e5 served per
+// second against 1.10e5 with 512 lists); alone, 512 and 1024 lists run
+// within noise of each other.
+constexpr int kBatGrid = SB_BAT_GRID;
 
 struct BatHeader {
     int64_t count;
@@ -117,10 +125,12 @@ static_assert(sizeof(BatProblem) == 144, "problem record layout");
 static_assert(sizeof(BatItem) == 16, "work item layout");
 
 // Rows [r0, r1) of one tile, per-row results to c or to the split partials.
-// Not inlined: each (dtype, group, alignment) variant gets its own register
-// allocation (inlined together they spill at the 128-VGPR bound).
+// Inlined into the kernel, whose bound of two workgroups per compute unit
+// leaves room for every (dtype, group, alignment) variant without spills
+// (204 VGPRs): as separate non-inlined functions their call frames cost 160
+// bytes of scratch per lane, and within 128 VGPRs the inlined variants spill.
 template <int DT, int G, bool AL>
-__device__ __attribute__((noinline)) void bat_rows(const BatProblem& p, int64_t s, int64_t r0, int64_t r1, int64_t k0,
+__device__ __forceinline__ void bat_rows(const BatProblem& p, int64_t s, int64_t r0, int64_t r1, int64_t k0,
                                          int64_t klen, const unsigned char* xs_raw)
 {
     constexpr int GW = kWave / G;
@@ -178,8 +188,8 @@ __device__ __forceinline__ void bat_finish(const BatProblem& p, int64_t r0, int6
     }
 }
 
-// At least 4 waves per SIMD (4 workgroups per CU with 32 KiB of LDS each).
-__global__ __launch_bounds__(kBatNT, 4) void gemv_batched_kernel(const unsigned char* table)
+// Two workgroups per compute unit (two waves per SIMD).
+__global__ __launch_bounds__(kBatNT, 2) void gemv_batched_kernel(const unsigned char* table)
 {
     __shared__ __align__(16) unsigned char xs[kBatLds];
     __shared__ int last_flag;

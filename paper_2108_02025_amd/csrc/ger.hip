@@ -46,9 +46,31 @@ struct GerArgs {
     const T* y;
     T* C;
     int64_t RB;
+    uint64_t mask;  // the update probe's XOR mask (0 at run time)
 };
 
-template <typename T, int NT, bool ALIGNED>
+// The update probe's stand-in for the GER arithmetic: XOR of the bits with a
+// mask that is 0 at run time (so C is rewritten unchanged, and the compiler
+// cannot drop the load or the store).
+template <typename V>
+__device__ __forceinline__ V xor_bits(V v, uint64_t mask)
+{
+    typedef uint64_t u2 __attribute__((ext_vector_type(2)));
+    if constexpr (sizeof(V) == 16) {
+        u2 b = __builtin_bit_cast(u2, v);
+        b ^= mask;
+        return __builtin_bit_cast(V, b);
+    } else if constexpr (sizeof(V) == 8) {
+        return __builtin_bit_cast(V, __builtin_bit_cast(uint64_t, v) ^ mask);
+    } else {
+        return __builtin_bit_cast(V, __builtin_bit_cast(uint32_t, v) ^ (uint32_t)mask);
+    }
+}
+
+// PROBE: the measurement probe with GER's access pattern and launch shape
+// (C read and rewritten in place, no arithmetic): the ceiling of the read +
+// write stream GER moves.
+template <typename T, int NT, bool ALIGNED, bool PROBE = false>
 __global__ __launch_bounds__(NT) void ger_kernel(GerArgs<T> a)
 {
     constexpr int W = ALIGNED ? Vec<T>::W : 1;
@@ -67,7 +89,7 @@ __global__ __launch_bounds__(NT) void ger_kernel(GerArgs<T> a)
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
 #pragma unroll
-            for (int q = 0; q < W; ++q) yv[k][q] = a.y[j0 + (int64_t)k * NT * W + q];
+            for (int q = 0; q < W; ++q) yv[k][q] = PROBE ? T(0) : a.y[j0 + (int64_t)k * NT * W + q];
         }
         int64_t i = i0;
         for (; i + U - 1 < i1; i += U) {
@@ -79,13 +101,15 @@ __global__ __launch_bounds__(NT) void ger_kernel(GerArgs<T> a)
                 for (int k = 0; k < CH; ++k)
                     cv[u][k] = ld_stream<kGerLoadNT>(
                         reinterpret_cast<const V*>(a.C + (i + u) * a.ld + j0 + (int64_t)k * NT * W));
-                xv[u] = a.x[i + u];
+                xv[u] = PROBE ? T(0) : a.x[i + u];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
 #pragma unroll
                 for (int k = 0; k < CH; ++k) {
-                    if constexpr (W == 1) {
+                    if constexpr (PROBE) {
+                        cv[u][k] = xor_bits(cv[u][k], a.mask);
+                    } else if constexpr (W == 1) {
                         cv[u][k] = add_rn(cv[u][k], mul_rn(xv[u], yv[k][0]));
                     } else {
 #pragma unroll
@@ -97,12 +121,14 @@ __global__ __launch_bounds__(NT) void ger_kernel(GerArgs<T> a)
             }
         }
         for (; i < i1; ++i) {
-            const T xi = a.x[i];
+            const T xi = PROBE ? T(0) : a.x[i];
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
                 V* p = reinterpret_cast<V*>(a.C + i * a.ld + j0 + (int64_t)k * NT * W);
                 V cv = ld_stream<kGerLoadNT>(p);
-                if constexpr (W == 1) {
+                if constexpr (PROBE) {
+                    cv = xor_bits(cv, a.mask);
+                } else if constexpr (W == 1) {
                     cv = add_rn(cv, mul_rn(xi, yv[k][0]));
                 } else {
 #pragma unroll
@@ -117,10 +143,10 @@ __global__ __launch_bounds__(NT) void ger_kernel(GerArgs<T> a)
             const int64_t jk = j0 + (int64_t)k * NT * W;
             const int64_t rem = min<int64_t>(W, a.cols - jk);
             for (int64_t i = i0; i < i1; ++i) {
-                const T xi = a.x[i];
+                const T xi = PROBE ? T(0) : a.x[i];
                 for (int64_t q = 0; q < rem; ++q) {
                     T* p = a.C + i * a.ld + jk + q;
-                    *p = add_rn(*p, mul_rn(xi, a.y[jk + q]));
+                    *p = PROBE ? xor_bits(*p, a.mask) : add_rn(*p, mul_rn(xi, a.y[jk + q]));
                 }
             }
         }
@@ -129,7 +155,7 @@ __global__ __launch_bounds__(NT) void ger_kernel(GerArgs<T> a)
 
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-template <typename T>
+template <typename T, bool PROBE = false>
 static sb_status ger_typed(sb_handle* h, int64_t rows, int64_t cols, const T* x, const T* y, T* C,
                            int64_t ld)
 {
@@ -142,11 +168,11 @@ static sb_status ger_typed(sb_handle* h, int64_t rows, int64_t cols, const T* x,
     const int64_t target = SB_GER_BLOCKS;
     int64_t rb = std::max<int64_t>(SB_GER_MIN_ROWS, ceil_div(rows, std::max<int64_t>(1, target / cblocks)));
     rb = std::min<int64_t>(rb, rows);
-    GerArgs<T> a{rows, cols, ld, x, y, C, rb};
+    GerArgs<T> a{rows, cols, ld, x, y, C, rb, 0};
     const dim3 grid((unsigned)cblocks, (unsigned)ceil_div(rows, rb));
-    if (al) hipLaunchKernelGGL((ger_kernel<T, NT, true>), grid, dim3(NT), 0, h->stream, a);
-    else hipLaunchKernelGGL((ger_kernel<T, NT, false>), grid, dim3(NT), 0, h->stream, a);
-    return check_launch(h, "ger_kernel");
+    if (al) hipLaunchKernelGGL((ger_kernel<T, NT, true, PROBE>), grid, dim3(NT), 0, h->stream, a);
+    else hipLaunchKernelGGL((ger_kernel<T, NT, false, PROBE>), grid, dim3(NT), 0, h->stream, a);
+    return check_launch(h, PROBE ? "ger_kernel (update probe)" : "ger_kernel");
 }
 
 sb_status run_ger(sb_handle* h, sb_dtype dt, int64_t rows, int64_t cols, const void* x,
@@ -158,6 +184,12 @@ sb_status run_ger(sb_handle* h, sb_dtype dt, int64_t rows, int64_t cols, const v
                                  static_cast<const double*>(y), static_cast<double*>(C), ld);
     return ger_typed<float>(h, rows, cols, static_cast<const float*>(x), static_cast<const float*>(y),
                             static_cast<float*>(C), ld);
+}
+
+sb_status run_stream_update(sb_handle* h, void* C, int64_t rows, int64_t cols, int64_t ld)
+{
+    if (rows == 0 || cols == 0) return SB_OK;
+    return ger_typed<double, true>(h, rows, cols, nullptr, nullptr, static_cast<double*>(C), ld);
 }
 
 }  // namespace sb

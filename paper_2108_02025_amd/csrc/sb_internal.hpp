@@ -119,6 +119,7 @@ sb_status run_fill_uniform(sb_handle* h, sb_dtype dt, void* out, int64_t count, 
 size_t probe_ws_bytes(size_t bytes);
 sb_status run_stream_read(sb_handle* h, const void* src, size_t bytes);
 sb_status run_stream_copy(sb_handle* h, const void* src, void* dst, size_t bytes);
+sb_status run_stream_update(sb_handle* h, void* C, int64_t rows, int64_t cols, int64_t ld);
 
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 

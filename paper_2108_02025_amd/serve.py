@@ -494,6 +494,7 @@ class Stats:
     expired: int = 0
     rounds: int = 0
     max_queue: int = 0
+    trace_rate: float = math.nan    # the trace's own arrival rate, (N - 1) / (last - first arrival)
 
     def as_dict(self) -> dict:
         return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in dataclasses.asdict(self).items()}
@@ -713,5 +714,7 @@ def stats_of(trace: list[Request], sched: Scheduler, busy_events=()) -> Stats:
         device_busy_GBs=total / busy / 1e9 if busy > 0 else math.nan,
         batches=sched.batches, mean_batch=len(ok) / max(sched.batches, 1), total_bytes=total,
         dot_requests=sum(r.op == "dot" for r in ok), expired=int((sched.status == 3).sum()),
-        rounds=sched.n_rounds, max_queue=sched.max_queue)
+        rounds=sched.n_rounds, max_queue=sched.max_queue,
+        trace_rate=(len(trace) - 1) / (trace[-1].arrival - trace[0].arrival)
+        if len(trace) > 1 and trace[-1].arrival > trace[0].arrival else math.nan)
 

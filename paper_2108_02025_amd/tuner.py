@@ -1,22 +1,27 @@
 """Autotuner for the batched GEMV kernel.
 
-For every bucket (kind, round(log2 m), round(log2 n)) with kind binary32 or
-bfloat16-A and m, n in [64, 8192], the tuner builds a batch of identical
-problems of the bucket's shape (operands generated on the device), times
-each candidate configuration
+For every bucket (kind, round(log2 m), round(log2 n)) with kind binary64,
+binary32, bfloat16-A or E4M3-A and m, n in [64, 8192], the tuner builds a
+batch of identical problems of the bucket's shape (operands made on the
+device), times each candidate configuration
 
     group          lanes per row (rows per wave = 64 / group): the powers of
                    two 4..64 that leave each lane at least one 16-byte load
-    split          column chunks (tile width n / split; split-K): 1, plus 2
-                   and 4 for short, wide shapes
+    split          column chunks (tile width n / split; split-K): the fewest
+                   whose x chunk fits 32 KiB of LDS, plus twice and four times
+                   that for short, wide shapes
+    rows_per_tile  tile height: automatic (about 256 KiB of A, at most eight
+                   row passes), or two or sixteen row passes of the workgroup
 
-(the tile height stays automatic: it is sized from the whole batch, which
-the tuner cannot know, and never changes a row's arithmetic)
 with HIP events (median of several launches over the same table) and keeps
-the fastest.  The table is saved as JSON keyed by GPU architecture and
-library version; `TuningTable` maps any (kind, m, n) to its bucket's
-configuration.  A problem's configuration depends only on its own shape, so
-tuning never breaks the alone-vs-mix equality of results.
+the fastest.  Waves per workgroup, loads in flight per lane and the grid are
+fixed when the library is built (measured: two 4-wave workgroups per
+compute unit with 8 loads in flight for binary64, binary32 and bfloat16
+codes and 4 for E4M3; as build-time constants they cost no registers).  The
+table is saved as JSON keyed by GPU architecture and library version;
+`TuningTable` maps any (kind, m, n) to its bucket's configuration.  A
+problem's configuration depends only on its own shape, so tuning never
+breaks the alone-vs-mix equality of results.
 
     python -m paper_2108_02025_amd.tuner [--out FILE] [--quick]
 """
@@ -30,7 +35,8 @@ import os
 import numpy as np
 import torch
 
-from . import SB_BF16, BatchTable, GemvProblem, sb_gemv_batched_table_bytes, sb_version
+from . import (SB_BF16, SB_FP8_E4M3, BatchTable, GemvProblem, StreamBlasError, sb_gemv_batched_table_bytes,
+               sb_quantize_rows, sb_version)
 from .serve import GEN_DESC, device_bytes
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -44,23 +50,52 @@ def bucket(kind: str, m: int, n: int) -> str:
     return f"{kind}/{lm}/{ln}"
 
 
+ESIZE = {"f64": 8, "f32": 4, "bf16": 2, "e4m3": 1}   # bytes per element of A
+
+
 def candidates(kind: str, m: int, n: int) -> list[dict]:
-    per16 = 4 if kind == "f32" else 8          # elements per 16-byte load
+    per16 = 16 // ESIZE[kind]                  # elements per 16-byte load
     out = []
     for g in (4, 8, 16, 32, 64):
         if g > 4 and (n + per16 - 1) // per16 < g:
             continue
-        splits = [1]
+        s0 = max(1, -(-n * (8 if kind == "f64" else 4) // 32768))   # x chunks must fit 32 KiB of LDS
+        splits = [s0]
         if n >= 2048 and m <= 1024:
-            splits += [2, 4]
+            splits += [2 * s0, 4 * s0]
+        rpass = 4 * (64 // g)                  # rows of one pass of a 4-wave workgroup
+        heights = [0] + [h for h in (2 * rpass, 16 * rpass) if h < m]
         for sp in splits:
-            out.append({"group": g, "rows_per_tile": 0, "split": sp})
+            for rt in heights:
+                out.append({"group": g, "rows_per_tile": rt, "split": sp})
     return out
 
 
+def problem_bytes(kind: str, m: int, n: int) -> int:
+    return ESIZE[kind] * m * n
+
+
 def _make_batch(kind: str, m: int, n: int, count: int, device):
-    """`count` problems of one shape with operands made on the device."""
+    """`count` problems of one shape with operands made on the device:
+    binary32 and bfloat16-A by the serving loop's generator, binary64 and
+    E4M3-A from torch's seeded uniform draws (E4M3 quantised per row)."""
     from . import Handle, load
+    if kind in ("f64", "e4m3"):
+        g = torch.Generator(device=device)
+        g.manual_seed(777)
+        dt = torch.float64 if kind == "f64" else torch.float32
+        views = []
+        for _ in range(count):
+            A = torch.rand((m, n), generator=g, device=device, dtype=dt) * 2 - 1
+            sc = None
+            if kind == "e4m3":
+                Aq = torch.empty((m, n), dtype=torch.uint8, device=device)
+                sc = torch.empty(m, dtype=torch.float32, device=device)
+                sb_quantize_rows(A, Aq, sc, SB_FP8_E4M3)
+                A = Aq
+            xv = torch.rand(n, generator=g, device=device, dtype=dt) * 2 - 1
+            views.append((A, sc, xv, torch.zeros(m, dtype=dt, device=device)))
+        return None, views
     per = device_bytes(kind, m, n)
     buf = torch.empty(per * count, dtype=torch.uint8, device=device)
     base = buf.data_ptr()
@@ -90,10 +125,13 @@ def _make_batch(kind: str, m: int, n: int, count: int, device):
 
 
 def time_config(kind, m, n, cfg, views, table: BatchTable, reps=7) -> float:
-    probs = [GemvProblem(A, xv, cv, scales=sc, q=SB_BF16 if kind == "bf16" else None, **cfg)
-             for A, sc, xv, cv in views]
-    if sb_gemv_batched_table_bytes(probs)[0] > table.capacity:
-        return math.inf
+    q = {"bf16": SB_BF16, "e4m3": SB_FP8_E4M3}.get(kind)
+    probs = [GemvProblem(A, xv, cv, scales=sc, q=q, **cfg) for A, sc, xv, cv in views]
+    try:
+        if sb_gemv_batched_table_bytes(probs)[0] > table.capacity:
+            return math.inf
+    except StreamBlasError:
+        return math.inf   # not a valid configuration for this shape (e.g. x chunk above 32 KiB)
     table.encode(probs)
     table.run()
     evs = []
@@ -108,7 +146,8 @@ def time_config(kind, m, n, cfg, views, table: BatchTable, reps=7) -> float:
     return sorted(x.elapsed_time(y) for x, y in evs)[reps // 2] * 1e3
 
 
-def tune(kinds=("f32", "bf16"), buckets=None, batch_bytes=96 << 20, max_count=64, log=print) -> dict:
+def tune(kinds=("f32", "bf16", "f64", "e4m3"), buckets=None, batch_bytes=96 << 20, max_count=64,
+         log=print) -> dict:
     dev = torch.device("cuda", torch.cuda.current_device())
     bt = BatchTable(64 << 20, dev)
     table = {}
@@ -119,7 +158,7 @@ def tune(kinds=("f32", "bf16"), buckets=None, batch_bytes=96 << 20, max_count=64
                 if buckets and key not in buckets:
                     continue
                 m, n = 1 << lm, 1 << ln
-                count = max(1, min(max_count, batch_bytes // device_bytes(kind, m, n)))
+                count = max(1, min(max_count, batch_bytes // problem_bytes(kind, m, n)))
                 buf, views = _make_batch(kind, m, n, count, dev)
                 best = None
                 for cfg in candidates(kind, m, n):
@@ -127,8 +166,7 @@ def tune(kinds=("f32", "bf16"), buckets=None, batch_bytes=96 << 20, max_count=64
                     if best is None or us < best[0]:
                         best = (us, cfg)
                 auto_us = time_config(kind, m, n, {"group": 0, "rows_per_tile": 0, "split": 0}, views, bt)
-                es = 4 if kind == "f32" else 2
-                gbs = count * (es * m * n) / best[0] / 1e3
+                gbs = count * problem_bytes(kind, m, n) / best[0] / 1e3
                 table[key] = {**best[1], "us": round(best[0], 2), "auto_us": round(auto_us, 2),
                               "GBs": round(gbs, 1), "count": int(count)}
                 log(f"{key}: {best[1]} {best[0]:.1f} us (automatic {auto_us:.1f} us), {gbs:.0f} GB/s")
@@ -168,7 +206,7 @@ def main():
     args = ap.parse_args()
     buckets = None
     if args.quick:
-        buckets = {"f32/13/13", "bf16/13/13", "f32/6/13", "bf16/13/6", "f32/10/10"}
+        buckets = {"f32/13/13", "bf16/13/13", "f32/6/13", "bf16/13/6", "f32/10/10", "f64/12/12", "e4m3/10/13"}
     data = tune(buckets=buckets)
     with open(args.out, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)

@@ -402,3 +402,13 @@ def test_gemv_noalloc_checks_before_any_hip_call(L, h):
     assert b"sb_gemv_noalloc" in L.sb_last_error(h)
     assert L.sb_gemv_noalloc(h, 0, 0, 0, 0, 10, A, 10, X, C) == 0        # empty output: nothing to do
     assert L.sb_gemv_noalloc(None, 0, 0, 0, 10, 10, A, 10, X, C) == -1
+
+
+def test_stream_update_validation(L, h):
+    C = 1 << 40
+    assert L.sb_stream_update(None, C, 4, 4, 4) == -1
+    assert L.sb_stream_update(h, C, 4, 8, 4) == -1          # ldc below cols
+    assert L.sb_stream_update(h, C, -1, 4, 4) == -1
+    assert L.sb_stream_update(h, C + 4, 4, 4, 4) == -1      # not 8-byte aligned
+    assert L.sb_stream_update(h, None, 4, 4, 4) == -1
+    assert L.sb_stream_update(h, None, 0, 4, 4) == 0        # empty: nothing launched

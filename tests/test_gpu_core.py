@@ -257,3 +257,13 @@ def test_ger_f32_and_misaligned(sb):
     out = host(bd)[1:].reshape(m, ld)
     assert np.array_equal(out[:, :n], oracle.ger(x, y, C0))
     assert np.isnan(out[:, n:]).all() and np.isnan(host(bd)[0])  # padding untouched
+
+
+@pytest.mark.parametrize("m,n", [(16384, 1024), (100, 1003), (37, 4096)])
+def test_stream_update_probe_leaves_matrix_unchanged(sb, m, n):
+    """The GER-pattern probe reads and rewrites C in place: every bit stays."""
+    rng = np.random.default_rng(m + n)
+    C = rng.standard_normal((m, n))
+    Cd = dev(C)
+    sb.sb_stream_update(Cd)
+    assert np.array_equal(host(Cd).view(np.uint64), C.view(np.uint64))

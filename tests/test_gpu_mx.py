@@ -42,12 +42,12 @@ def decode(codes, scales, q, n):
     return X * P
 
 
-def to_device_mx(sb, codes, scales, q, n, pad_q=0, pad_s=0):
+def to_device_mx(sb, codes, scales, q, n, pad_q=0, pad_s=0, fill=0):
     m = codes.shape[0]
     Q, S = sb.mx_buffers(q, m, n)
-    if pad_q or pad_s:
-        Q = torch.zeros((m, Q.shape[1] + pad_q), dtype=torch.uint8, device="cuda")
-        S = torch.zeros((m, S.shape[1] + pad_s), dtype=torch.uint8, device="cuda")
+    if pad_q or pad_s or fill:
+        Q = torch.full((m, Q.shape[1] + pad_q), fill, dtype=torch.uint8, device="cuda")
+        S = torch.full((m, S.shape[1] + pad_s), fill, dtype=torch.uint8, device="cuda")
     Q[:, :codes.shape[1]] = dev(codes)
     S[:, :scales.shape[1]] = dev(scales)
     return Q, S
@@ -126,6 +126,23 @@ def test_gemv_mx_bound(sb, q, m, n):
     assert_within(got, ref, gemv_bound(D, x, c0, 0, n, U32), f"gemv_mx q={q} {m}x{n}")
     got2 = run_gemv_mx(sb, codes, scales, q, x, c0, pad_q=48, pad_s=5)   # padded strides
     assert np.array_equal(got, got2)
+
+
+@pytest.mark.parametrize("q", QS)
+@pytest.mark.parametrize("m,n", [(5, 4097), (17, 8191), (3, 16385), (9, 16415), (130, 70001)])
+def test_gemv_mx_row_edges_ignore_padding(sb, q, m, n):
+    """Rows that end inside a 16-byte code vector, with every padding byte of
+    Q and S set to 0xFF (a NaN E4M3 code, a NaN E8M0 scale): the padding
+    never reaches the result, which equals the zero-padded run bit for bit
+    and lies within the bound of the oracle."""
+    A, x, c0 = workloads.gemv_inputs(m, n, seed=n, dist="normal", dtype=np.float32)
+    codes, scales = oracle.quantize_mx(A, q)
+    ref = oracle.gemv_mx(codes, scales, x, c0, q, n)
+    got = run_gemv_mx(sb, codes, scales, q, x, c0, pad_q=32, pad_s=3)
+    poisoned = run_gemv_mx(sb, codes, scales, q, x, c0, pad_q=32, pad_s=3, fill=0xFF)
+    assert np.array_equal(got, poisoned)
+    D = decode(codes, scales, q, n)
+    assert_within(got, ref, gemv_bound(D, x, c0, 0, n, U32), f"gemv_mx q={q} {m}x{n}")
 
 
 @pytest.mark.parametrize("q", QS)

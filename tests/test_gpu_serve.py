@@ -141,7 +141,9 @@ def test_generate_batched_matches_fill_and_quantise(sb):
     # short rows are dealt in blocks of several rows per work item (ragged last blocks)
     shapes = [("f32", 5, 7), ("bf16", 64, 8192), ("bf16", 300, 1000), ("f32", 1000, 300), ("bf16", 3, 0),
               ("f32", 0, 5), ("bf16", 1, 1), ("f32", 700, 64), ("bf16", 513, 33), ("f32", 129, 31),
-              ("bf16", 2, 5000), ("f32", 3, 4097)]
+              ("bf16", 2, 5000), ("f32", 3, 4097),
+              # bfloat16 rows past the LDS stash (generated twice), rows on odd counters
+              ("bf16", 5, 4097), ("bf16", 3, 8191), ("bf16", 1, 2049), ("bf16", 2, 8193), ("f32", 4, 8193)]
     stage = torch.empty(8192 * 8192, dtype=torch.float32, device="cuda")
     gen = np.zeros(len(shapes), dtype=GEN_DESC)
     bufs, refs = [], []
@@ -175,7 +177,8 @@ def test_generate_batched_padded_rows(sb):
     from paper_2108_02025_amd.serve import GEN_DESC, Request, device_bytes, materialise
     up = lambda v: (v + 255) // 256 * 256  # noqa: E731
     stage = torch.empty(1 << 20, dtype=torch.float32, device="cuda")
-    for kind, m, n, pad in (("f32", 37, 100, 3), ("bf16", 37, 100, 5), ("f32", 300, 40, 1), ("bf16", 200, 21, 2)):
+    for kind, m, n, pad in (("f32", 37, 100, 3), ("bf16", 37, 100, 5), ("f32", 300, 40, 1), ("bf16", 200, 21, 2),
+                            ("bf16", 7, 3001, 3), ("f32", 5, 3001, 1)):
         es = 4 if kind == "f32" else 2
         lda = n + pad
         r = Request(0, 0.0, kind, m, n, 77)
