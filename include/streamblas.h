@@ -281,27 +281,43 @@ sb_status sb_dot2_f32(sb_handle* handle, int64_t n, const float* x, const float*
 /*
  * Batched GEMV (batching form).  The paper notes that for small problems the
  * cost of starting threads dominates (section 4.2); on the GPU that cost is
- * a launch, so many row-major problems c += A x share one persistent launch.
- * Each problem is cut into tiles of rows_per_tile rows by one column chunk
+ * a launch, so many problems c += op(A) x share one persistent launch.
+ * layout and op have sb_gemv's meaning (m x n matrix A, lda its leading
+ * dimension; op SB_N: x has n entries and c m, SB_T: x m and c n).
+ *
+ * Row dots (row-major N, column-major T: the output runs along the stored
+ * rows) are cut into tiles of rows_per_tile stored rows by one column chunk
  * (split chunks per row; split > 1 is split-K: per-chunk partial sums are
- * added in chunk order, then the initial c).  Runs of consecutive tiles of
- * one problem form work items, which the encoder deals to the workgroups of
- * a fixed grid, largest first in rounds of alternating direction, so the
- * workgroups' shares differ by at most one item.  A problem's result depends
- * only on the problem and its configuration, so it is bit-identical alone and
- * in any mix.  The same per-row arithmetic as sb_gemv / sb_gemv_q is used.
+ * added in chunk order, then the initial c).  Column axpys (row-major T,
+ * column-major N: the output runs along the stored columns; sections 4.1
+ * and 4.2) are cut into column blocks of one wave's width (256 binary32 or
+ * 128 binary64 columns, or 64 if the stored rows are not 16-byte aligned)
+ * by chunks of rows_per_tile stored rows (split chunks; partial sums added
+ * in chunk order, then the initial c).
+ * Runs of consecutive tiles of one problem form work items, which the
+ * encoder deals to the workgroups of a fixed grid, largest first in rounds
+ * of alternating direction, so the workgroups' shares differ by at most one
+ * item.  A problem's result depends only on the problem and its
+ * configuration, so it is bit-identical alone and in any mix.  Row dots use
+ * the same per-row arithmetic as sb_gemv / sb_gemv_q.
  *
  *   dtype  SB_F64 or SB_F32: A, x and c of that type.  SB_BF16 or
- *          SB_FP8_E4M3: A holds codes (lda in elements) with per-row binary32
- *          scales as written by sb_quantize_rows; x and c are binary32 and
+ *          SB_FP8_E4M3 (row-major N only, else SB_EUNSUPPORTED): A holds
+ *          codes (lda in elements) with per-row binary32 scales as written
+ *          by sb_quantize_rows; x and c are binary32 and
  *          c_i += s_i * sum_j q_ij x_j.
- *   group  lanes cooperating on a row: 4, 8, 16, 32 or 64 (0: automatic).
- *   rows_per_tile  a multiple of 4 * (64 / group) (0: automatic, about
- *          256 KiB of A per tile and at most 8 row passes of a workgroup;
- *          the tile height never changes a row's result).
- *   split  column chunks; each chunk's x must fit 32 KiB of LDS (0: automatic).
+ *   group  row dots: lanes cooperating on a row, 4, 8, 16, 32 or 64 (0:
+ *          automatic).  Column axpys: must be 0.
+ *   rows_per_tile  row dots: a multiple of 4 * (64 / group) (0: automatic,
+ *          about 256 KiB of A per tile and at most 8 row passes of a
+ *          workgroup; the tile height never changes a row's result).
+ *          Column axpys: stored rows per chunk (0: from split, or about
+ *          256 KiB of A per tile); the chunking sets the summation order.
+ *   split  row dots: column chunks, each chunk's x must fit 32 KiB of LDS
+ *          (0: automatic).  Column axpys: row chunks (0: from
+ *          rows_per_tile; if both are given they must agree).
  * Outputs of different problems must not overlap.  Problems with m = 0 or
- * n = 0 are skipped.
+ * n = 0 are skipped.  The zero-initialised layout and op are row-major N.
  */
 typedef struct {
     int32_t dtype;
@@ -313,10 +329,12 @@ typedef struct {
     const float* scales;
     const void* x;
     void* c;
+    int32_t layout;  /* sb_layout */
+    int32_t op;      /* sb_op */
 } sb_gemv_desc;
 
 /* Device bytes of the batch table (header, problem records, work items and
- * the per-workgroup item lists, split counters and split scratch) for these
+ * the per-workgroup item lists, second-stage items and split scratch) for these
  * descriptors; *image_bytes (if not NULL)
  * receives the size of the part sb_gemv_batched_encode writes.  Returns
  * (size_t)-1 for invalid descriptors. */
@@ -335,10 +353,12 @@ sb_status sb_gemv_batched_encode(const sb_gemv_desc* descs, int32_t count, void*
 
 /* Launch the persistent kernel over the table at dev_table on the handle's
  * stream (grid workgroups; 0 = 1024, the grid the items are dealt to; a
- * smaller grid runs several workgroups' lists per workgroup).  Everything
- * the kernel needs is read from the table, so a captured launch can be
- * replayed over new tables written to the same address.  The table stays
- * valid for further launches. */
+ * smaller grid runs several workgroups' lists per workgroup), then the
+ * second-stage kernel that adds the split problems' partial sums in split
+ * order (it returns at once if the table has none).  Everything the kernels
+ * need is read from the table, so a captured launch can be replayed over new
+ * tables written to the same address.  The table stays valid for further
+ * launches. */
 sb_status sb_gemv_batched_run(sb_handle* handle, const void* dev_table, int32_t grid);
 
 /* Encode, copy the table into the handle's workspace (needs

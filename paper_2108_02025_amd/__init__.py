@@ -50,7 +50,8 @@ class sb_gemv_desc(ctypes.Structure):
     """One problem of a batched GEMV (layout of the C struct)."""
     _fields_ = [("dtype", ctypes.c_int32), ("group", ctypes.c_int32), ("rows_per_tile", ctypes.c_int32),
                 ("split", ctypes.c_int32), ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("lda", ctypes.c_int64),
-                ("A", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("x", ctypes.c_void_p), ("c", ctypes.c_void_p)]
+                ("A", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("x", ctypes.c_void_p), ("c", ctypes.c_void_p),
+                ("layout", ctypes.c_int32), ("op", ctypes.c_int32)]
 
 
 class StreamBlasError(RuntimeError):
@@ -478,18 +479,20 @@ def sb_stream_update(C: torch.Tensor) -> None:
 
 
 class GemvProblem:
-    """One row-major problem c += A x (or c += diag(scales) Q x for codes).
+    """One problem c += op(A) x (or c += diag(scales) Q x for codes).
 
-    A is a 2-D device tensor with unit column stride (float64/float32, or
-    2-byte / 1-byte codes with q = SB_BF16 / SB_FP8_E4M3 and scales);
-    group / rows_per_tile / split select the launch configuration (0: automatic).
+    A is a 2-D device tensor with unit stride along its rows or its columns
+    (float64/float32 with op SB_N or SB_T; or row-major 2-byte / 1-byte codes
+    with q = SB_BF16 / SB_FP8_E4M3, scales and op SB_N); group /
+    rows_per_tile / split select the launch configuration (0: automatic).
     """
 
-    __slots__ = ("A", "x", "c", "scales", "q", "group", "rows_per_tile", "split")
+    __slots__ = ("A", "x", "c", "scales", "q", "group", "rows_per_tile", "split", "op")
 
-    def __init__(self, A, x, c, scales=None, q=None, group=0, rows_per_tile=0, split=0):
+    def __init__(self, A, x, c, scales=None, q=None, group=0, rows_per_tile=0, split=0, op=SB_N):
         self.A, self.x, self.c, self.scales, self.q = A, x, c, scales, q
         self.group, self.rows_per_tile, self.split = group, rows_per_tile, split
+        self.op = op
 
     def dtype(self) -> int:
         if self.q is not None:
@@ -502,22 +505,26 @@ def make_descs(problems) -> "ctypes.Array":
     arr = (sb_gemv_desc * max(len(problems), 1))()
     for i, p in enumerate(problems):
         layout, ld = _matrix_layout(p.A)
-        if layout != SB_ROW_MAJOR:
-            raise ValueError("batched problems must be row-major")
         m, n = p.A.shape
         dt = p.dtype()
+        if p.op not in (SB_N, SB_T):
+            raise ValueError("op must be SB_N or SB_T")
         if dt in (SB_BF16, SB_FP8_E4M3):
+            if layout != SB_ROW_MAJOR or p.op != SB_N:
+                raise ValueError("quantised batched problems are row-major N (the scales belong to rows)")
             _q_check(dt, p.A)
             if p.scales is None or p.scales.numel() != m or p.x.dtype != torch.float32 or p.c.dtype != torch.float32:
                 raise ValueError("quantised problems need m scales and float32 x, c")
         elif p.x.dtype != p.A.dtype or p.c.dtype != p.A.dtype:
             raise TypeError("A, x and c must share a dtype")
         _vec(p.x), _vec(p.c)
-        if p.x.numel() != n or p.c.numel() != m:
-            raise ValueError("x must have n entries and c m")
+        xl, cl = (n, m) if p.op == SB_N else (m, n)
+        if p.x.numel() != xl or p.c.numel() != cl:
+            raise ValueError("x must have n entries and c m (op N), or x m and c n (op T)")
         d = arr[i]
         d.dtype, d.group, d.rows_per_tile, d.split = dt, p.group, p.rows_per_tile, p.split
         d.m, d.n, d.lda = m, n, ld
+        d.layout, d.op = layout, p.op
         d.A, d.x, d.c = p.A.data_ptr(), p.x.data_ptr(), p.c.data_ptr()
         d.scales = p.scales.data_ptr() if p.scales is not None else None
     return arr

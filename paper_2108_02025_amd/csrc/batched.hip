@@ -16,16 +16,32 @@
 // the same chunk) and runs the same per-row dot products as the single-call
 // kernels.
 //
-// A problem split into S column chunks writes per-split partial sums to
-// scratch; the tile that completes a row tile (a per-row-tile counter
-// reaches S) adds the partials in split order and then the initial c.  Every
-// result therefore depends only on the problem and its (group, rows per
-// tile, split) configuration, never on the rest of the batch or on which
-// workgroup ran it: a problem gives the same bits alone and in a mix.
+// Both layouts and both operations are accepted (sections 4.1 and 4.2 treat
+// both storage orders).  (row-major, N) and (column-major, T) are row dots
+// over the stored rows, as above.  (row-major, T) and (column-major, N) are
+// column axpys over the stored rows (the output runs along the stored
+// columns): such a problem is cut into column blocks of one wave's width
+// (64 lanes, each owning one 16-byte vector of consecutive columns, or one
+// column if the rows are not 16-byte aligned) by row chunks; the four waves
+// of the workgroup take alternate rows of a chunk, each lane adding its
+// columns' products in row order, and the waves' sums are added in wave
+// order through LDS.  Several row chunks write partial sums that the
+// completing tile adds in chunk order, as for split row dots.
 //
-// The table (header, problem records, work items grouped by workgroup,
-// zeroed split counters) is encoded on the host and copied to device memory
-// before the launch; the kernel reads everything it needs from it, so a
+// A problem split into S column chunks writes per-split partial sums to
+// scratch; a second kernel then adds each output's partials in split order
+// and then the initial c.  (Handing the last split's tile the sum instead,
+// through a counter, needs a device-scope release and acquire per tile,
+// which on this chip write back and invalidate the whole L2 of the
+// workgroup's XCD: binary64 8192^2 problems, all split in two, ran at
+// 0.66 TB/s that way.)  Every result therefore depends only on the problem
+// and its (group, rows per tile, split) configuration, never on the rest of
+// the batch or on which workgroup ran it: a problem gives the same bits
+// alone and in a mix.
+//
+// The table (header, problem records, work items grouped by workgroup, the
+// second kernel's items) is encoded on the host and copied to device memory
+// before the launch; the kernels read everything they need from it, so a
 // captured launch can be replayed over new tables written to the same
 // address.
 #include <string.h>
@@ -74,11 +90,15 @@ constexpr int64_t kBatTileBytes = SB_BAT_TILE_BYTES;  // largest automatic tile 
 #ifndef SB_BAT_UNROLL_E4M3
 #define SB_BAT_UNROLL_E4M3 4
 #endif
+#ifndef SB_BAT_UNROLL_T
+#define SB_BAT_UNROLL_T 8
+#endif
 #ifndef SB_BAT_GRID
 #define SB_BAT_GRID 1024
 #endif
 constexpr int kBatUnrollPlain = SB_BAT_UNROLL_PLAIN, kBatUnrollBf16 = SB_BAT_UNROLL_BF16,
               kBatUnrollE4m3 = SB_BAT_UNROLL_E4M3;
+constexpr int kBatUnrollT = SB_BAT_UNROLL_T;  // rows in flight per wave of a column-axpy tile (16-byte rows)
 // The items are dealt to 1024 workgroups, two rounds of the two that fit a
 // compute unit: in the serving loop the operand generator runs beside the
 // batched kernel, and finer lists let the batched workgroups fill whatever
@@ -86,6 +106,8 @@ constexpr int kBatUnrollPlain = SB_BAT_UNROLL_PLAIN, kBatUnrollBf16 = SB_BAT_UNR
 // second against 1.10e5 with 512 lists); alone, 512 and 1024 lists run
 // within noise of each other.
 constexpr int kBatGrid = SB_BAT_GRID;
+constexpr int64_t kFinishChunk = 4 * kBatNT;  // outputs per second-stage item
+constexpr int kFinishGrid = 256;              // second-stage workgroups
 
 struct BatHeader {
     int64_t count;
@@ -95,10 +117,15 @@ struct BatHeader {
     int64_t items_off;   // byte offset of the work items (grouped by workgroup)
     int64_t lists_off;   // byte offset of grid + 1 int32 offsets: workgroup b's items are [off[b], off[b + 1])
     int32_t grid;        // workgroups the items were dealt to
-    int32_t pad;
-    int64_t pad2;
+    int32_t nfinish;     // second-stage items (outputs of split problems, kFinishChunk at a time)
+    int64_t finish_off;  // byte offset of the second-stage items
 };
 
+// m, n, lda describe the stored matrix: m stored rows of n contiguous
+// elements.  Row dot (cols == 0): c has m entries, x n; RT rows per tile,
+// KC columns per split.  Column axpy (cols == 1): c has n entries, x m; RT
+// rows per chunk, KC columns per block; rtiles counts the output tiles (row
+// tiles or column blocks).
 struct BatProblem {
     int32_t dtype, G, RT, S;
     int64_t m, n, lda, KC;
@@ -109,12 +136,13 @@ struct BatProblem {
     const void* x;
     void* c;
     void* partial;
-    int32_t* counters;
-    int32_t aligned, pad;
+    void* reserved;
+    int32_t aligned, cols;
     int64_t pad2;
 };
 
-// Tiles [first, first + count) (numbered within the problem) of one problem.
+// Tiles [first, first + count) (numbered within the problem) of one problem;
+// for the second stage, outputs [first, first + count).
 struct BatItem {
     int32_t problem;
     int32_t count;
@@ -123,6 +151,7 @@ struct BatItem {
 static_assert(sizeof(BatHeader) == 64, "header layout");
 static_assert(sizeof(BatProblem) == 144, "problem record layout");
 static_assert(sizeof(BatItem) == 16, "work item layout");
+static_assert(sizeof(sb_gemv_desc) == 80, "descriptor layout (mirrored by the Python binding)");
 
 // Rows [r0, r1) of one tile, per-row results to c or to the split partials.
 // Inlined into the kernel, whose bound of two workgroups per compute unit
@@ -175,24 +204,91 @@ __device__ __forceinline__ void bat_rows_g(const BatProblem& p, int64_t s, int64
     }
 }
 
-// Second stage of a split row tile: c_i += (scale *) sum over splits in order.
-template <typename T>
-__device__ __forceinline__ void bat_finish(const BatProblem& p, int64_t r0, int64_t r1)
+// Columns [j0, j1) of one row chunk of a column-axpy problem: c_j += sum_i
+// A[i, j] x_i over the chunk's rows, or the chunk's partial sums.  red is
+// 4 KiB of LDS.
+template <typename T, bool AL>
+__device__ __forceinline__ void bat_cols(const BatProblem& p, int64_t cb, int64_t s, unsigned char* red_raw)
 {
-    const T* part = static_cast<const T*>(p.partial);
-    T* c = static_cast<T*>(p.c);
-    for (int64_t row = r0 + threadIdx.x; row < r1; row += kBatNT) {
-        const T t = ordered_split_sum(part + row, (int64_t)p.S, p.m);
-        if (p.dtype == SB_BF16 || p.dtype == SB_FP8_E4M3) c[row] = c[row] + p.scales[row] * t;
-        else c[row] = c[row] + t;
+    constexpr int W = AL ? Vec<T>::W : 1;
+    typedef typename std::conditional<AL, typename Vec<T>::type, T>::type V;
+    // rows in flight per wave: element loads move fewer bytes each
+    constexpr int U = AL ? kBatUnrollT : 16 / (int)sizeof(T) * kBatUnrollT;
+    constexpr int CW = kWave * W;
+    static_assert(kBatWaves * CW * sizeof(T) <= 4096, "column-axpy LDS");
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t j0 = cb * CW + lane * W;
+    const int64_t i0 = s * p.RT, i1 = min(p.m, i0 + p.RT);
+    const T* A = static_cast<const T*>(p.A);
+    const T* x = static_cast<const T*>(p.x);
+    T acc[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) acc[q] = 0;
+    if (j0 + W <= p.n) {
+        int64_t i = i0 + w;
+        for (; i + (U - 1) * kBatWaves < i1; i += U * kBatWaves) {
+            V av[U];
+            T xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                av[u] = ld_stream<true>(reinterpret_cast<const V*>(A + (i + u * kBatWaves) * p.lda + j0));
+                xv[u] = x[i + u * kBatWaves];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if constexpr (W == 1) {
+                    acc[0] += av[u] * xv[u];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < W; ++q) acc[q] += av[u][q] * xv[u];
+                }
+            }
+        }
+        for (; i < i1; i += kBatWaves) {
+            const V av = ld_stream<true>(reinterpret_cast<const V*>(A + i * p.lda + j0));
+            const T xv = x[i];
+            if constexpr (W == 1) {
+                acc[0] += av * xv;
+            } else {
+#pragma unroll
+                for (int q = 0; q < W; ++q) acc[q] += av[q] * xv;
+            }
+        }
+    } else if (j0 < p.n) {
+        // right edge: fewer than W columns left for this lane
+        const int rem = (int)(p.n - j0);
+        for (int64_t i = i0 + w; i < i1; i += kBatWaves) {
+            const T xv = x[i];
+#pragma unroll
+            for (int q = 0; q < W; ++q)
+                if (q < rem) acc[q] += A[i * p.lda + j0 + q] * xv;
+        }
     }
+    T* red = reinterpret_cast<T*>(red_raw);
+#pragma unroll
+    for (int q = 0; q < W; ++q) red[w * CW + lane * W + q] = acc[q];
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            T t = red[lane * W + q];
+#pragma unroll
+            for (int k = 1; k < kBatWaves; ++k) t += red[k * CW + lane * W + q];
+            const int64_t j = j0 + q;
+            if (j < p.n) {
+                if (p.S > 1) static_cast<T*>(p.partial)[s * p.n + j] = t;
+                else static_cast<T*>(p.c)[j] = static_cast<T*>(p.c)[j] + t;
+            }
+        }
+    }
+    __syncthreads();  // red is written again by the next tile
 }
 
 // Two workgroups per compute unit (two waves per SIMD).
 __global__ __launch_bounds__(kBatNT, 2) void gemv_batched_kernel(const unsigned char* table)
 {
     __shared__ __align__(16) unsigned char xs[kBatLds];
-    __shared__ int last_flag;
+    __shared__ __align__(16) unsigned char red[4096];
     const BatHeader* hdr = reinterpret_cast<const BatHeader*>(table);
     const BatProblem* probs = reinterpret_cast<const BatProblem*>(table + sizeof(BatHeader));
     const BatItem* items = reinterpret_cast<const BatItem*>(table + hdr->items_off);
@@ -208,57 +304,77 @@ __global__ __launch_bounds__(kBatNT, 2) void gemv_batched_kernel(const unsigned 
         const int64_t pi = it.problem;
         const BatProblem p = probs[pi];
         for (int64_t local = it.first; local < it.first + it.count; ++local) {
+            // s: the split (column chunk of a row dot, row chunk of a column
+            // axpy); rt: the output tile (row tile, or column block)
             const int64_t s = local % p.S, rt = local / p.S;
             const int64_t r0 = rt * p.RT, r1 = min(p.m, r0 + p.RT);
             const int64_t k0 = s * p.KC, klen = min(p.n, k0 + p.KC) - k0;
 
-            if (pi != cached_p || s != cached_s) {
-                __syncthreads();  // every row of the previous tile has read x
-                const int xs_size = p.dtype == SB_F64 ? 8 : 4;
-                const unsigned char* xg = static_cast<const unsigned char*>(p.x) + k0 * xs_size;
-                const int64_t nbytes = klen * xs_size;
-                if (((reinterpret_cast<uintptr_t>(xg) | (uintptr_t)nbytes) & 15) == 0) {
-                    stage_to_lds<kBatNT, 8>(reinterpret_cast<const v4u*>(xg), nbytes / 16,
-                                            [&](int64_t e, v4u v) { reinterpret_cast<v4u*>(xs)[e] = v; });
+            if (p.cols) {
+                if (p.dtype == SB_F64) {
+                    if (p.aligned) bat_cols<double, true>(p, rt, s, red);
+                    else bat_cols<double, false>(p, rt, s, red);
                 } else {
-                    stage_to_lds<kBatNT, 16>(reinterpret_cast<const uint32_t*>(xg), nbytes / 4,
-                                             [&](int64_t e, uint32_t v) { reinterpret_cast<uint32_t*>(xs)[e] = v; });
+                    if (p.aligned) bat_cols<float, true>(p, rt, s, red);
+                    else bat_cols<float, false>(p, rt, s, red);
                 }
-                __syncthreads();
-                cached_p = pi;
-                cached_s = s;
-            }
+            } else {
+                if (pi != cached_p || s != cached_s) {
+                    __syncthreads();  // every row of the previous tile has read x
+                    const int xs_size = p.dtype == SB_F64 ? 8 : 4;
+                    const unsigned char* xg = static_cast<const unsigned char*>(p.x) + k0 * xs_size;
+                    const int64_t nbytes = klen * xs_size;
+                    if (((reinterpret_cast<uintptr_t>(xg) | (uintptr_t)nbytes) & 15) == 0) {
+                        stage_to_lds<kBatNT, 8>(reinterpret_cast<const v4u*>(xg), nbytes / 16,
+                                                [&](int64_t e, v4u v) { reinterpret_cast<v4u*>(xs)[e] = v; });
+                    } else {
+                        stage_to_lds<kBatNT, 16>(reinterpret_cast<const uint32_t*>(xg), nbytes / 4,
+                                                 [&](int64_t e, uint32_t v) { reinterpret_cast<uint32_t*>(xs)[e] = v; });
+                    }
+                    __syncthreads();
+                    cached_p = pi;
+                    cached_s = s;
+                }
 
-            switch (p.dtype) {
-            case SB_F64:
-                if (p.aligned) bat_rows_g<SB_F64, true>(p, s, r0, r1, k0, klen, xs);
-                else bat_rows_g<SB_F64, false>(p, s, r0, r1, k0, klen, xs);
-                break;
-            case SB_F32:
-                if (p.aligned) bat_rows_g<SB_F32, true>(p, s, r0, r1, k0, klen, xs);
-                else bat_rows_g<SB_F32, false>(p, s, r0, r1, k0, klen, xs);
-                break;
-            case SB_BF16: bat_rows_g<SB_BF16, false>(p, s, r0, r1, k0, klen, xs); break;
-            default: bat_rows_g<SB_FP8_E4M3, false>(p, s, r0, r1, k0, klen, xs); break;
+                switch (p.dtype) {
+                case SB_F64:
+                    if (p.aligned) bat_rows_g<SB_F64, true>(p, s, r0, r1, k0, klen, xs);
+                    else bat_rows_g<SB_F64, false>(p, s, r0, r1, k0, klen, xs);
+                    break;
+                case SB_F32:
+                    if (p.aligned) bat_rows_g<SB_F32, true>(p, s, r0, r1, k0, klen, xs);
+                    else bat_rows_g<SB_F32, false>(p, s, r0, r1, k0, klen, xs);
+                    break;
+                case SB_BF16: bat_rows_g<SB_BF16, false>(p, s, r0, r1, k0, klen, xs); break;
+                default: bat_rows_g<SB_FP8_E4M3, false>(p, s, r0, r1, k0, klen, xs); break;
+                }
             }
+        }
+    }
+}
 
-            if (p.S > 1) {
-                // Publish this split's partials; the tile that completes the
-                // row tile adds all splits in order.
-                __threadfence();
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    last_flag = atomicAdd(&p.counters[rt], 1) == p.S - 1;
-                    // every split of this row tile has arrived: rearm the
-                    // counter so the same table can be launched again
-                    if (last_flag) atomicExch(&p.counters[rt], 0);
-                }
-                __syncthreads();
-                if (last_flag) {
-                    __threadfence();
-                    if (p.dtype == SB_F64) bat_finish<double>(p, r0, r1);
-                    else bat_finish<float>(p, r0, r1);
-                }
+// Second stage: each item's outputs get the partial sums of their problem's
+// splits added in split order, then the initial c (times the row's scale for
+// codes).  Reads only the table, so it can follow any batched launch; a
+// table without split problems has no items.
+__global__ __launch_bounds__(kBatNT) void gemv_batched_finish_kernel(const unsigned char* table)
+{
+    const BatHeader* hdr = reinterpret_cast<const BatHeader*>(table);
+    const BatProblem* probs = reinterpret_cast<const BatProblem*>(table + sizeof(BatHeader));
+    const BatItem* fin = reinterpret_cast<const BatItem*>(table + hdr->finish_off);
+    for (int64_t f = blockIdx.x; f < hdr->nfinish; f += gridDim.x) {
+        const BatItem it = fin[f];
+        const BatProblem& p = probs[it.problem];
+        const int64_t stride = p.cols ? p.n : p.m;  // outputs of the problem
+        for (int64_t o = it.first + threadIdx.x; o < it.first + it.count; o += kBatNT) {
+            if (p.dtype == SB_F64) {
+                double* c = static_cast<double*>(p.c);
+                c[o] = c[o] + ordered_split_sum(static_cast<const double*>(p.partial) + o, (int64_t)p.S, stride);
+            } else {
+                float* c = static_cast<float*>(p.c);
+                const float t = ordered_split_sum(static_cast<const float*>(p.partial) + o, (int64_t)p.S, stride);
+                if (p.dtype == SB_BF16 || p.dtype == SB_FP8_E4M3) c[o] = c[o] + p.scales[o] * t;
+                else c[o] = c[o] + t;
             }
         }
     }
@@ -271,10 +387,16 @@ static int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
 static int esize(int32_t dt) { return dt == SB_F64 ? 8 : dt == SB_F32 ? 4 : dt == SB_BF16 ? 2 : 1; }
 static int xsize(int32_t dt) { return dt == SB_F64 ? 8 : 4; }
+// Binary64/32 rows that all start on a 16-byte boundary (16-byte loads).
+static bool aligned_rows(int32_t dt, const void* A, int64_t lda)
+{
+    return (dt == SB_F64 || dt == SB_F32) && aligned16(A) && (lda * esize(dt)) % 16 == 0;
+}
 
-// Fill the automatic fields of one descriptor; false if it cannot be run.
-static bool resolve(const sb_gemv_desc& in, sb_gemv_desc& out, int64_t* KC, int64_t tile_bytes, char* why,
-                    size_t whylen)
+// Fill the automatic fields of a row-dot descriptor (in.m, in.n: the stored
+// rows and columns); false if it cannot be run.
+static bool resolve_rows(const sb_gemv_desc& in, sb_gemv_desc& out, int64_t* KC, int64_t tile_bytes, char* why,
+                         size_t whylen)
 {
     out = in;
     const int es = esize(in.dtype), xs = xsize(in.dtype);
@@ -321,12 +443,61 @@ static bool resolve(const sb_gemv_desc& in, sb_gemv_desc& out, int64_t* KC, int6
     return true;
 }
 
+// The same for a column-axpy descriptor (in.m stored rows of in.n columns):
+// rows_per_tile is the row chunk of a tile and split the number of chunks
+// (either may be given; 0 for both: about tile_bytes of A per tile).  *CW
+// receives the column block width.  group does not apply (0).
+static bool resolve_cols(const sb_gemv_desc& in, bool aligned, sb_gemv_desc& out, int64_t* CW, int64_t tile_bytes,
+                         char* why, size_t whylen)
+{
+    out = in;
+    if (in.split < 0 || in.group < 0 || in.rows_per_tile < 0) {
+        snprintf(why, whylen, "negative configuration value");
+        return false;
+    }
+    if (in.group != 0) {
+        snprintf(why, whylen, "group applies to row dots (row-major N, column-major T), not to column axpys");
+        return false;
+    }
+    const int es = esize(in.dtype);
+    const int64_t cw = (int64_t)kWave * (aligned ? 16 / es : 1);
+    const int64_t pass = (int64_t)kBatWaves * (aligned ? kBatUnrollT : 16 / es * kBatUnrollT);
+    const int64_t rows = std::max<int64_t>(in.m, 1);
+    int64_t RT = in.rows_per_tile;
+    if (RT == 0 && in.split > 0) {
+        RT = ceil_div(rows, in.split);
+    } else if (RT == 0) {
+        const int64_t row_bytes = std::min<int64_t>(cw, std::max<int64_t>(in.n, 1)) * es;
+        RT = std::max<int64_t>(pass, (tile_bytes / row_bytes) / pass * pass);
+        RT = std::min<int64_t>(RT, round_up(rows, pass));
+    }
+    if (RT > (1 << 30)) RT = 1 << 30;
+    const int64_t S = ceil_div(rows, RT);
+    if (in.rows_per_tile > 0 && in.split > 0 && in.split != S) {
+        snprintf(why, whylen, "split %d and rows_per_tile %d disagree (%lld chunks)", in.split, in.rows_per_tile,
+                 (long long)S);
+        return false;
+    }
+    if (S > (1 << 30)) {
+        snprintf(why, whylen, "too many row chunks");
+        return false;
+    }
+    out.group = 0;
+    out.rows_per_tile = (int32_t)RT;
+    out.split = (int32_t)S;
+    *CW = cw;
+    return true;
+}
+
 struct BatLayout {
-    std::vector<sb_gemv_desc> res;
-    std::vector<int64_t> kc, tiles, rtiles, tile_cost, counter_off, partial_off;
+    std::vector<sb_gemv_desc> res;  // the descriptors with their configuration resolved
+    std::vector<int64_t> rows, cols;  // the stored matrix
+    std::vector<int32_t> colform;     // 1: column axpy over the stored rows, 0: row dot
+    std::vector<int64_t> kc, tiles, rtiles, tile_cost, partial_off;
     std::vector<BatItem> items;
+    std::vector<BatItem> finish;  // second-stage items
     int32_t grid = 0;            // workgroups the items are dealt to
-    size_t image = 0, total = 0, items_off = 0, lists_off = 0;
+    size_t image = 0, total = 0, items_off = 0, lists_off = 0, finish_off = 0;
     int64_t ntiles = 0, total_cost = 0;
 };
 
@@ -337,20 +508,32 @@ static sb_status layout(const sb_gemv_desc* d, int32_t count, BatLayout& L, char
         return SB_EINVAL;
     }
     L.res.resize(count);
+    L.rows.resize(count);
+    L.cols.resize(count);
+    L.colform.resize(count);
     L.kc.resize(count);
     L.tiles.resize(count);
     L.rtiles.resize(count);
     L.tile_cost.resize(count);
-    L.counter_off.resize(count);
     L.partial_off.resize(count);
     // The rows of a tile never change a row's arithmetic, so results do not
     // depend on the tile size.
     const int64_t tile_bytes = kBatTileBytes;
     for (int32_t i = 0; i < count; ++i) {
         const sb_gemv_desc& in = d[i];
-        if (in.dtype < SB_F64 || in.dtype > SB_FP8_E4M3 || in.m < 0 || in.n < 0 || in.lda < std::max<int64_t>(1, in.n)) {
+        if ((in.layout != SB_ROW_MAJOR && in.layout != SB_COL_MAJOR) || (in.op != SB_N && in.op != SB_T)) {
+            snprintf(why, whylen, "descriptor %d: bad layout or op", i);
+            return SB_EINVAL;
+        }
+        const bool colmajor = in.layout == SB_COL_MAJOR;
+        const int64_t rows = colmajor ? in.n : in.m, cols = colmajor ? in.m : in.n;
+        if (in.dtype < SB_F64 || in.dtype > SB_FP8_E4M3 || in.m < 0 || in.n < 0 || in.lda < std::max<int64_t>(1, cols)) {
             snprintf(why, whylen, "descriptor %d: bad dtype, size or lda", i);
             return SB_EINVAL;
+        }
+        if ((in.dtype == SB_BF16 || in.dtype == SB_FP8_E4M3) && (colmajor || in.op != SB_N)) {
+            snprintf(why, whylen, "descriptor %d: quantised problems are row-major N (the scales belong to rows)", i);
+            return SB_EUNSUPPORTED;
         }
         if (in.m > 0 && in.n > 0 && (!in.A || !in.x || !in.c ||
                                      ((in.dtype == SB_BF16 || in.dtype == SB_FP8_E4M3) && !in.scales))) {
@@ -366,20 +549,36 @@ static sb_status layout(const sb_gemv_desc* d, int32_t count, BatLayout& L, char
             snprintf(why, whylen, "descriptor %d: size too large", i);
             return SB_EINVAL;
         }
+        // row-major N and column-major T are row dots over the stored rows;
+        // row-major T and column-major N are column axpys over them
+        const bool colform = colmajor == (in.op == SB_N);
+        L.rows[i] = rows;
+        L.cols[i] = cols;
+        L.colform[i] = colform;
+        sb_gemv_desc st = in;  // the stored form
+        st.m = rows;
+        st.n = cols;
+        const bool al = aligned_rows(in.dtype, in.A, in.lda);
         char sub[160];
-        if (!resolve(in, L.res[i], &L.kc[i], tile_bytes, sub, sizeof sub)) {
+        if (!(colform ? resolve_cols(st, al, L.res[i], &L.kc[i], tile_bytes, sub, sizeof sub)
+                      : resolve_rows(st, L.res[i], &L.kc[i], tile_bytes, sub, sizeof sub))) {
             snprintf(why, whylen, "descriptor %d: %s", i, sub);
             return SB_EINVAL;
         }
+        L.res[i].m = in.m;
+        L.res[i].n = in.n;
         const sb_gemv_desc& r = L.res[i];
-        const int64_t rt = (in.m == 0 || in.n == 0) ? 0 : ceil_div(in.m, r.rows_per_tile);
+        // output tiles: row tiles of a row dot, column blocks of a column axpy
+        const int64_t rt = (rows == 0 || cols == 0) ? 0 : colform ? ceil_div(cols, L.kc[i]) : ceil_div(rows, r.rows_per_tile);
         L.rtiles[i] = rt;
         L.tiles[i] = rt * r.split;
         L.ntiles += L.tiles[i];
         // tile cost: its bytes of A, the set-up and x staging, and one
         // memory latency per row pass
-        const int64_t a_bytes = (int64_t)r.rows_per_tile * std::min<int64_t>(L.kc[i], in.n) * es;
-        const int64_t passes = ceil_div(r.rows_per_tile, (int64_t)kBatWaves * (64 / r.group));
+        const int64_t a_bytes = (int64_t)r.rows_per_tile * std::min<int64_t>(L.kc[i], cols) * es;
+        const int64_t pass = colform ? (int64_t)kBatWaves * (al ? kBatUnrollT : 16 / es * kBatUnrollT)
+                                     : (int64_t)kBatWaves * (64 / r.group);
+        const int64_t passes = ceil_div(r.rows_per_tile, pass);
         L.tile_cost[i] = L.tiles[i] > 0 ? (a_bytes + SB_BAT_TILE_COST + passes * SB_BAT_PASS_COST + 1023) / 1024 : 0;
         L.total_cost += L.tile_cost[i] * L.tiles[i];
     }
@@ -404,20 +603,27 @@ static sb_status layout(const sb_gemv_desc* d, int32_t count, BatLayout& L, char
     off += L.items.size() * sizeof(BatItem);
     L.lists_off = off;
     off += (size_t)(L.grid + 1) * sizeof(int32_t);
+    // second stage: the outputs of every split problem, in chunks
     for (int32_t i = 0; i < count; ++i) {
-        L.counter_off[i] = -1;
-        if (L.res[i].split > 1 && L.rtiles[i] > 0) {
-            L.counter_off[i] = (int64_t)off;
-            off += (size_t)L.rtiles[i] * sizeof(int32_t);
+        if (L.res[i].split <= 1 || L.rtiles[i] == 0) continue;
+        const int64_t out_len = L.colform[i] ? L.cols[i] : L.rows[i];
+        for (int64_t first = 0; first < out_len; first += kFinishChunk)
+            L.finish.push_back(BatItem{i, (int32_t)std::min<int64_t>(kFinishChunk, out_len - first), first});
+        if (L.finish.size() > ((size_t)1 << 30)) {
+            snprintf(why, whylen, "too many outputs");
+            return SB_EINVAL;
         }
     }
+    L.finish_off = off;
+    off += L.finish.size() * sizeof(BatItem);
     L.image = round_up((int64_t)off, 64);
     size_t total = L.image;
     for (int32_t i = 0; i < count; ++i) {
         L.partial_off[i] = -1;
         if (L.res[i].split > 1 && L.rtiles[i] > 0) {
             L.partial_off[i] = (int64_t)total;
-            total += (size_t)round_up(L.res[i].split * d[i].m * xsize(d[i].dtype), 64);
+            const int64_t out_len = L.colform[i] ? L.cols[i] : L.rows[i];
+            total += (size_t)round_up(L.res[i].split * out_len * xsize(d[i].dtype), 64);
         }
     }
     L.total = total;
@@ -426,7 +632,8 @@ static sb_status layout(const sb_gemv_desc* d, int32_t count, BatLayout& L, char
     for (int32_t i = 0; i < count; ++i) {
         if (d[i].m > 0 && d[i].n > 0) {
             const uintptr_t lo = (uintptr_t)d[i].c;
-            cs.push_back({lo, lo + (uintptr_t)d[i].m * xsize(d[i].dtype)});
+            const int64_t out_len = L.colform[i] ? L.cols[i] : L.rows[i];
+            cs.push_back({lo, lo + (uintptr_t)out_len * xsize(d[i].dtype)});
         }
     }
     std::sort(cs.begin(), cs.end());
@@ -507,6 +714,9 @@ static void encode(const sb_gemv_desc* d, int32_t count, const BatLayout& L, uns
     hdr->items_off = (int64_t)L.items_off;
     hdr->lists_off = (int64_t)L.lists_off;
     hdr->grid = L.grid;
+    hdr->nfinish = (int32_t)L.finish.size();
+    hdr->finish_off = (int64_t)L.finish_off;
+    if (!L.finish.empty()) memcpy(image + L.finish_off, L.finish.data(), L.finish.size() * sizeof(BatItem));
     deal_items(L, reinterpret_cast<BatItem*>(image + L.items_off), reinterpret_cast<int32_t*>(image + L.lists_off));
     BatProblem* P = reinterpret_cast<BatProblem*>(image + sizeof(BatHeader));
     int64_t tile0 = 0, cost = 0;
@@ -517,8 +727,8 @@ static void encode(const sb_gemv_desc* d, int32_t count, const BatLayout& L, uns
         p.G = r.group;
         p.RT = r.rows_per_tile;
         p.S = r.split;
-        p.m = d[i].m;
-        p.n = d[i].n;
+        p.m = L.rows[i];
+        p.n = L.cols[i];
         p.lda = d[i].lda;
         p.KC = L.kc[i];
         p.tile0 = tile0;
@@ -531,9 +741,8 @@ static void encode(const sb_gemv_desc* d, int32_t count, const BatLayout& L, uns
         p.x = d[i].x;
         p.c = d[i].c;
         p.partial = L.partial_off[i] >= 0 ? dev_table + L.partial_off[i] : nullptr;
-        p.counters = L.counter_off[i] >= 0 ? reinterpret_cast<int32_t*>(dev_table + L.counter_off[i]) : nullptr;
-        const int es = esize(r.dtype);
-        p.aligned = (r.dtype == SB_F64 || r.dtype == SB_F32) && aligned16(d[i].A) && (d[i].lda * es) % 16 == 0;
+        p.aligned = aligned_rows(r.dtype, d[i].A, d[i].lda);
+        p.cols = L.colform[i];
         tile0 += L.tiles[i];
     }
     hdr->total_cost = cost;
@@ -578,15 +787,29 @@ sb_status sb_gemv_batched_encode(const sb_gemv_desc* descs, int32_t count, void*
     return SB_OK;
 }
 
+namespace sb {
+// The persistent kernel, then (finish_grid > 0) the second stage.
+static sb_status launch_batched(sb_handle* h, const void* dev_table, int grid, int finish_grid)
+{
+    hipLaunchKernelGGL(gemv_batched_kernel, dim3(grid), dim3(kBatNT), 0, h->stream,
+                       static_cast<const unsigned char*>(dev_table));
+    const sb_status st = check_launch(h, "gemv_batched_kernel");
+    if (st != SB_OK || finish_grid == 0) return st;
+    hipLaunchKernelGGL(gemv_batched_finish_kernel, dim3(finish_grid), dim3(kBatNT), 0, h->stream,
+                       static_cast<const unsigned char*>(dev_table));
+    return check_launch(h, "gemv_batched_finish_kernel");
+}
+static int finish_grid(size_t nfinish) { return (int)std::min<size_t>(nfinish, (size_t)kFinishGrid); }
+}  // namespace sb
+
 sb_status sb_gemv_batched_run(sb_handle* handle, const void* dev_table, int32_t grid)
 {
     if (!handle) return fail(nullptr, SB_EINVAL, "sb_gemv_batched_run: NULL handle");
     if (!dev_table || !sb::aligned16(dev_table)) return fail(handle, SB_EINVAL, "sb_gemv_batched_run: bad table");
     if (grid < 0 || grid > (1 << 20)) return fail(handle, SB_EINVAL, "sb_gemv_batched_run: bad grid %d", grid);
-    const int g = grid ? grid : sb::kBatGrid;
-    hipLaunchKernelGGL(sb::gemv_batched_kernel, dim3(g), dim3(sb::kBatNT), 0, handle->stream,
-                       static_cast<const unsigned char*>(dev_table));
-    return sb::check_launch(handle, "gemv_batched_kernel");
+    // The table may be rewritten between replays of a captured run, so the
+    // second stage is always launched (it returns at once without items).
+    return sb::launch_batched(handle, dev_table, grid ? grid : sb::kBatGrid, sb::kFinishGrid);
 }
 
 sb_status sb_gemv_batched(sb_handle* handle, const sb_gemv_desc* descs, int32_t count)
@@ -607,7 +830,7 @@ sb_status sb_gemv_batched(sb_handle* handle, const sb_gemv_desc* descs, int32_t 
         // so the local image may be released afterwards.
         const hipError_t e = hipMemcpyAsync(handle->ws, image.data(), L.image, hipMemcpyHostToDevice, handle->stream);
         if (e != hipSuccess) return fail(handle, SB_EDEVICE, "sb_gemv_batched: copy of the table: %s", hipGetErrorString(e));
-        return sb_gemv_batched_run(handle, handle->ws, 0);
+        return sb::launch_batched(handle, handle->ws, sb::kBatGrid, sb::finish_grid(L.finish.size()));
     } catch (...) {
         return fail(handle, SB_EINTERNAL, "sb_gemv_batched: unexpected C++ exception");
     }
@@ -622,6 +845,7 @@ struct sb_plan {
     void* table;
     uint64_t gen;
     int64_t ntiles;
+    int finish_grid;  // second-stage workgroups (0: no split problem)
 };
 
 extern "C" {
@@ -647,7 +871,8 @@ sb_status sb_plan_create(sb_handle* handle, const sb_gemv_desc* descs, int32_t c
             if (e != hipSuccess)
                 return fail(handle, SB_EDEVICE, "sb_plan_create: copy of the table: %s", hipGetErrorString(e));
         }
-        sb_plan* p = new (std::nothrow) sb_plan{handle, handle->ws, handle->ws_gen, L.ntiles};
+        sb_plan* p = new (std::nothrow) sb_plan{handle, handle->ws, handle->ws_gen, L.ntiles,
+                                                sb::finish_grid(L.finish.size())};
         if (!p) return fail(handle, SB_EINTERNAL, "sb_plan_create: out of host memory");
         *out = p;
         return SB_OK;
@@ -664,7 +889,7 @@ sb_status sb_plan_run(sb_plan* plan)
     if (h->ws != plan->table || h->ws_gen != plan->gen)
         return fail(h, SB_EINVAL, "sb_plan_run: the handle's workspace was replaced or written by a later call; "
                                   "create the plan again");
-    return sb_gemv_batched_run(h, plan->table, 0);
+    return sb::launch_batched(h, plan->table, sb::kBatGrid, plan->finish_grid);
 }
 
 sb_status sb_plan_destroy(sb_plan* plan)

@@ -211,10 +211,11 @@ class Stats:
 
 GEMV_DESC = np.dtype([("dtype", "<i4"), ("group", "<i4"), ("rows_per_tile", "<i4"), ("split", "<i4"),
                       ("m", "<i8"), ("n", "<i8"), ("lda", "<i8"),
-                      ("A", "<u8"), ("scales", "<u8"), ("x", "<u8"), ("c", "<u8")])
+                      ("A", "<u8"), ("scales", "<u8"), ("x", "<u8"), ("c", "<u8"),
+                      ("layout", "<i4"), ("op", "<i4")])
 GEN_DESC = np.dtype([("dtype", "<i4"), ("reserved", "<i4"), ("m", "<i8"), ("n", "<i8"), ("lda", "<i8"),
                      ("seed", "<u8"), ("A", "<u8"), ("scales", "<u8"), ("x", "<u8"), ("c", "<u8")])
-assert GEMV_DESC.itemsize == 72 and GEN_DESC.itemsize == 72
+assert GEMV_DESC.itemsize == 80 and GEN_DESC.itemsize == 72
 
 
 # ------------------------------------------------------------------ policy --

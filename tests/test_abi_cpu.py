@@ -223,11 +223,12 @@ def test_handle_errors(L):
     assert L.sb_handle_destroy(None) == 0
 
 
-def _desc(sbmod, dtype, m, n, A, c, x=X_, lda=None, scales=0, **cfg):
+def _desc(sbmod, dtype, m, n, A, c, x=X_, lda=None, scales=0, layout=0, op=0, **cfg):
     d = sbmod.sb_gemv_desc()
-    d.dtype, d.m, d.n, d.lda = dtype, m, n, lda or max(n, 1)
+    d.dtype, d.m, d.n, d.lda = dtype, m, n, lda or max(n if layout == 0 else m, 1)
     d.A, d.x, d.c, d.scales = A, x, c, scales or None
     d.group, d.rows_per_tile, d.split = cfg.get("group", 0), cfg.get("rows_per_tile", 0), cfg.get("split", 0)
+    d.layout, d.op = layout, op
     return d
 
 
@@ -412,3 +413,94 @@ def test_stream_update_validation(L, h):
     assert L.sb_stream_update(h, C + 4, 4, 4, 4) == -1      # not 8-byte aligned
     assert L.sb_stream_update(h, None, 4, 4, 4) == -1
     assert L.sb_stream_update(h, None, 0, 4, 4) == 0        # empty: nothing launched
+
+
+def test_batched_layouts_resolve_and_encode_on_host(L):
+    """(row-major, T) and (column-major, N) are column axpys over the stored
+    rows, (column-major, T) a row dot: the records carry the stored shape,
+    the form, column blocks of one wave's width and the row chunking."""
+    import struct
+
+    import paper_2108_02025_amd as sb
+    arr = (sb.sb_gemv_desc * 4)()
+    arr[0] = _desc(sb, 1, 1000, 3000, A_, C_, layout=0, op=1)                        # 1000 stored rows of 3000
+    arr[1] = _desc(sb, 0, 3000, 70, A_ + (1 << 30), C_ + (1 << 20), layout=1, op=0)  # 70 stored rows of 3000
+    arr[2] = _desc(sb, 1, 500, 20000, A_ + (2 << 30), C_ + (2 << 20), layout=1, op=1)  # row dot, 20000 rows of 500
+    arr[3] = _desc(sb, 1, 1000, 3001, A_ + (3 << 30), C_ + (3 << 20), layout=0, op=1, rows_per_tile=100)
+    out = (sb.sb_gemv_desc * 4)()
+    assert L.sb_gemv_batched_resolve(arr, 4, out) == 0
+    # binary32, 16-byte rows: 256-column blocks, 32 rows a pass, 256 KiB tiles
+    assert (out[0].group, out[0].rows_per_tile, out[0].split) == (0, 256, 4)
+    assert (out[1].group, out[1].rows_per_tile, out[1].split) == (0, 96, 1)      # binary64: 128 columns, 70 rows
+    assert out[2].group in (4, 8, 16, 32, 64) and out[2].split == 1
+    assert (out[3].group, out[3].rows_per_tile, out[3].split) == (0, 100, 10)    # rows of 3001 floats: unaligned
+    assert all((out[k].m, out[k].n, out[k].layout, out[k].op) == (arr[k].m, arr[k].n, arr[k].layout, arr[k].op)
+               for k in range(4))
+    img = ctypes.c_size_t(0)
+    total = L.sb_gemv_batched_table_bytes(arr, 4, ctypes.byref(img))
+    buf = (ctypes.c_ubyte * img.value)()
+    assert L.sb_gemv_batched_encode(arr, 4, ctypes.c_void_p(1 << 44), buf, img.value) == 0
+    want = [  # stored rows, stored columns, block or chunk width, output tiles, aligned, column form
+        (1000, 3000, 256, 12, 1, 1), (70, 3000, 128, 24, 1, 1), (20000, 500, None, None, 1, 0),
+        (1000, 3001, 64, 47, 0, 1)]
+    ntiles = 0
+    for k, (rows, cols, kc, rt, al, form) in enumerate(want):
+        rec = 64 + 144 * k
+        dtype, G, RT, S = struct.unpack_from("<iiii", buf, rec)
+        m, n, lda, KC, tile0, rtiles = struct.unpack_from("<qqqqqq", buf, rec + 16)
+        aligned, colform = struct.unpack_from("<ii", buf, rec + 128)
+        assert (m, n, aligned, colform) == (rows, cols, al, form)
+        assert (RT, S) == (out[k].rows_per_tile, out[k].split)
+        if form:
+            assert (KC, rtiles) == (kc, rt)
+        else:
+            assert rtiles == -(-rows // RT)
+        ntiles += rtiles * S
+    assert struct.unpack_from("<q", buf, 8)[0] == ntiles
+    # partial sums of the split column axpys: S x (output columns) each
+    assert total - img.value >= 4 * 3000 * 4 + 10 * 3001 * 4
+    # second-stage items: the outputs of each split problem once, 1024 at a time
+    nfinish, finish_off = struct.unpack_from("<iq", buf, 52)
+    covered = {}
+    for j in range(nfinish):
+        prob, cnt, first = struct.unpack_from("<iiq", buf, finish_off + 16 * j)
+        assert 1 <= cnt <= 1024 and first % 1024 == 0
+        covered.setdefault(prob, []).append((first, cnt))
+    assert sorted(covered) == [0, 3]                      # the problems with split > 1
+    for prob, out_len in ((0, 3000), (3, 3001)):
+        spans = sorted(covered[prob])
+        assert spans[0][0] == 0 and sum(c for _, c in spans) == out_len
+        assert all(a + c == b for (a, c), (b, _) in zip(spans, spans[1:]))
+
+
+def test_batched_descriptor_mirrors_agree():
+    """The serving loop's numpy descriptor and the ctypes one have the C
+    struct's layout (80 bytes, checked by a static assertion in the library)."""
+    import paper_2108_02025_amd as sb
+    from paper_2108_02025_amd.serve import GEMV_DESC
+    assert ctypes.sizeof(sb.sb_gemv_desc) == GEMV_DESC.itemsize == 80
+    for name, *_ in sb.sb_gemv_desc._fields_:
+        assert getattr(sb.sb_gemv_desc, name).offset == GEMV_DESC.fields[name][1], name
+
+
+def test_batched_layout_validation(L):
+    import paper_2108_02025_amd as sb
+    bad = [
+        (_desc(sb, 1, 10, 10, A_, C_, layout=2), -1),                          # bad layout
+        (_desc(sb, 1, 10, 10, A_, C_, op=5), -1),                              # bad op
+        (_desc(sb, 1, 10, 20, A_, C_, layout=1, lda=5), -1),                   # column-major lda < m
+        (_desc(sb, 1, 10, 10, A_, C_, op=1, group=8), -1),                     # group on a column axpy
+        (_desc(sb, 1, 1000, 10, A_, C_, op=1, rows_per_tile=100, split=3), -1),  # chunking disagrees
+        (_desc(sb, 2, 10, 10, A_, C_, scales=X_, op=1), -4),                   # codes: row-major N only
+        (_desc(sb, 3, 10, 10, A_, C_, scales=X_, layout=1), -4),
+    ]
+    for d, st in bad:
+        arr = (sb.sb_gemv_desc * 1)(d)
+        assert L.sb_gemv_batched_table_bytes(arr, 1, None) == (1 << 64) - 1
+        assert L.sb_gemv_batched_resolve(arr, 1, (sb.sb_gemv_desc * 1)()) == st
+    # a column axpy's output has n entries: 10 x 100 row-major T writes 400 bytes
+    two = (sb.sb_gemv_desc * 2)(_desc(sb, 1, 10, 100, A_, C_, op=1), _desc(sb, 1, 10, 10, A_, C_ + 200))
+    assert L.sb_gemv_batched_resolve(two, 2, (sb.sb_gemv_desc * 2)()) == -1
+    assert b"overlap" in L.sb_last_error(None)
+    ok = (sb.sb_gemv_desc * 2)(_desc(sb, 1, 10, 100, A_, C_, op=1), _desc(sb, 1, 10, 10, A_, C_ + 400))
+    assert L.sb_gemv_batched_resolve(ok, 2, (sb.sb_gemv_desc * 2)()) == 0

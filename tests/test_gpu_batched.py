@@ -7,7 +7,7 @@ import torch
 
 import oracle
 import workloads
-from gpu_util import U32, U64, assert_within, dev, gemv_bound, host
+from gpu_util import U32, U64, assert_within, dev, gamma, gemv_bound, host
 
 pytestmark = pytest.mark.gpu
 
@@ -49,7 +49,7 @@ def oracle_check(P, H):
 def fresh_copy(sb, P, H):
     """The same problem with its own output vector reset to c0."""
     return sb.GemvProblem(P.A, P.x, dev(H["c0"]), scales=P.scales, q=P.q, group=P.group,
-                          rows_per_tile=P.rows_per_tile, split=P.split)
+                          rows_per_tile=P.rows_per_tile, split=P.split, op=P.op)
 
 
 def test_batched_random_mix_alone_vs_mix(sb):
@@ -250,3 +250,122 @@ def test_plan_invalidated_by_workspace_writes(sb):
     finally:
         L.sb_plan_destroy(p)
         L.sb_handle_destroy(h)
+
+
+# ----------------------------------------------------- layouts and ops ----
+# (row-major, N) and (column-major, T) are row dots over the stored rows;
+# (row-major, T) and (column-major, N) are column axpys over them.
+
+LAYOUT_OPS = [(0, 0), (1, 1), (0, 1), (1, 0)]
+
+
+def stored(A, layout, pad=0):
+    """Device tensor of logical shape A.shape stored row- or column-major,
+    each stored row followed by `pad` NaN elements (so a read outside the
+    matrix would poison the result, and pad > 0 moves the rows off 16-byte
+    alignment)."""
+    S = A if layout == 0 else A.T
+    buf = np.full((S.shape[0], S.shape[1] + pad), np.nan, dtype=A.dtype)
+    buf[:, :S.shape[1]] = S
+    d = dev(buf)[:, :S.shape[1]]
+    return d if layout == 0 else d.t()
+
+
+def test_batched_layouts_and_ops_mix(sb):
+    """Every (layout, op) pair in binary64 and binary32, with aligned and
+    unaligned stored rows and edge shapes, in one batch: each problem within
+    the summation bound of the oracle, and alone gives the bits it gave in
+    the mix."""
+    shapes = [(1, 1), (1, 300), (300, 1), (37, 1000), (1000, 37), (257, 513), (2048, 3000), (5, 20000),
+              (20000, 5)]
+    probs, hosts = [], []
+    k = 0
+    for kind, npd, u in (("f64", np.float64, U64), ("f32", np.float32, U32)):
+        for m, n in shapes:
+            for layout, op in LAYOUT_OPS:
+                A, x, c0 = workloads.gemv_inputs(m, n, seed=2000 + k, dist="normal", op_t=bool(op), dtype=npd)
+                P = sb.GemvProblem(stored(A, layout, pad=k % 3), dev(x), dev(c0), op=op)
+                probs.append(P)
+                hosts.append(dict(A=A, x=x, c0=c0, op=op, u=u, what=f"{kind} {m}x{n} layout {layout} op {op}"))
+                k += 1
+    sb.sb_gemv_batched(probs)
+    mix = [host(P.c).copy() for P in probs]
+    for P, H, got in zip(probs, hosts, mix):
+        m, n = H["A"].shape
+        ref = oracle.gemv(H["A"], H["x"], H["c0"], op=H["op"])
+        K = n if H["op"] == 0 else m
+        assert_within(got, ref, gemv_bound(H["A"], H["x"], H["c0"], H["op"], K, H["u"]), H["what"])
+        alone = fresh_copy(sb, P, H)
+        sb.sb_gemv_batched([alone])
+        assert np.array_equal(host(alone.c), got), "alone differs from mix: " + H["what"]
+
+
+@pytest.mark.parametrize("cfg", [dict(rows_per_tile=1), dict(rows_per_tile=7), dict(split=3), dict(split=1),
+                                 dict(rows_per_tile=200, split=5)])
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+def test_batched_column_axpy_chunks_exact_and_table_reuse(sb, kind, cfg):
+    """Column axpys with explicit row chunking on integer data (every sum
+    exact): the oracle's bits, and a table launched twice adds op(A) x
+    twice (the chunk counters re-arm themselves)."""
+    npd = np.float64 if kind == "f64" else np.float32
+    probs, refs = [], []
+    for i, (m, n, layout, pad) in enumerate([(1000, 300, 0, 0), (999, 1001, 0, 1), (300, 1000, 1, 0),
+                                             (1001, 999, 1, 3), (1, 70, 0, 0)]):
+        op = 1 if layout == 0 else 0      # the column-axpy pairs
+        rows = m if layout == 0 else n    # stored rows
+        if cfg.get("rows_per_tile") and cfg.get("split") and -(-rows // cfg["rows_per_tile"]) != cfg["split"]:
+            continue                      # chunking that disagrees is rejected (CPU test)
+        A, x, c0 = workloads.gemv_inputs(m, n, seed=40 + i, dist="int8" if kind == "f64" else "int7",
+                                         op_t=bool(op), dtype=npd)
+        P = sb.GemvProblem(stored(A, layout, pad), dev(x), dev(c0), op=op, **cfg)
+        probs.append(P)
+        r = oracle.gemv(A, x, c0, op=op)
+        refs.append((r, c0 + 2 * (r - c0)))
+    for P, r in zip(probs, sb.sb_gemv_batched_resolve(probs)):
+        assert r["group"] == 0
+        if cfg.get("rows_per_tile"):
+            assert r["rows_per_tile"] == cfg["rows_per_tile"]
+    table = sb.BatchTable(sb.sb_gemv_batched_table_bytes(probs)[0])
+    table.encode(probs)
+    table.run()
+    torch.cuda.synchronize()
+    for P, (once, _) in zip(probs, refs):
+        assert np.array_equal(host(P.c), once)
+    table.run()
+    for P, (_, twice) in zip(probs, refs):
+        assert np.array_equal(host(P.c), twice)
+
+
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+def test_batched_same_buffer_pairs_bitwise(sb, kind):
+    """On one buffer, (row-major, T) and (column-major, N) are the same
+    computation and give the same bits; so are (row-major, N) and
+    (column-major, T); the batch matches the single-call sb_gemv to the
+    summation bound."""
+    npd, u = (np.float64, U64) if kind == "f64" else (np.float32, U32)
+    m, n = 777, 1531
+    A, _, _ = workloads.gemv_inputs(m, n, seed=5, dist="normal", dtype=npd)
+    buf = dev(A)
+    colview = buf.reshape(-1).as_strided((n, m), (1, n))     # the same memory as an n x m column-major matrix
+    xm = dev(workloads.gemv_inputs(m, 1, seed=6, dtype=npd)[0].reshape(-1))
+    xn = dev(workloads.gemv_inputs(n, 1, seed=7, dtype=npd)[0].reshape(-1))
+    cm = [dev(np.zeros(m, npd)) for _ in range(2)]
+    cn = [dev(np.zeros(n, npd)) for _ in range(2)]
+    sb.sb_gemv_batched([sb.GemvProblem(buf, xm, cn[0], op=1), sb.GemvProblem(colview, xm, cn[1], op=0),
+                        sb.GemvProblem(buf, xn, cm[0], op=0), sb.GemvProblem(colview, xn, cm[1], op=1)])
+    assert torch.equal(cn[0], cn[1]) and torch.equal(cm[0], cm[1])
+    Ah = A.astype(np.float64)
+    for got, ref, bnd in ((cn[0], Ah.T @ host(xm), 2 * gamma(m + 1, u) * (np.abs(Ah).T @ np.abs(host(xm)))),
+                          (cm[0], Ah @ host(xn), 2 * gamma(n + 1, u) * (np.abs(Ah) @ np.abs(host(xn))))):
+        assert np.all(np.abs(host(got) - ref) <= bnd + 1e-300)
+
+
+def test_batched_quantised_layouts_rejected(sb):
+    codes = torch.zeros((10, 10), dtype=torch.int16, device="cuda")
+    s = torch.ones(10, dtype=torch.float32, device="cuda")
+    x = torch.zeros(10, dtype=torch.float32, device="cuda")
+    c = torch.zeros(10, dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        sb.make_descs([sb.GemvProblem(codes, x, c, scales=s, q=sb.SB_BF16, op=sb.SB_T)])
+    with pytest.raises(ValueError):
+        sb.make_descs([sb.GemvProblem(codes.t(), x, c, scales=s, q=sb.SB_BF16)])
