@@ -16,7 +16,10 @@
 //    wave-uniform, partial column sums are combined across waves in LDS in
 //    wave order.  This is Algorithm 1's micro-kernel shape (a contiguous
 //    segment of the output updated over a block of the reduction index).
-//    Used for row-major T and column-major N.
+//    Used for row-major T and column-major N.  Rows that are not 16-byte
+//    aligned: gemv_t_phase_kernel (binary32: the same 16-byte loads, one
+//    accumulator set per row phase) or gemv_t_elem_kernel (binary64:
+//    element loads).
 //
 // Splits (of columns for row-dot, of rows for col-axpy) write partial sums
 // to the workspace and a second kernel adds them in split order (above 32
@@ -25,6 +28,7 @@
 // the summation order depends only on the shape, so results are
 // reproducible bit for bit.
 #include <algorithm>
+#include <type_traits>
 
 #include "sb_device.hpp"
 #include "sb_internal.hpp"
@@ -231,6 +235,125 @@ __global__ __launch_bounds__(NT) void gemv_t_kernel(GemvTArgs<T> a)
             if (j < a.cols) {
                 if (a.partial) a.partial[s * a.cols + j] = t;
                 else a.c[j] = a.c[j] + t;
+            }
+        }
+    }
+}
+
+// Column-axpy for binary32 rows that are not 16-byte aligned, with the
+// aligned kernel's 16-byte loads, column blocks and row splits.  Row i
+// starts r_i elements past a 16-byte boundary (r_i < W, the same for the
+// whole row), so the vector at index v of the row's aligned grid holds
+// columns W*v - r_i + q (q < W): lane l's vector (v = 64*b + l in column
+// block b) holds W - r_i of the lane's own columns and r_i of lane l - 1's.
+// Each lane adds its vector's products into one of W accumulator sets,
+// chosen by the row's phase r_i, and the columns are put together once,
+// after the rows: lane l's column W*v + t takes, phase by phase, set r's
+// position t + r if that is below W, else position t + r - W of lane
+// l + 1's set r.  The last lane also loads the vector after its own (rows
+// with r_i > 0) into a set of its own, whose first r_i positions close the
+// block.  A column's sum is the sum over phases, in phase order, of its
+// rows' products in row order per wave; then the waves in order, as in the
+// aligned kernel.  Every loaded vector holds at least one column of its row
+// (so it lies in a page of the matrix); elements outside the block's
+// columns fall into positions that are dropped.  (Binary64 rows, two
+// phases, run faster with element loads.)
+#ifndef SB_GEMV_T_PHASE
+#define SB_GEMV_T_PHASE 1
+#endif
+template <typename T>
+__global__ __launch_bounds__(256) void gemv_t_phase_kernel(GemvTArgs<T> a)
+{
+    constexpr int W = Vec<T>::W;
+    typedef typename Vec<T>::type V;
+    constexpr int U = kUnrollT;
+    constexpr int NW = 256 / kWave;
+    constexpr int CW = kWave * W;
+    __shared__ T red[NW][CW];
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const bool last = lane == kWave - 1;
+    const int64_t v = (int64_t)blockIdx.x * kWave + lane;  // this lane's vector of each row
+    const int64_t s = blockIdx.y;
+    const int64_t i0 = s * a.RS, i1 = min(a.rows, i0 + a.RS);
+
+    T acc[W][W], ext[W][W];
+#pragma unroll
+    for (int r = 0; r < W; ++r) {
+#pragma unroll
+        for (int q = 0; q < W; ++q) acc[r][q] = ext[r][q] = 0;
+    }
+    // Loads of row i: the lane's vector (if it holds a column of the row)
+    // and, for the last lane, the next one.
+    auto load_row = [&](int64_t i, V& av, V& ev) -> int {
+        const T* p = a.A + i * a.ld;
+        const int r = __builtin_amdgcn_readfirstlane((int)((reinterpret_cast<uintptr_t>(p) & 15) / sizeof(T)));
+        const V* b = reinterpret_cast<const V*>(p - r);
+        av = v * W - r < a.cols ? ld_stream<kGemvNT>(b + v) : (V)0;
+        ev = (last && r > 0 && (v + 1) * W - r < a.cols) ? ld_stream<kGemvNT>(b + v + 1) : (V)0;
+        return r;
+    };
+    auto add_row = [&](int r, const V& av, const V& ev, T xv) {
+#pragma unroll
+        for (int ph = 0; ph < W; ++ph) {
+            if (r == ph) {
+#pragma unroll
+                for (int q = 0; q < W; ++q) acc[ph][q] += av[q] * xv;
+#pragma unroll
+                for (int q = 0; q < ph; ++q) ext[ph][q] += ev[q] * xv;
+            }
+        }
+    };
+
+    int64_t i = i0 + w;
+    for (; i + (U - 1) * NW < i1; i += U * NW) {
+        V av[U], ev[U];
+        T xv[U];
+        int rr[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            rr[u] = load_row(i + u * NW, av[u], ev[u]);
+            xv[u] = a.x[i + u * NW];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) add_row(rr[u], av[u], ev[u], xv[u]);
+    }
+    for (; i < i1; i += NW) {
+        V av, ev;
+        const int r = load_row(i, av, ev);
+        add_row(r, av, ev, a.x[i]);
+    }
+
+    // Put the columns together: phase by phase, in phase order.
+    T tot[W];
+#pragma unroll
+    for (int ph = 0; ph < W; ++ph) {
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+            T part;
+            if (t + ph < W) {
+                part = acc[ph][t + ph];
+            } else {
+                const T nb = __shfl_down(acc[ph][t + ph - W], 1);
+                part = last ? ext[ph][t + ph - W] : nb;
+            }
+            tot[t] = ph == 0 ? part : tot[t] + part;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < W; ++t) red[w][lane * W + t] = tot[t];
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+            T sum = red[0][lane * W + t];
+#pragma unroll
+            for (int k = 1; k < NW; ++k) sum += red[k][lane * W + t];
+            const int64_t j = v * W + t;
+            if (j < a.cols) {
+                if (a.partial) a.partial[s * a.cols + j] = sum;
+                else a.c[j] = a.c[j] + sum;
             }
         }
     }
@@ -462,7 +585,12 @@ static sb_status gemv_t_typed(sb_handle* h, int64_t rows, int64_t cols, const T*
     const bool al = aligned16(A) && ((ld * (int64_t)sizeof(T)) % 16 == 0);
     const int64_t CW = 64 * (al ? 16 / (int64_t)sizeof(T) : 1);
     const dim3 grid((unsigned)ceil_div(cols, CW), (unsigned)p.nsplit);
-    if (!al && p.NT == 256) {
+    constexpr bool kPhaseForm = std::is_same<T, float>::value && SB_GEMV_T_PHASE;
+    if (kPhaseForm && !al && p.NT == 256) {
+        if constexpr (kPhaseForm)
+            hipLaunchKernelGGL(gemv_t_phase_kernel<T>, dim3((unsigned)ceil_div(cols, 64 * 4), (unsigned)p.nsplit),
+                               dim3(256), 0, h->stream, a);
+    } else if (!al && p.NT == 256) {
         GemvTElemArgs<T> e{rows, cols, ld, A, x, c, a.partial, p.RS};
         hipLaunchKernelGGL(gemv_t_elem_kernel<T>, dim3((unsigned)ceil_div(cols, 256), (unsigned)p.nsplit), dim3(256),
                            0, h->stream, e);
