@@ -84,10 +84,16 @@ struct GemvNArgs {
     int64_t RB;
 };
 
-template <typename T, int G, int NT, bool ALIGNED, int U = kUnrollN>
+// SHIFT (rows not 16-byte aligned, x small enough): LDS holds W copies of
+// the x chunk, copy h shifted left by h elements, KC elements apart, and a
+// row whose first 16-byte boundary is h elements in reads copy h as
+// aligned vectors (otherwise it reads x one element at a time: four LDS
+// reads instead of one per binary32 vector).  Same arithmetic either way.
+template <typename T, int G, int NT, bool ALIGNED, int U = kUnrollN, bool SHIFT = false>
 __global__ __launch_bounds__(NT) void gemv_n_kernel(GemvNArgs<T> a)
 {
     constexpr int NW = NT / kWave, GW = kWave / G;
+    constexpr int W = Vec<T>::W;
     extern __shared__ __align__(16) unsigned char smem[];
     T* xs = reinterpret_cast<T*>(smem);
 
@@ -96,7 +102,15 @@ __global__ __launch_bounds__(NT) void gemv_n_kernel(GemvNArgs<T> a)
     const int64_t klen = min(a.cols, k0 + a.KC) - k0;
 
     // Stage x[k0, k0 + klen) in LDS (read by every row of this workgroup).
-    stage_to_lds<NT>(a.x + k0, klen, [&](int64_t t, T v) { xs[t] = v; });
+    if constexpr (SHIFT) {
+        stage_to_lds<NT>(a.x + k0, klen, [&](int64_t t, T v) {
+#pragma unroll
+            for (int h = 0; h < W; ++h)
+                if (t >= h) xs[h * a.KC + t - h] = v;
+        });
+    } else {
+        stage_to_lds<NT>(a.x + k0, klen, [&](int64_t t, T v) { xs[t] = v; });
+    }
     __syncthreads();
 
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -105,7 +119,7 @@ __global__ __launch_bounds__(NT) void gemv_n_kernel(GemvNArgs<T> a)
     const int64_t r1 = min(a.rows, r0 + a.RB);
 
     for (int64_t row = r0 + w * GW + g; row < r1; row += NW * GW) {
-        T t = row_dot<T, G, U, ALIGNED, kGemvNT>(a.A + row * a.ld + k0, klen, xs, l);
+        T t = row_dot<T, G, U, ALIGNED, kGemvNT, true, SHIFT>(a.A + row * a.ld + k0, klen, xs, l, a.KC);
         t = group_sum<G>(t);
         if (l == 0) {
             if (a.partial) a.partial[s * a.rows + row] = t;
@@ -413,12 +427,16 @@ constexpr int64_t kLdsPerCU = 160 * 1024;      // gfx950 LDS per compute unit
 constexpr int64_t kMaxStagedX = 128 * 1024;    // x bytes staged whole before splitting
 constexpr int64_t kSplitChunkBytes = 32 * 1024;
 constexpr int64_t kSplitFloorBytes = 16 * 1024;  // smallest chunk the few-rows split goes down to
+#ifndef SB_GEMV_N_SHIFTED_X_BYTES
+#define SB_GEMV_N_SHIFTED_X_BYTES (80 * 1024)
+#endif
+constexpr int64_t kShiftedXBytes = SB_GEMV_N_SHIFTED_X_BYTES;  // LDS for shifted x copies (0: never)
 
 // Launch shape for a column chunk of KC elements (nsplit chunks per row).
 static void shape_gemv_n(GemvNPlan& p, int esize, int64_t rows)
 {
     const int W = 16 / esize;
-    p.lds = (size_t)round_up(p.KC * esize, 16);
+    p.lds = (size_t)p.xcopies * (size_t)round_up(p.KC * esize, 16);
     p.NT = p.lds > 80 * 1024 ? SB_GEMV_N_NT_HUGE : (p.lds > 40 * 1024 ? 512 : 256);
     const int64_t waves_per_block = p.NT / 64;
     const int64_t bpc = std::max<int64_t>(1, std::min<int64_t>(kLdsPerCU / (int64_t)p.lds,
@@ -433,9 +451,10 @@ static void shape_gemv_n(GemvNPlan& p, int esize, int64_t rows)
     p.RB = round_up(std::max<int64_t>(1, ceil_div(rows, row_blocks)), pass);
 }
 
-GemvNPlan plan_gemv_n(int esize, int64_t rows, int64_t cols)
+GemvNPlan plan_gemv_n(int esize, int64_t rows, int64_t cols, bool unaligned)
 {
     GemvNPlan p{};
+    p.xcopies = 1;
     const int W = 16 / esize;
     if (cols * esize <= kMaxStagedX) {
         p.nsplit = 1;
@@ -455,6 +474,12 @@ GemvNPlan plan_gemv_n(int esize, int64_t rows, int64_t cols)
             p.nsplit = ceil_div(cols, p.KC);
             shape_gemv_n(p, esize, rows);
         }
+    }
+    // Rows not 16-byte aligned: shifted copies of x when W of them fit
+    // kShiftedXBytes of LDS (x read as vectors; at most about 20 KiB of x).
+    if (unaligned && p.nsplit == 1 && W * round_up(p.KC * esize, 16) <= kShiftedXBytes) {
+        p.xcopies = W;
+        shape_gemv_n(p, esize, rows);
     }
     p.ws = p.nsplit > 1 ? (size_t)(p.nsplit * rows * esize) : 0;
     return p;
@@ -497,38 +522,37 @@ GemvTPlan plan_gemv_t(int esize, int64_t rows, int64_t cols, int64_t small_split
 
 // ------------------------------------------------------------- launchers ---
 
-template <typename T, int G, int NT, bool AL, int U = kUnrollN>
+template <typename T, int G, int NT, bool AL, int U = kUnrollN, bool SH = false>
 static void launch_n(const GemvNArgs<T>& a, dim3 grid, size_t lds, hipStream_t st)
 {
     static const bool attr_set = [] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemv_n_kernel<T, G, NT, AL, U>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemv_n_kernel<T, G, NT, AL, U, SH>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsPerCU);
         return true;
     }();
     (void)attr_set;
-    hipLaunchKernelGGL((gemv_n_kernel<T, G, NT, AL, U>), grid, dim3(NT), lds, st, a);
+    hipLaunchKernelGGL((gemv_n_kernel<T, G, NT, AL, U, SH>), grid, dim3(NT), lds, st, a);
 }
 
-template <typename T, int NT, bool AL>
+template <typename T, int NT, bool AL, bool SH>
 static bool dispatch_n_g(int G, const GemvNArgs<T>& a, dim3 grid, size_t lds, hipStream_t st)
 {
     switch (G) {
-    case 4: launch_n<T, 4, NT, AL>(a, grid, lds, st); return true;
-    case 8: launch_n<T, 8, NT, AL>(a, grid, lds, st); return true;
-    case 16: launch_n<T, 16, NT, AL>(a, grid, lds, st); return true;
-    case 32: launch_n<T, 32, NT, AL>(a, grid, lds, st); return true;
-    case 64: launch_n<T, 64, NT, AL>(a, grid, lds, st); return true;
+    case 4: launch_n<T, 4, NT, AL, kUnrollN, SH>(a, grid, lds, st); return true;
+    case 8: launch_n<T, 8, NT, AL, kUnrollN, SH>(a, grid, lds, st); return true;
+    case 16: launch_n<T, 16, NT, AL, kUnrollN, SH>(a, grid, lds, st); return true;
+    case 32: launch_n<T, 32, NT, AL, kUnrollN, SH>(a, grid, lds, st); return true;
+    case 64: launch_n<T, 64, NT, AL, kUnrollN, SH>(a, grid, lds, st); return true;
     }
     return false;
 }
 
-template <typename T, bool AL>
+template <typename T, bool AL, bool SH = false>
 static bool dispatch_n(int NT, int G, const GemvNArgs<T>& a, dim3 grid, size_t lds, hipStream_t st)
 {
-    switch (NT) {
-    case 256: return dispatch_n_g<T, 256, AL>(G, a, grid, lds, st);
-    case 512: return dispatch_n_g<T, 512, AL>(G, a, grid, lds, st);
-    case 1024: return dispatch_n_g<T, 1024, AL>(G, a, grid, lds, st);
+    switch (NT) {  // the shapes shape_gemv_n picks (SB_GEMV_N_NT_HUGE goes through launch_n)
+    case 256: return dispatch_n_g<T, 256, AL, SH>(G, a, grid, lds, st);
+    case 512: return dispatch_n_g<T, 512, AL, SH>(G, a, grid, lds, st);
     }
     return false;
 }
@@ -549,20 +573,22 @@ template <typename T>
 static sb_status gemv_n_typed(sb_handle* h, int64_t rows, int64_t cols, const T* A, int64_t ld,
                               const T* x, T* c)
 {
-    const GemvNPlan p = plan_gemv_n(sizeof(T), rows, cols);
+    const bool al = aligned16(A) && ((ld * (int64_t)sizeof(T)) % 16 == 0);
+    const GemvNPlan p = plan_gemv_n(sizeof(T), rows, cols, !al);
     if (p.ws > h->ws_bytes)
         return fail(h, SB_ENOMEM, "gemv needs %zu workspace bytes, handle has %zu", p.ws, h->ws_bytes);
     if (p.nsplit > 65535)
         return fail(h, SB_EUNSUPPORTED, "gemv: rows of %lld elements need %lld column splits (at most 65535)",
                     (long long)cols, (long long)p.nsplit);
     GemvNArgs<T> a{rows, cols, ld, A, x, c, p.nsplit > 1 ? static_cast<T*>(claim_ws(h)) : nullptr, p.KC, p.RB};
-    const bool al = aligned16(A) && ((ld * (int64_t)sizeof(T)) % 16 == 0);
     const dim3 grid((unsigned)ceil_div(rows, p.RB), (unsigned)p.nsplit);
     bool ok = true;
     if (p.lds > 80 * 1024 && p.NT == SB_GEMV_N_NT_HUGE && p.G == 64) {
         // whole rows with x above 80 KiB: more loads in flight per lane
         if (al) launch_n<T, 64, SB_GEMV_N_NT_HUGE, true, kUnrollNHuge>(a, grid, p.lds, h->stream);
         else launch_n<T, 64, SB_GEMV_N_NT_HUGE, false, kUnrollNHuge>(a, grid, p.lds, h->stream);
+    } else if (p.xcopies > 1) {
+        ok = dispatch_n<T, false, true>(p.NT, p.G, a, grid, p.lds, h->stream);
     } else {
         ok = al ? dispatch_n<T, true>(p.NT, p.G, a, grid, p.lds, h->stream)
                 : dispatch_n<T, false>(p.NT, p.G, a, grid, p.lds, h->stream);

@@ -49,8 +49,9 @@ struct GemvNPlan {
     int64_t RB;     // rows per workgroup
     size_t lds;     // dynamic LDS bytes
     size_t ws;      // workspace bytes (split partial sums)
+    int xcopies;    // copies of x in LDS: 1, or 16/esize shifted ones for rows not 16-byte aligned
 };
-GemvNPlan plan_gemv_n(int esize, int64_t rows, int64_t cols);
+GemvNPlan plan_gemv_n(int esize, int64_t rows, int64_t cols, bool unaligned = false);
 
 struct GemvTPlan {
     int NT;         // threads per workgroup (waves split the rows of a split): 256, or

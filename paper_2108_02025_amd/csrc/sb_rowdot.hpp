@@ -19,10 +19,13 @@ namespace sb {
 // from LDS as vectors; otherwise up to W-1 leading elements are peeled.
 // BATCH_TAIL: the vectors left after the full batches of U (fewer than U
 // per lane) are loaded as one predicated batch, all in flight together;
-// otherwise one at a time (fewer registers).  The additions happen in the
-// same order either way.
-template <typename T, int G, int U, bool ALIGNED, bool NTL, bool BATCH_TAIL = true>
-__device__ __forceinline__ T row_dot(const T* Ar, int64_t klen, const T* xs, int l)
+// otherwise one at a time (fewer registers).  SHIFTED (rows not aligned):
+// LDS holds W copies of x, copy h shifted left by h elements and xstride
+// elements apart, so that the x of a row peeled by h elements is read from
+// copy h as aligned vectors.  The additions happen in the same order in
+// every case.
+template <typename T, int G, int U, bool ALIGNED, bool NTL, bool BATCH_TAIL = true, bool SHIFTED = false>
+__device__ __forceinline__ T row_dot(const T* Ar, int64_t klen, const T* xs, int l, int64_t xstride = 0)
 {
     typedef typename Vec<T>::type V;
     constexpr int W = Vec<T>::W;
@@ -36,7 +39,7 @@ __device__ __forceinline__ T row_dot(const T* Ar, int64_t klen, const T* xs, int
 
     const int64_t nv = (klen - head) / W;
     const V* Av = reinterpret_cast<const V*>(Ar + head);
-    const T* xb = xs + head;
+    const T* xb = SHIFTED ? xs + head * xstride : xs + head;
     int64_t v = l;
     // Full batches: with BATCH_TAIL as many as every lane of the group has
     // (the same count for the whole wave), the rest in one predicated batch.
@@ -48,7 +51,7 @@ __device__ __forceinline__ T row_dot(const T* Ar, int64_t klen, const T* xs, int
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t e = (v + u * G) * W;
-            if (ALIGNED) {
+            if (ALIGNED || SHIFTED) {
                 acc += av[u] * *reinterpret_cast<const V*>(xb + e);
             } else {
 #pragma unroll
