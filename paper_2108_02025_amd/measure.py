@@ -17,6 +17,8 @@ Sections (each prints one JSON line per case, times are HIP-event medians):
   ger        GER 16384^2 binary64 beside the probes that bound it: a
              streaming read, a copy and the read-and-rewrite probe with
              GER's own access pattern
+  serve      the serving loop: 4096 requests at 1e5/s, 4 GiB budget,
+             tuned configurations (one JSON line of its statistics)
 The operands are synthetic: uniform [-1, 1) and normal(0, 1) draws from
 torch's seeded generator, or the serving generator's SplitMix64 streams.
 """
@@ -188,7 +190,16 @@ def ger(dev, reps):
         emit("ger", name, bytes=nbytes, us=round(us, 2), GBs=round(nbytes / us / 1e3, 1))
 
 
-SECTIONS = {"batched": batched, "generator": generator, "narrow": narrow, "ger": ger}
+def serve(dev, reps):
+    """The serving loop on 4096 requests (Poisson 1e5/s, seed 501) with a
+    4 GiB budget and the tuned configurations (`reps` is not used)."""
+    from .serve import Server
+    server = Server(budget_bytes=4 << 30, tuning=TuningTable.load(), sample_every=256)
+    st = server.run(make_trace(4096, rate=1e5, seed=501))
+    emit("serve", "budget_4GiB_rate_1e5", **st.as_dict())
+
+
+SECTIONS = {"batched": batched, "generator": generator, "narrow": narrow, "ger": ger, "serve": serve}
 
 
 def main():
