@@ -196,7 +196,13 @@ class TuningTable:
         e = self.buckets.get(bucket(kind, m, n))
         if e is None:
             return None
-        return {"group": e["group"], "rows_per_tile": e["rows_per_tile"], "split": e["split"]}
+        # a bucket spans widths up to 2^0.5 times its centre: raise the split
+        # where this width's x chunk would not fit 32 KiB of LDS
+        xs = 8 if kind == "f64" else 4
+        split = e["split"]
+        while split and -(-n // split) * xs > 32768:
+            split += 1
+        return {"group": e["group"], "rows_per_tile": e["rows_per_tile"], "split": split}
 
 
 def main():
