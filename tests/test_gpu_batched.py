@@ -369,3 +369,54 @@ def test_batched_quantised_layouts_rejected(sb):
         sb.make_descs([sb.GemvProblem(codes, x, c, scales=s, q=sb.SB_BF16, op=sb.SB_T)])
     with pytest.raises(ValueError):
         sb.make_descs([sb.GemvProblem(codes.t(), x, c, scales=s, q=sb.SB_BF16)])
+
+
+def test_batched_graph_replay_split_and_column_problems(sb):
+    """A captured run replayed over new tables whose problems need the second
+    stage (split row dots, chunked column axpys) or none: every replay gives
+    the eager bits, with eager work on the same stream between replays."""
+    rng = np.random.default_rng(21)
+    batches = []
+    for b in range(3):
+        ps, hs = [], []
+        for i in range(5):
+            kind = ["f64", "f32"][i % 2]
+            npd = np.float64 if kind == "f64" else np.float32
+            m, n = int(rng.integers(1, 700)), int(rng.integers(1, 9000))
+            layout, op = LAYOUT_OPS[(b + i) % 4]
+            A, x, c0 = workloads.gemv_inputs(m, n, seed=700 + 10 * b + i, dist="normal", op_t=bool(op), dtype=npd)
+            cfg = {} if b == 2 else ({"split": 3} if (layout, op) in ((0, 0), (1, 1)) else {"rows_per_tile": 37})
+            ps.append(sb.GemvProblem(stored(A, layout, pad=i % 2), dev(x), dev(c0), op=op, **cfg))
+            hs.append(dict(c0=c0))
+        batches.append((ps, hs))
+    cap = max(sb.sb_gemv_batched_table_bytes(ps)[0] for ps, _ in batches)
+    table = sb.BatchTable(cap)
+    eager = []
+    for ps, hs in batches:
+        fresh = [sb.GemvProblem(P.A, P.x, dev(H["c0"]), op=P.op, group=P.group, rows_per_tile=P.rows_per_tile,
+                                split=P.split) for P, H in zip(ps, hs)]
+        sb.sb_gemv_batched(fresh)
+        eager.append([host(P.c).copy() for P in fresh])
+    table.encode(batches[0][0])
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        table.run()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=s):
+            table.run()
+    torch.cuda.synchronize()
+    other = torch.ones((300, 300), dtype=torch.float64, device="cuda")
+    for rep in range(2):
+        for (ps, hs), ref in zip(batches, eager):
+            for P, H in zip(ps, hs):
+                P.c.copy_(dev(H["c0"]))
+            table.encode(ps)
+            graph.replay()
+            sb.sb_gemv(other, torch.ones(300, dtype=torch.float64, device="cuda"),
+                       torch.zeros(300, dtype=torch.float64, device="cuda"))
+            torch.cuda.synchronize()
+            for P, r in zip(ps, ref):
+                assert np.array_equal(host(P.c), r), f"replay {rep}"
