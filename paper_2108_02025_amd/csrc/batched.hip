@@ -103,6 +103,12 @@ constexpr int64_t kBatTileBytes = SB_BAT_TILE_BYTES;  // largest automatic tile 
 #ifndef SB_BAT_UNROLL_T
 #define SB_BAT_UNROLL_T 8
 #endif
+// The vectors of a row left after its full batches of U: one predicated
+// batch, all in flight together (1), or one at a time (0), a round trip
+// each.  The additions happen in the same order either way.
+#ifndef SB_BAT_BATCH_TAIL
+#define SB_BAT_BATCH_TAIL 1
+#endif
 #ifndef SB_BAT_GRID
 #define SB_BAT_GRID 1024
 #endif
@@ -179,7 +185,7 @@ __device__ __forceinline__ void bat_rows(const BatProblem& p, int64_t s, int64_t
         if constexpr (DT == SB_F64 || DT == SB_F32) {
             typedef typename std::conditional<DT == SB_F64, double, float>::type T;
             const T* Ar = static_cast<const T*>(p.A) + row * p.lda + k0;
-            T t = row_dot<T, G, kBatUnrollPlain, AL, true, false>(Ar, klen, reinterpret_cast<const T*>(xs_raw), l);
+            T t = row_dot<T, G, kBatUnrollPlain, AL, true, SB_BAT_BATCH_TAIL>(Ar, klen, reinterpret_cast<const T*>(xs_raw), l);
             t = group_sum<G>(t);
             if (l == 0) {
                 if (p.S > 1) static_cast<T*>(p.partial)[s * p.m + row] = t;
@@ -190,7 +196,7 @@ __device__ __forceinline__ void bat_rows(const BatProblem& p, int64_t s, int64_t
             typedef typename C::code_t code_t;
             constexpr int U = DT == SB_BF16 ? kBatUnrollBf16 : kBatUnrollE4m3;
             float t[1];
-            tile_dot<C, G, U, 1, true, false>(static_cast<const code_t*>(p.A) + row * p.lda + k0, p.lda, klen,
+            tile_dot<C, G, U, 1, true, SB_BAT_BATCH_TAIL>(static_cast<const code_t*>(p.A) + row * p.lda + k0, p.lda, klen,
                                        reinterpret_cast<const float*>(xs_raw), l, t);
             float v = group_sum<G>(t[0]);
             if (l == 0) {
