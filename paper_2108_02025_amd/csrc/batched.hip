@@ -75,20 +75,20 @@ constexpr int64_t kBatLds = 32 * 1024;     // x chunk bytes per tile
 // Cost of a tile for the division of the work, in units of 10 ns: its
 // bytes of A at a per-format rate, a latency per row pass (a pass waits for
 // its loads) and a fixed part per tile.  The constants are a least-squares
-// fit to the measured durations of 107k tiles of random batches (m, n
+// fit to the measured durations of 90k tiles of random batches (m, n
 // log-uniform in [64, 8192], all four formats, tuned configurations):
-// microseconds per MB of A 35.85 (binary64), 46.74 (binary32), 74.18
-// (bfloat16 codes), 115.78 (E4M3 codes); 3.68 per pass; 0.66 per tile
-// (R^2 0.78, against 0.43-0.58 for bytes + 4 KiB + 8 KiB per pass).
+// microseconds per MB of A 44.38 (binary64), 47.73 (binary32), 76.06
+// (bfloat16 codes), 134.35 (E4M3 codes); 2.47 per pass; 0.37 per tile
+// (R^2 0.84, against 0.43-0.58 for bytes + 4 KiB + 8 KiB per pass).
 #ifndef SB_BAT_COST_PASS_US
-#define SB_BAT_COST_PASS_US 3.68
+#define SB_BAT_COST_PASS_US 2.47
 #endif
 #ifndef SB_BAT_COST_TILE_US
-#define SB_BAT_COST_TILE_US 0.66
+#define SB_BAT_COST_TILE_US 0.37
 #endif
 static double cost_us_per_mb(int32_t dt)
 {
-    return dt == SB_F64 ? 35.85 : dt == SB_F32 ? 46.74 : dt == SB_BF16 ? 74.18 : 115.78;
+    return dt == SB_F64 ? 44.38 : dt == SB_F32 ? 47.73 : dt == SB_BF16 ? 76.06 : 134.35;
 }
 constexpr int64_t kBatTileBytes = SB_BAT_TILE_BYTES;  // largest automatic tile (bytes of A)
 #ifndef SB_BAT_UNROLL_PLAIN
