@@ -71,6 +71,11 @@ constexpr int kUnrollN = SB_GEMV_N_UNROLL;  // 16-byte loads in flight per lane 
 #endif
 constexpr int kUnrollNHuge = SB_GEMV_N_UNROLL_HUGE;
 constexpr int kUnrollT = SB_GEMV_T_UNROLL;  // rows in flight per wave
+// the phase kernel of unaligned binary32 rows: 4 rows in flight per wave
+// (65537 x 4093: 193-195 -> 186 us against 8)
+#ifndef SB_GEMV_T_PHASE_UNROLL
+#define SB_GEMV_T_PHASE_UNROLL 4
+#endif
 constexpr bool kGemvNT = SB_GEMV_LOAD_NT;
 
 template <typename T>
@@ -280,7 +285,7 @@ __global__ __launch_bounds__(256) void gemv_t_phase_kernel(GemvTArgs<T> a)
 {
     constexpr int W = Vec<T>::W;
     typedef typename Vec<T>::type V;
-    constexpr int U = kUnrollT;
+    constexpr int U = SB_GEMV_T_PHASE_UNROLL;
     constexpr int NW = 256 / kWave;
     constexpr int CW = kWave * W;
     __shared__ T red[NW][CW];
