@@ -124,7 +124,7 @@ __global__ __launch_bounds__(NT) void gemv_n_kernel(GemvNArgs<T> a)
     const int64_t r1 = min(a.rows, r0 + a.RB);
 
     for (int64_t row = r0 + w * GW + g; row < r1; row += NW * GW) {
-        T t = row_dot<T, G, U, ALIGNED, kGemvNT, true, SHIFT>(a.A + row * a.ld + k0, klen, xs, l, a.KC);
+        T t = row_dot<T, G, U, ALIGNED, kGemvNT, true, SHIFT, true>(a.A + row * a.ld + k0, klen, xs, l, a.KC);
         t = group_sum<G>(t);
         if (l == 0) {
             if (a.partial) a.partial[s * a.rows + row] = t;

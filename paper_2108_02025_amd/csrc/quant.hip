@@ -28,6 +28,9 @@
 #ifndef SB_GEMVQ_UNROLL_E4M3
 #define SB_GEMVQ_UNROLL_E4M3 8
 #endif
+#ifndef SB_GEMVQ_UNROLL_E4M3_XT
+#define SB_GEMVQ_UNROLL_E4M3_XT 4
+#endif
 #ifndef SB_GEMVQ_MIN_WAVES
 #define SB_GEMVQ_MIN_WAVES 4
 #endif
@@ -109,16 +112,23 @@ struct GemvQArgs {
     float* c;
     float* partial;  // nsplit x m, or nullptr
     int64_t KC, RB;
+    int64_t NP;  // rows not 16-byte aligned: slots per residue of the transposed x
 };
 
 // A lower bound on waves per SIMD caps the registers the compiler may use
-// for the loads in flight and their decodes.
-template <bool BF16, int G, int NT, int R>
-__global__ __launch_bounds__(NT, SB_GEMVQ_MIN_WAVES) void gemv_q_kernel(GemvQArgs a)
+// for the loads in flight and their decodes.  XT (rows not 16-byte aligned,
+// R = 1): x staged transposed by residue, read by tile_dot_xt.
+template <bool BF16, int G, int NT, int R, bool XT = false>
+__global__ __launch_bounds__(NT, XT && !BF16 && G < 64 ? 3 : SB_GEMVQ_MIN_WAVES) void gemv_q_kernel(GemvQArgs a)
 {
+    static_assert(!XT || R == 1, "transposed x is read one row at a time");
     typedef Codes<BF16> C;
     typedef typename C::code_t code_t;
-    constexpr int U = BF16 ? SB_GEMVQ_UNROLL_BF16 : SB_GEMVQ_UNROLL_E4M3;
+    // E4M3 rows against the transposed x with several rows per wave: 4 loads
+    // in flight (their 16 slot offsets per lane leave no registers for 8);
+    // one row per wave keeps the offsets in scalar registers and 8 loads
+    constexpr int U = BF16 ? SB_GEMVQ_UNROLL_BF16
+                           : (XT && G < 64 ? SB_GEMVQ_UNROLL_E4M3_XT : SB_GEMVQ_UNROLL_E4M3);
     constexpr int NW = NT / kWave, GW = kWave / G;
     extern __shared__ __align__(16) unsigned char smem[];
     float* xs = reinterpret_cast<float*>(smem);
@@ -127,7 +137,9 @@ __global__ __launch_bounds__(NT, SB_GEMVQ_MIN_WAVES) void gemv_q_kernel(GemvQArg
     const int64_t k0 = s * a.KC;
     const int64_t klen = min(a.n, k0 + a.KC) - k0;
     const float* xg = a.x + k0;
-    if (SB_STAGE_VEC && ((reinterpret_cast<uintptr_t>(xg) | (uintptr_t)(klen * 4)) & 15) == 0)
+    if constexpr (XT)
+        stage_to_lds<NT>(xg, klen, [&](int64_t t, float v) { xs[xt_slot<C::PER16>(t, a.NP)] = v; });
+    else if (SB_STAGE_VEC && ((reinterpret_cast<uintptr_t>(xg) | (uintptr_t)(klen * 4)) & 15) == 0)
         stage_to_lds<NT>(reinterpret_cast<const v4f*>(xg), klen / 4,
                          [&](int64_t t, v4f v) { reinterpret_cast<v4f*>(xs)[t] = v; });
     else
@@ -148,16 +160,21 @@ __global__ __launch_bounds__(NT, SB_GEMVQ_MIN_WAVES) void gemv_q_kernel(GemvQArg
         }
     };
     int64_t row = r0 + (int64_t)(w * GW + g) * R;
+    if constexpr (XT) {
+        for (; row < r1; row += (int64_t)NW * GW)
+            finish(row, tile_dot_xt<C, G, U, kGemvQNT, true, true>(Q + row * a.ldq + k0, klen, xs, a.NP, l));
+        return;
+    }
     for (; row + R <= r1; row += (int64_t)NW * GW * R) {
         float t[R];
-        tile_dot<C, G, U, R, kGemvQNT>(Q + row * a.ldq + k0, a.ldq, klen, xs, l, t);
+        tile_dot<C, G, U, R, kGemvQNT, true, true>(Q + row * a.ldq + k0, a.ldq, klen, xs, l, t);
 #pragma unroll
         for (int r = 0; r < R; ++r) finish(row + r, t[r]);
     }
     // rows of a last, partial tile
     for (; row < r1; ++row) {
         float t[1];
-        tile_dot<C, G, U, 1, kGemvQNT>(Q + row * a.ldq + k0, a.ldq, klen, xs, l, t);
+        tile_dot<C, G, U, 1, kGemvQNT, true, true>(Q + row * a.ldq + k0, a.ldq, klen, xs, l, t);
         finish(row, t[0]);
     }
 }
@@ -178,11 +195,12 @@ static int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
 struct GemvQPlan {
     int G, NT;
-    int64_t KC, nsplit, RB;
+    int64_t KC, nsplit, RB, NP;
     size_t lds, ws;
 };
 
-static GemvQPlan plan_gemv_q(sb_dtype q, int64_t m, int64_t n, int R)
+// xt: rows not 16-byte aligned, x transposed by residue (NP slots each)
+static GemvQPlan plan_gemv_q(sb_dtype q, int64_t m, int64_t n, int R, bool xt = false)
 {
     GemvQPlan p{};
     const int64_t P = q == SB_BF16 ? 8 : 16;
@@ -193,7 +211,8 @@ static GemvQPlan plan_gemv_q(sb_dtype q, int64_t m, int64_t n, int R)
         p.KC = 8192;
         p.nsplit = ceil_div(n, p.KC);
     }
-    p.lds = (size_t)round_up(p.KC * 4, 16);
+    p.NP = xt ? (ceil_div(p.KC, P) | 1) : 0;
+    p.lds = xt ? (size_t)(P * p.NP * 4) : (size_t)round_up(p.KC * 4, 16);
     const bool big = p.lds > 40 * 1024;
     p.NT = p.lds > 80 * 1024 ? 1024 : (big ? (q == SB_BF16 ? SB_GEMVQ_NT_BIG_BF16 : SB_GEMVQ_NT_BIG_E4M3) : 256);
     const int64_t wpb = p.NT / 64;
@@ -202,8 +221,11 @@ static GemvQPlan plan_gemv_q(sb_dtype q, int64_t m, int64_t n, int R)
                              big ? SB_GEMVQ_BIG_WGS_PER_CU : SB_GEMVQ_WAVES_PER_CU / wpb));
     const int64_t nvec = ceil_div(p.KC, P);
     int G = 64;
+    // (the transposed E4M3 form takes fewer loads per lane below 64 lanes a row)
     const int64_t U = q == SB_BF16 ? SB_GEMVQ_UNROLL_BF16 : SB_GEMVQ_UNROLL_E4M3;
-    while (G > 4 && nvec < (int64_t)G * U) G >>= 1;
+    const int64_t Usmall = q == SB_BF16 || !xt ? U : SB_GEMVQ_UNROLL_E4M3_XT;
+    if (nvec < 64 * U)
+        while (G > 4 && nvec < (int64_t)G * Usmall) G >>= 1;
     p.G = G;
     const int64_t pass = wpb * (64 / G) * R;
     const int64_t row_blocks = std::max<int64_t>(1, ceil_div(256 * bpc, p.nsplit));
@@ -214,38 +236,38 @@ static GemvQPlan plan_gemv_q(sb_dtype q, int64_t m, int64_t n, int R)
 
 size_t gemv_q_ws_bytes(sb_dtype q, int64_t m, int64_t n) { return plan_gemv_q(q, m, n, 1).ws; }
 
-template <bool BF16, int G, int NT, int R>
+template <bool BF16, int G, int NT, int R, bool XT>
 static void launch_q(const GemvQArgs& a, dim3 grid, size_t lds, hipStream_t st)
 {
     static const bool attr_set = [] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemv_q_kernel<BF16, G, NT, R>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemv_q_kernel<BF16, G, NT, R, XT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         return true;
     }();
     (void)attr_set;
-    hipLaunchKernelGGL((gemv_q_kernel<BF16, G, NT, R>), grid, dim3(NT), lds, st, a);
+    hipLaunchKernelGGL((gemv_q_kernel<BF16, G, NT, R, XT>), grid, dim3(NT), lds, st, a);
 }
 
-template <bool BF16, int NT, int R>
+template <bool BF16, int NT, int R, bool XT>
 static bool dispatch_q_g(int G, const GemvQArgs& a, dim3 grid, size_t lds, hipStream_t st)
 {
     switch (G) {
-    case 4: launch_q<BF16, 4, NT, R>(a, grid, lds, st); return true;
-    case 8: launch_q<BF16, 8, NT, R>(a, grid, lds, st); return true;
-    case 16: launch_q<BF16, 16, NT, R>(a, grid, lds, st); return true;
-    case 32: launch_q<BF16, 32, NT, R>(a, grid, lds, st); return true;
-    case 64: launch_q<BF16, 64, NT, R>(a, grid, lds, st); return true;
+    case 4: launch_q<BF16, 4, NT, R, XT>(a, grid, lds, st); return true;
+    case 8: launch_q<BF16, 8, NT, R, XT>(a, grid, lds, st); return true;
+    case 16: launch_q<BF16, 16, NT, R, XT>(a, grid, lds, st); return true;
+    case 32: launch_q<BF16, 32, NT, R, XT>(a, grid, lds, st); return true;
+    case 64: launch_q<BF16, 64, NT, R, XT>(a, grid, lds, st); return true;
     }
     return false;
 }
 
-template <bool BF16, int R>
+template <bool BF16, int R, bool XT = false>
 static bool dispatch_q(int NT, int G, const GemvQArgs& a, dim3 grid, size_t lds, hipStream_t st)
 {
     switch (NT) {
-    case 256: return dispatch_q_g<BF16, 256, R>(G, a, grid, lds, st);
-    case 512: return dispatch_q_g<BF16, 512, R>(G, a, grid, lds, st);
-    case 1024: return dispatch_q_g<BF16, 1024, R>(G, a, grid, lds, st);
+    case 256: return dispatch_q_g<BF16, 256, R, XT>(G, a, grid, lds, st);
+    case 512: return dispatch_q_g<BF16, 512, R, XT>(G, a, grid, lds, st);
+    case 1024: return dispatch_q_g<BF16, 1024, R, XT>(G, a, grid, lds, st);
     }
     return false;
 }
@@ -257,18 +279,25 @@ sb_status run_gemv_q(sb_handle* h, sb_dtype q, int64_t m, int64_t n, const void*
     const int csize = q == SB_BF16 ? 2 : 1;
     // Row tiles need every row of a tile at the same 16-byte alignment.
     const bool rows_aligned = (ldq * csize) % 16 == 0;
+    // Rows not all 16-byte aligned read x transposed (conflict-free LDS
+    // reads at any row start).
+    const bool xt = !rows_aligned || (reinterpret_cast<uintptr_t>(Aq) & 15) != 0;
     constexpr int RB16 = SB_GEMVQ_ROWS_BF16, RE4 = SB_GEMVQ_ROWS_E4M3;
     const int R = rows_aligned ? (q == SB_BF16 ? RB16 : RE4) : 1;
-    const GemvQPlan p = plan_gemv_q(q, m, n, R);
+    const GemvQPlan p = plan_gemv_q(q, m, n, xt ? 1 : R, xt);
     if (p.ws > h->ws_bytes)
         return fail(h, SB_ENOMEM, "gemv_q needs %zu workspace bytes, handle has %zu", p.ws, h->ws_bytes);
     if (p.nsplit > 65535)
         return fail(h, SB_EUNSUPPORTED, "gemv_q: rows of %lld codes need %lld column splits (at most 65535)",
                     (long long)n, (long long)p.nsplit);
-    GemvQArgs a{m, n, ldq, Aq, scales, x, c, p.nsplit > 1 ? static_cast<float*>(claim_ws(h)) : nullptr, p.KC, p.RB};
+    GemvQArgs a{m, n, ldq, Aq, scales, x, c, p.nsplit > 1 ? static_cast<float*>(claim_ws(h)) : nullptr, p.KC, p.RB,
+                p.NP};
     const dim3 grid((unsigned)ceil_div(m, p.RB), (unsigned)p.nsplit);
     bool ok;
-    if (q == SB_BF16)
+    if (xt)
+        ok = q == SB_BF16 ? dispatch_q<true, 1, true>(p.NT, p.G, a, grid, p.lds, h->stream)
+                          : dispatch_q<false, 1, true>(p.NT, p.G, a, grid, p.lds, h->stream);
+    else if (q == SB_BF16)
         ok = R == 1 ? dispatch_q<true, 1>(p.NT, p.G, a, grid, p.lds, h->stream)
                     : dispatch_q<true, RB16>(p.NT, p.G, a, grid, p.lds, h->stream);
     else

@@ -22,9 +22,15 @@ namespace sb {
 // otherwise one at a time (fewer registers).  SHIFTED (rows not aligned):
 // LDS holds W copies of x, copy h shifted left by h elements and xstride
 // elements apart, so that the x of a row peeled by h elements is read from
-// copy h as aligned vectors.  The additions happen in the same order in
-// every case.
-template <typename T, int G, int U, bool ALIGNED, bool NTL, bool BATCH_TAIL = true, bool SHIFTED = false>
+// copy h as aligned vectors.  EDGE_NT: the peeled elements at either end
+// of an unaligned row are read with the non-temporal hint too, so that
+// they allocate no cache lines (a cached read of them misses to HBM when
+// other data has filled the caches since the last call: binary32 65537 x
+// 4093 GEMV-N after a 2 GiB write 189 -> 175 us; with A's row ends still
+// cached from the previous call the hint costs 2-3 us).  The additions
+// happen in the same order in every case.
+template <typename T, int G, int U, bool ALIGNED, bool NTL, bool BATCH_TAIL = true, bool SHIFTED = false,
+          bool EDGE_NT = false>
 __device__ __forceinline__ T row_dot(const T* Ar, int64_t klen, const T* xs, int l, int64_t xstride = 0)
 {
     typedef typename Vec<T>::type V;
@@ -35,7 +41,7 @@ __device__ __forceinline__ T row_dot(const T* Ar, int64_t klen, const T* xs, int
         head = min(head, klen);
     }
     V acc = (V)0;
-    if (!ALIGNED && l < head) acc[0] = Ar[l] * xs[l];
+    if (!ALIGNED && l < head) acc[0] = ld_stream<NTL && EDGE_NT>(Ar + l) * xs[l];
 
     const int64_t nv = (klen - head) / W;
     const V* Av = reinterpret_cast<const V*>(Ar + head);
@@ -82,7 +88,7 @@ __device__ __forceinline__ T row_dot(const T* Ar, int64_t klen, const T* xs, int
         for (int q = 0; q < W; ++q) acc[q] += av[q] * xb[e + q];
     }
     const int64_t t0 = head + nv * W;  // fewer than W elements remain
-    if (l < klen - t0) acc[1 % W] += Ar[t0 + l] * xs[t0 + l];
+    if (l < klen - t0) acc[1 % W] += ld_stream<NTL && EDGE_NT>(Ar + t0 + l) * xs[t0 + l];
 
     T t = acc[0];
 #pragma unroll
@@ -134,7 +140,9 @@ template <> struct Codes<false> {
 // codes apart) with the staged x, for lane l of a group of G lanes.  All R
 // rows must share the same 16-byte alignment.  A lane's additions happen in
 // the same order for any U and R, so the result does not depend on them.
-template <class C, int G, int U, int R, bool NTL, bool BATCH_TAIL = true>
+// EDGE_NT as for row_dot: the codes peeled at the row ends read with the
+// non-temporal hint.
+template <class C, int G, int U, int R, bool NTL, bool BATCH_TAIL = true, bool EDGE_NT = false>
 __device__ __forceinline__ void tile_dot(const typename C::code_t* Q0, int64_t ldq, int64_t klen,
                                          const float* xs, int l, float (&t)[R])
 {
@@ -147,7 +155,7 @@ __device__ __forceinline__ void tile_dot(const typename C::code_t* Q0, int64_t l
     for (int r = 0; r < R; ++r) acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0f;
     for (int64_t e = l; e < head; e += G) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r][0] += C::one(Q0[r * ldq + e]) * xs[e];
+        for (int r = 0; r < R; ++r) acc[r][0] += C::one(ld_stream<NTL && EDGE_NT>(Q0 + r * ldq + e)) * xs[e];
     }
     const int64_t nv = (klen - head) / P;
     const float* xb = xs + head;
@@ -240,10 +248,82 @@ __device__ __forceinline__ void tile_dot(const typename C::code_t* Q0, int64_t l
     }
     for (int64_t e = head + nv * P + l; e < klen; e += G) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r][1] += C::one(Q0[r * ldq + e]) * xs[e];
+        for (int r = 0; r < R; ++r) acc[r][1] += C::one(ld_stream<NTL && EDGE_NT>(Q0 + r * ldq + e)) * xs[e];
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) t[r] = (acc[r][0] + acc[r][1]) + (acc[r][2] + acc[r][3]);
+}
+
+// x transposed by residue, for rows that are not 16-byte aligned: element e
+// of the staged segment sits at xt[(e % P) * NP + e / P], NP >= klen / P
+// rounded up (odd, so that staging writes spread over the banks).
+// A row peeled by h codes pairs code q of its vector v with element
+// h + v P + q, whose slot is off_q + v with off_q fixed for the row, so the
+// lanes of a group (consecutive v) read consecutive dwords whatever h is.
+// In the plain layout those lanes read dwords P apart, a bank conflict of
+// every lane pair 32/P apart (E4M3 rows of 16383 codes: 1.2 TB/s, bound by
+// the LDS).
+template <int P>
+__device__ __forceinline__ int64_t xt_slot(int64_t e, int64_t NP)
+{
+    return (e & (P - 1)) * NP + (e >> __builtin_ctz(P));
+}
+
+// One row's partial dot product against the transposed x: the same loads
+// and the same additions in the same order as tile_dot with R = 1.
+template <class C, int G, int U, bool NTL, bool BATCH_TAIL = true, bool EDGE_NT = false>
+__device__ __forceinline__ float tile_dot_xt(const typename C::code_t* Q0, int64_t klen, const float* xt, int64_t NP,
+                                             int l)
+{
+    constexpr int P = C::PER16;
+    typedef typename C::code_t code_t;
+    int64_t head = ((16 - (reinterpret_cast<uintptr_t>(Q0) & 15)) & 15) / sizeof(code_t);
+    head = min(head, klen);
+    // one row per wave: the slot offsets below are wave-uniform (scalar)
+    if constexpr (G == 64) head = __builtin_amdgcn_readfirstlane((int32_t)head);
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t e = l; e < head; e += G) acc[0] += C::one(ld_stream<NTL && EDGE_NT>(Q0 + e)) * xt[xt_slot<P>(e, NP)];
+    const int64_t nv = (klen - head) / P;
+    const v4u* Qv = reinterpret_cast<const v4u*>(Q0 + head);
+    // slot of element head + v P + q: off[q] + v (head < P, so at most one carry)
+    int32_t off[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int32_t hq = (int32_t)head + q;
+        off[q] = (hq & (P - 1)) * (int32_t)NP + (hq >= P ? 1 : 0);
+    }
+    auto step = [&](const v4u& wv, int64_t v) {
+        float f[P];
+        C::unpack(wv, f);
+        const float* xv = xt + v;
+#pragma unroll
+        for (int q = 0; q < P; ++q) acc[q & 3] += f[q] * xv[off[q]];
+    };
+    int64_t v = l;
+    const int64_t vfull = BATCH_TAIL ? nv / (U * G) * (U * G) : nv - (U - 1) * G;
+    for (; v < vfull && v + (U - 1) * G < nv; v += U * G) {
+        v4u wv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) wv[u] = ld_stream<NTL>(Qv + v + u * G);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            step(wv[u], v + u * G);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    if (BATCH_TAIL && v < nv) {
+        v4u wv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) wv[u] = v + u * G < nv ? ld_stream<NTL>(Qv + v + u * G) : v4u{0, 0, 0, 0};
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (v + u * G < nv) step(wv[u], v + u * G);
+        v += U * G;
+    }
+    for (; v < nv; v += G) step(ld_stream<NTL>(Qv + v), v);  // not taken after a batched tail
+    for (int64_t e = head + nv * P + l; e < klen; e += G)
+        acc[1] += C::one(ld_stream<NTL && EDGE_NT>(Q0 + e)) * xt[xt_slot<P>(e, NP)];
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 }  // namespace sb

@@ -179,6 +179,34 @@ def test_gemv_q_integer_exact_and_shapes(sb, q):
             assert np.array_equal(host(cd).astype(np.float64), ref), (m, n, off)
 
 
+@pytest.mark.parametrize("q", ["bf16", "e4m3"])
+def test_gemv_q_unaligned_rows_float(sb, q):
+    """Rows that are not 16-byte aligned (odd n, a code base one element off)
+    read x transposed in LDS: normal(0, 1) data against the dequantised
+    oracle within the binary32 bound, across launch shapes (x below 40 KiB,
+    above 40 and 80 KiB, and column splits) and row-head offsets."""
+    qc = sb.SB_BF16 if q == "bf16" else sb.SB_FP8_E4M3
+    fmt = oracle.Q_BF16 if q == "bf16" else oracle.Q_E4M3
+    cdt = np.uint16 if q == "bf16" else np.uint8
+    rng = np.random.default_rng(72)
+    for m, n in ((257, 4093), (300, 1021), (65, 16383), (33, 24577), (17, 70001), (1, 3)):
+        A32 = rng.standard_normal((m, n)).astype(np.float32)
+        x = rng.standard_normal(n).astype(np.float32)
+        c0 = rng.standard_normal(m).astype(np.float32)
+        codes, s = oracle.quantize_rows(A32, fmt)
+        ref = oracle.gemv_q(codes, s, x, c0.astype(np.float64), fmt)
+        mag = np.abs(A32.astype(np.float64)) @ np.abs(x.astype(np.float64))
+        bound = 2 * gamma(n + 2, U32) * (1.125 * mag + s.astype(np.float64) * np.abs(x).sum() + np.abs(c0))
+        for off in (0, 1, 3):
+            buf = np.zeros(m * n + 3, dtype=cdt)
+            buf[off:off + m * n] = codes.reshape(-1)
+            bd = dev(buf.view(np.int16) if q == "bf16" else buf)
+            Aq = bd[off:off + m * n].reshape(m, n)
+            cd = dev(c0)
+            sb.sb_gemv_q(Aq, dev(s), dev(x), cd, qc)
+            assert_within(host(cd).astype(np.float64), ref, bound, f"gemv_q {q} {m}x{n} off {off}")
+
+
 def dot2_bound(s_exact, abs_sum, L):
     """Ogita-Rump-Oishi bound for Dot2 with a reduction path of length L:
     |res - s| <= u|s| + gamma_L^2 * sum|x_i y_i| (u = 2^-24)."""
