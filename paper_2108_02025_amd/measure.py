@@ -17,6 +17,9 @@ Sections (each prints one JSON line per case, times are HIP-event medians):
   ger        GER 16384^2 binary64 beside the probes that bound it: a
              streaming read, a copy and the read-and-rewrite probe with
              GER's own access pattern
+  skewed     GEMV N and T, binary64 and binary32, on 262144 x 256,
+             256 x 262144, 65536 x 4096 and 65537 x 4093 beside a streaming
+             read of A's bytes, each after a 2 GiB write and back to back
   serve      the serving loop: 4096 requests at 1e5/s, 4 GiB budget,
              tuned configurations (one JSON line of its statistics)
 The operands are synthetic: uniform [-1, 1) and normal(0, 1) draws from
@@ -32,7 +35,7 @@ import numpy as np
 import torch
 
 from . import (SB_BF16, SB_FP8_E4M3, SB_MXFP4_E2M1, SB_MXFP8_E4M3, SB_N, SB_T, GemvProblem, Handle, Plan, load,
-               mx_buffers, sb_gemv_mx,
+               mx_buffers, sb_gemv, sb_gemv_mx,
                sb_gemv_q, sb_ger, sb_quantize_mx, sb_quantize_rows, sb_stream_copy, sb_stream_read,
                sb_stream_update)
 from .serve import GEN_DESC, device_bytes, make_trace, materialise
@@ -190,6 +193,50 @@ def ger(dev, reps):
         emit("ger", name, bytes=nbytes, us=round(us, 2), GBs=round(nbytes / us / 1e3, 1))
 
 
+def skewed(dev, reps):
+    """GEMV N and T on the skewed shapes beside a streaming read of A's
+    bytes: per-call times after a 2 GiB write (x, c and A out of the
+    caches, as in the bench) and back to back."""
+    junk = torch.empty(1 << 28, dtype=torch.float64, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(12)
+
+    def cold_us(fn):
+        fn()
+        t = []
+        for _ in range(reps):
+            junk.fill_(0.5)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            t.append(1e3 * a.elapsed_time(b))
+        return sorted(t)[len(t) // 2]
+
+    for dt, es, tname in ((torch.float64, 8, "f64"), (torch.float32, 4, "f32")):
+        for m, n in ((262144, 256), (256, 262144), (65536, 4096), (65537, 4093)):
+            A = torch.randn((m, n), generator=g, device=dev, dtype=dt)
+            flat = A.view(-1)[: m * n // (16 // es) * (16 // es)]  # the probe reads whole 16-byte vectors
+            rb = flat.numel() * es
+            rd = {"cold": cold_us(lambda: sb_stream_read(flat)), "warm": timed_us(lambda: sb_stream_read(flat), reps)}
+            emit("skewed", f"read_probe_{tname}_{m}x{n}", bytes=rb,
+                 **{f"{k}_us": round(v, 2) for k, v in rd.items()},
+                 **{f"{k}_GBs": round(rb / v / 1e3, 1) for k, v in rd.items()})
+            for op, label, xl, cl in ((SB_N, "gemv_n", n, m), (SB_T, "gemv_t", m, n)):
+                x = torch.randn(xl, generator=g, device=dev, dtype=dt)
+                c = torch.randn(cl, generator=g, device=dev, dtype=dt)
+                nb = es * (m * n + xl + 2 * cl)
+                t = {"cold": cold_us(lambda: sb_gemv(A, x, c, op=op)),
+                     "warm": timed_us(lambda: sb_gemv(A, x, c, op=op), reps)}
+                emit("skewed", f"{label}_{tname}_{m}x{n}", bytes=nb,
+                     **{f"{k}_us": round(v, 2) for k, v in t.items()},
+                     **{f"{k}_GBs": round(nb / v / 1e3, 1) for k, v in t.items()},
+                     **{f"{k}_of_read_probe": round(rd[k] / t[k] * nb / rb, 3) for k in t})
+            del A, flat
+    del junk
+
+
 def serve(dev, reps):
     """The serving loop on 4096 requests (Poisson 1e5/s, seed 501) with a
     4 GiB budget and the tuned configurations (`reps` is not used)."""
@@ -199,7 +246,8 @@ def serve(dev, reps):
     emit("serve", "budget_4GiB_rate_1e5", **st.as_dict())
 
 
-SECTIONS = {"batched": batched, "generator": generator, "narrow": narrow, "ger": ger, "serve": serve}
+SECTIONS = {"batched": batched, "generator": generator, "narrow": narrow, "ger": ger, "skewed": skewed,
+            "serve": serve}
 
 
 def main():
