@@ -561,6 +561,25 @@ def host_info() -> dict:
     return {"cpu_model": model, "cpus_online": os.cpu_count(), "cpus_usable": len(os.sched_getaffinity(0))}
 
 
+def device_info(torch) -> dict:
+    """The GPU the step ran on: name, architecture, compute units, HBM,
+    peak engine and memory clocks, and the HIP version torch was built with."""
+    import ctypes
+    from paper_2108_02025_amd.build import torch_lib_dir
+    props = torch.cuda.get_device_properties(0)
+    out = {"name": props.name, "arch": getattr(props, "gcnArchName", None),
+           "compute_units": props.multi_processor_count, "hbm_bytes": props.total_memory,
+           "hip": torch.version.hip}
+    # hipDeviceAttribute_t values of hip_runtime_api.h (ROCm 7): peak clock
+    # (kHz) 5, memory bus width (bits) 59, peak memory clock (kHz) 60
+    hip = ctypes.CDLL(os.path.join(torch_lib_dir(), "libamdhip64.so"))
+    for key, attr in (("clock_mhz", 5), ("memory_bus_bits", 59), ("memory_clock_mhz", 60)):
+        v = ctypes.c_int(0)
+        if hip.hipDeviceGetAttribute(ctypes.byref(v), attr, torch.cuda.current_device()) == 0:
+            out[key] = v.value // 1000 if key.endswith("mhz") else v.value
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -685,6 +704,7 @@ def main():
                                    "turns a quarter of them into f32 DOTs of length log-uniform [64,65536])",
                           **serving}
     out["host"] = host_info()
+    out["device"] = device_info(torch)
     if not args.no_cpu:
         log("checking every step operation against the CPU oracle")
         out["errors"] = error_stats(sb, torch, ops)

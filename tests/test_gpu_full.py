@@ -55,6 +55,20 @@ def test_gemv_skewed(sb, dt, m, n, seed, op):
         assert normwise(got, ref) < 2.0 ** -16
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("m", [1, 7, 300])
+def test_gemv_t_wide_side_by_side(sb, dt, m):
+    """GEMV-T of a wide matrix with few aligned rows (the side-by-side
+    kernel: at least 1024 column blocks, no row split) with a padded leading
+    dimension, so that the last lane holds fewer than a vector's columns, and
+    a row count that leaves a partial batch of rows."""
+    npd = np.float64 if dt == "f64" else np.float32
+    W = 16 // np.dtype(npd).itemsize
+    n = 1024 * 64 * W + W - 1
+    got, ref, bnd = gemv_case(sb, m, n, 1, 311 + m, "normal", npd, lda=n + (W - n % W) % W + W)
+    assert_within(got, ref, bnd, f"{m}x{n} {dt} T")
+
+
 @pytest.mark.parametrize("m,n,seed", SKEWED)
 def test_gemv_skewed_integer_f32(sb, m, n, seed):
     """binary32 integer data in [-7, 7]: partial sums stay below 2^24, so the
