@@ -519,8 +519,14 @@ static void shape_gemv_n(GemvNPlan& p, int esize, int64_t rows)
     const int64_t bpc = std::max<int64_t>(1, std::min<int64_t>(kLdsPerCU / (int64_t)p.lds,
                                                               SB_GEMV_N_WAVES_PER_CU / waves_per_block));
     const int64_t nvec = ceil_div(p.KC, W);
+    // Lanes per row: the fewest that leave kUnrollN vectors per lane, but
+    // at least 8 (a 128-byte line per row and load instruction: with 4 lanes
+    // a row, each instruction reads half of 16 lines; 262144 x 256 binary32
+    // 51.1 -> 47.7 us, 524288 x 128 binary64 106 -> 94 us) unless a row has
+    // fewer than 32 vectors (1048576 x 64 binary32: 4 lanes 64 us, 8 lanes 71).
     int G = 64;
-    while (G > 4 && nvec < (int64_t)G * kUnrollN) G >>= 1;
+    const int gmin = nvec >= 32 ? 8 : 4;
+    while (G > gmin && nvec < (int64_t)G * kUnrollN) G >>= 1;
     p.G = G;
     const int64_t pass = waves_per_block * (64 / G);  // rows a workgroup covers at once
     const int64_t target = kCUs * bpc;
