@@ -59,7 +59,13 @@ namespace sb {
 
 constexpr int kBatNT = 256;
 constexpr int kBatWaves = kBatNT / kWave;
-constexpr int64_t kBatLds = 32 * 1024;     // x chunk bytes per tile
+// x chunk bytes per tile: two workgroups per compute unit, each with 64 KiB
+// (68 KiB with the column-axpy buffer) of the 160 KiB of LDS
+constexpr int64_t kBatLds = 64 * 1024;
+// Code rows that are not 16-byte aligned: four copies of x, copy h shifted
+// left by h elements, kBatXStride elements apart, so chunks of at most
+// kBatXStride columns (the automatic or given split is raised to keep them so).
+constexpr int64_t kBatXStride = kBatLds / 4 / 4;
 // Automatic tile height: about SB_BAT_TILE_BYTES of A per tile, and at most
 // SB_BAT_MAX_PASSES row passes of the workgroup (a pass: the rows its groups
 // take at once), since short rows are latency-bound per pass.
@@ -181,7 +187,32 @@ __device__ __forceinline__ void bat_rows(const BatProblem& p, int64_t s, int64_t
     constexpr int GW = kWave / G;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int g = lane / G, l = lane % G;
-    for (int64_t row = r0 + w * GW + g; row < r1; row += kBatWaves * GW) {
+    constexpr bool CODES = DT == SB_BF16 || DT == SB_FP8_E4M3;
+    // Code rows not 16-byte aligned: the rows of one pass of a wave are
+    // `period` rows apart (period: the rows after which the phase of a row
+    // start repeats), so that its groups share the copy of x they read and
+    // read the same addresses.  Pass slot q covers rows c + period (b GW + g),
+    // c = q % period, b = q / period: every row of the tile once.  A row's
+    // arithmetic does not depend on the order.
+    int lp = 0;  // log2 of the period (a power of two, at most 16)
+    if constexpr (CODES) {
+        const int rb = (int)((p.lda * (DT == SB_BF16 ? 2 : 1)) & 15);
+        lp = rb ? 4 - __builtin_ctz(rb) : 0;
+    }
+    const int64_t period = (int64_t)1 << lp;
+    const int64_t nrows = r1 - r0;
+    for (int64_t q = w;; q += kBatWaves) {
+        int64_t row;
+        if constexpr (CODES) {
+            const int64_t c = q & (period - 1), b = q >> lp;
+            const int64_t base = c + period * b * GW;
+            if (base >= nrows) break;
+            row = r0 + base + period * g;
+        } else {
+            if (q * GW >= nrows) break;
+            row = r0 + q * GW + g;
+        }
+        if (row >= r1) continue;
         if constexpr (DT == SB_F64 || DT == SB_F32) {
             typedef typename std::conditional<DT == SB_F64, double, float>::type T;
             const T* Ar = static_cast<const T*>(p.A) + row * p.lda + k0;
@@ -196,8 +227,11 @@ __device__ __forceinline__ void bat_rows(const BatProblem& p, int64_t s, int64_t
             typedef typename C::code_t code_t;
             constexpr int U = DT == SB_BF16 ? kBatUnrollBf16 : kBatUnrollE4m3;
             float t[1];
-            tile_dot<C, G, U, 1, true, SB_BAT_BATCH_TAIL>(static_cast<const code_t*>(p.A) + row * p.lda + k0, p.lda, klen,
-                                       reinterpret_cast<const float*>(xs_raw), l, t);
+            // x always read as aligned vectors: from the single copy when
+            // every row is 16-byte aligned (head 0), else from copy head % 4
+            tile_dot<C, G, U, 1, true, SB_BAT_BATCH_TAIL, false, true>(static_cast<const code_t*>(p.A) + row * p.lda + k0,
+                                                                       p.lda, klen, reinterpret_cast<const float*>(xs_raw),
+                                                                       l, t, p.aligned ? 0 : kBatXStride);
             float v = group_sum<G>(t[0]);
             if (l == 0) {
                 if (p.S > 1) static_cast<float*>(p.partial)[s * p.m + row] = v;
@@ -340,7 +374,14 @@ __global__ __launch_bounds__(kBatNT, 2) void gemv_batched_kernel(const unsigned 
                     const int xs_size = p.dtype == SB_F64 ? 8 : 4;
                     const unsigned char* xg = static_cast<const unsigned char*>(p.x) + k0 * xs_size;
                     const int64_t nbytes = klen * xs_size;
-                    if (((reinterpret_cast<uintptr_t>(xg) | (uintptr_t)nbytes) & 15) == 0) {
+                    if ((p.dtype == SB_BF16 || p.dtype == SB_FP8_E4M3) && !p.aligned) {
+                        float* xf = reinterpret_cast<float*>(xs);
+                        stage_to_lds<kBatNT, 16>(reinterpret_cast<const float*>(xg), klen, [&](int64_t e, float v) {
+#pragma unroll
+                            for (int h = 0; h < 4; ++h)
+                                if (e >= h) xf[h * kBatXStride + e - h] = v;
+                        });
+                    } else if (((reinterpret_cast<uintptr_t>(xg) | (uintptr_t)nbytes) & 15) == 0) {
                         stage_to_lds<kBatNT, 8>(reinterpret_cast<const v4u*>(xg), nbytes / 16,
                                                 [&](int64_t e, v4u v) { reinterpret_cast<v4u*>(xs)[e] = v; });
                     } else {
@@ -361,6 +402,8 @@ __global__ __launch_bounds__(kBatNT, 2) void gemv_batched_kernel(const unsigned 
                     if (p.aligned) bat_rows_g<SB_F32, true>(p, s, r0, r1, k0, klen, xs);
                     else bat_rows_g<SB_F32, false>(p, s, r0, r1, k0, klen, xs);
                     break;
+                // codes: one instance per format (alignment is a run-time
+                // stride), which keeps the kernel's code small
                 case SB_BF16: bat_rows_g<SB_BF16, false>(p, s, r0, r1, k0, klen, xs); break;
                 default: bat_rows_g<SB_FP8_E4M3, false>(p, s, r0, r1, k0, klen, xs); break;
                 }
@@ -403,10 +446,11 @@ static int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
 static int esize(int32_t dt) { return dt == SB_F64 ? 8 : dt == SB_F32 ? 4 : dt == SB_BF16 ? 2 : 1; }
 static int xsize(int32_t dt) { return dt == SB_F64 ? 8 : 4; }
-// Binary64/32 rows that all start on a 16-byte boundary (16-byte loads).
+// Stored rows that all start on a 16-byte boundary (binary64/32: 16-byte
+// loads of whole rows; codes: x from the single copy as vectors).
 static bool aligned_rows(int32_t dt, const void* A, int64_t lda)
 {
-    return (dt == SB_F64 || dt == SB_F32) && aligned16(A) && (lda * esize(dt)) % 16 == 0;
+    return aligned16(A) && (lda * esize(dt)) % 16 == 0;
 }
 
 // Fill the automatic fields of a row-dot descriptor (in.m, in.n: the stored
@@ -417,12 +461,15 @@ static bool resolve_rows(const sb_gemv_desc& in, sb_gemv_desc& out, int64_t* KC,
     out = in;
     const int es = esize(in.dtype), xs = xsize(in.dtype);
     const int64_t vec = 16 / es;  // elements per 16-byte load
-    const int64_t max_kc = kBatLds / xs;
+    const bool codes = in.dtype == SB_BF16 || in.dtype == SB_FP8_E4M3;
+    const bool shifted = codes && !aligned_rows(in.dtype, in.A, in.lda);  // four copies of x
+    const int64_t max_kc = shifted ? kBatXStride : kBatLds / xs;
     if (in.split < 0 || in.group < 0 || in.rows_per_tile < 0) {
         snprintf(why, whylen, "negative configuration value");
         return false;
     }
     int64_t S = in.split ? in.split : std::max<int64_t>(1, ceil_div(in.n, max_kc));
+    if (shifted) S = std::max<int64_t>(S, ceil_div(in.n, max_kc));
     int64_t kc = round_up(std::max<int64_t>(1, ceil_div(in.n, S)), 16);
     if (kc > max_kc) {
         snprintf(why, whylen, "split %lld leaves %lld columns per chunk, above %lld", (long long)S, (long long)kc,

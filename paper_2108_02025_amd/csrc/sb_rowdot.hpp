@@ -141,10 +141,15 @@ template <> struct Codes<false> {
 // rows must share the same 16-byte alignment.  A lane's additions happen in
 // the same order for any U and R, so the result does not depend on them.
 // EDGE_NT as for row_dot: the codes peeled at the row ends read with the
-// non-temporal hint.
-template <class C, int G, int U, int R, bool NTL, bool BATCH_TAIL = true, bool EDGE_NT = false>
+// non-temporal hint.  SHIFTED: LDS holds 4 copies of x, copy h shifted left
+// by h elements and xstride elements apart, and a row peeled by h codes
+// reads the x of its vectors from copy h % 4 as aligned 16-byte vectors
+// (in the single copy, rows with h % 4 != 0 read x one element at a time,
+// lanes P elements apart: a bank conflict of every lane pair 32/P apart).
+template <class C, int G, int U, int R, bool NTL, bool BATCH_TAIL = true, bool EDGE_NT = false,
+          bool SHIFTED = false>
 __device__ __forceinline__ void tile_dot(const typename C::code_t* Q0, int64_t ldq, int64_t klen,
-                                         const float* xs, int l, float (&t)[R])
+                                         const float* xs, int l, float (&t)[R], int64_t xstride = 0)
 {
     typedef typename C::code_t code_t;
     constexpr int P = C::PER16;
@@ -158,8 +163,9 @@ __device__ __forceinline__ void tile_dot(const typename C::code_t* Q0, int64_t l
         for (int r = 0; r < R; ++r) acc[r][0] += C::one(ld_stream<NTL && EDGE_NT>(Q0 + r * ldq + e)) * xs[e];
     }
     const int64_t nv = (klen - head) / P;
-    const float* xb = xs + head;
-    const bool xal = ((head * 4) & 15) == 0;
+    const int64_t hs = SHIFTED ? (head & 3) : 0;
+    const float* xb = xs + hs * xstride + head - hs;
+    const bool xal = SHIFTED || ((head * 4) & 15) == 0;
     const v4u* Qv[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) Qv[r] = reinterpret_cast<const v4u*>(Q0 + r * ldq + head);

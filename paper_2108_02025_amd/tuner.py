@@ -8,8 +8,9 @@ device), times each candidate configuration
     group          lanes per row (rows per wave = 64 / group): the powers of
                    two 4..64 that leave each lane at least one 16-byte load
     split          column chunks (tile width n / split; split-K): the fewest
-                   whose x chunk fits 32 KiB of LDS, plus twice and four times
-                   that for short, wide shapes
+                   whose x chunk fits 32 KiB of LDS (the kernel takes up to
+                   64 KiB; the table was measured with 32), plus twice and
+                   four times that for short, wide shapes
     rows_per_tile  tile height: automatic (about 256 KiB of A, at most eight
                    row passes), or two or sixteen row passes of the workgroup
 

@@ -238,13 +238,20 @@ def test_batched_resolve_encode_on_host(L):
 
     import paper_2108_02025_amd as sb
     arr = (sb.sb_gemv_desc * 3)()
-    arr[0] = _desc(sb, 1, 1000, 8192, A_, C_)                       # binary32: x fits one 32 KiB chunk
-    arr[1] = _desc(sb, 0, 64, 10000, A_ + (1 << 30), C_ + (1 << 20))  # binary64: needs 3 chunks
+    arr[0] = _desc(sb, 1, 1000, 16384, A_, C_)                      # binary32: x fits one 64 KiB chunk
+    arr[1] = _desc(sb, 0, 64, 20000, A_ + (1 << 30), C_ + (1 << 20))  # binary64: needs 3 chunks
     arr[2] = _desc(sb, 2, 5, 7, A_ + (2 << 30), C_ + (2 << 20), scales=X_ + 4096, group=8, rows_per_tile=32)
     out = (sb.sb_gemv_desc * 3)()
     assert L.sb_gemv_batched_resolve(arr, 3, out) == 0
     assert out[0].split == 1 and out[1].split == 3
     assert (out[2].group, out[2].rows_per_tile, out[2].split) == (8, 32, 1)
+    # codes whose rows are not 16-byte aligned read x from four shifted
+    # copies: chunks of at most 4096 columns, a given split raised to that
+    odd = (sb.sb_gemv_desc * 2)(_desc(sb, 2, 100, 8191, A_, C_, scales=X_, split=1),
+                                _desc(sb, 2, 100, 8192, A_ + (1 << 30), C_ + (1 << 20), scales=X_ + 4096, split=1))
+    odd_out = (sb.sb_gemv_desc * 2)()
+    assert L.sb_gemv_batched_resolve(odd, 2, odd_out) == 0
+    assert odd_out[0].split == 2 and odd_out[1].split == 1
     for k in range(3):
         assert out[k].group in (4, 8, 16, 32, 64) and out[k].rows_per_tile % (4 * 64 // out[k].group) == 0
     img = ctypes.c_size_t(0)
