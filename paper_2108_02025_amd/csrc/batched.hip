@@ -62,10 +62,11 @@ constexpr int kBatWaves = kBatNT / kWave;
 // x chunk bytes per tile: two workgroups per compute unit, each with 64 KiB
 // (68 KiB with the column-axpy buffer) of the 160 KiB of LDS
 constexpr int64_t kBatLds = 64 * 1024;
-// Code rows that are not 16-byte aligned: four copies of x, copy h shifted
-// left by h elements, kBatXStride elements apart, so chunks of at most
-// kBatXStride columns (the automatic or given split is raised to keep them so).
-constexpr int64_t kBatXStride = kBatLds / 4 / 4;
+// Code rows that are not 16-byte aligned: two copies of x, copy h shifted
+// left by h elements, kBatXStride elements apart, read as 8-byte pairs, so
+// chunks of at most kBatXStride columns (the automatic or given split is
+// raised to keep them so).
+constexpr int64_t kBatXStride = kBatLds / 2 / 4;
 // Automatic tile height: about SB_BAT_TILE_BYTES of A per tile, and at most
 // SB_BAT_MAX_PASSES row passes of the workgroup (a pass: the rows its groups
 // take at once), since short rows are latency-bound per pass.
@@ -227,11 +228,13 @@ __device__ __forceinline__ void bat_rows(const BatProblem& p, int64_t s, int64_t
             typedef typename C::code_t code_t;
             constexpr int U = DT == SB_BF16 ? kBatUnrollBf16 : kBatUnrollE4m3;
             float t[1];
-            // x always read as aligned vectors: from the single copy when
-            // every row is 16-byte aligned (head 0), else from copy head % 4
-            tile_dot<C, G, U, 1, true, SB_BAT_BATCH_TAIL, false, true>(static_cast<const code_t*>(p.A) + row * p.lda + k0,
-                                                                       p.lda, klen, reinterpret_cast<const float*>(xs_raw),
-                                                                       l, t, p.aligned ? 0 : kBatXStride);
+            // x read as aligned vectors: 16 bytes from the single copy when
+            // every row is 16-byte aligned (head 0), else 8-byte pairs from
+            // copy head % 2
+            const code_t* Qr = static_cast<const code_t*>(p.A) + row * p.lda + k0;
+            const float* xf = reinterpret_cast<const float*>(xs_raw);
+            if (p.aligned) tile_dot<C, G, U, 1, true, SB_BAT_BATCH_TAIL, false, 4>(Qr, p.lda, klen, xf, l, t, 0);
+            else tile_dot<C, G, U, 1, true, SB_BAT_BATCH_TAIL, false, 2>(Qr, p.lda, klen, xf, l, t, kBatXStride);
             float v = group_sum<G>(t[0]);
             if (l == 0) {
                 if (p.S > 1) static_cast<float*>(p.partial)[s * p.m + row] = v;
@@ -377,9 +380,8 @@ __global__ __launch_bounds__(kBatNT, 2) void gemv_batched_kernel(const unsigned 
                     if ((p.dtype == SB_BF16 || p.dtype == SB_FP8_E4M3) && !p.aligned) {
                         float* xf = reinterpret_cast<float*>(xs);
                         stage_to_lds<kBatNT, 16>(reinterpret_cast<const float*>(xg), klen, [&](int64_t e, float v) {
-#pragma unroll
-                            for (int h = 0; h < 4; ++h)
-                                if (e >= h) xf[h * kBatXStride + e - h] = v;
+                            xf[e] = v;
+                            if (e >= 1) xf[kBatXStride + e - 1] = v;
                         });
                     } else if (((reinterpret_cast<uintptr_t>(xg) | (uintptr_t)nbytes) & 15) == 0) {
                         stage_to_lds<kBatNT, 8>(reinterpret_cast<const v4u*>(xg), nbytes / 16,
@@ -462,7 +464,7 @@ static bool resolve_rows(const sb_gemv_desc& in, sb_gemv_desc& out, int64_t* KC,
     const int es = esize(in.dtype), xs = xsize(in.dtype);
     const int64_t vec = 16 / es;  // elements per 16-byte load
     const bool codes = in.dtype == SB_BF16 || in.dtype == SB_FP8_E4M3;
-    const bool shifted = codes && !aligned_rows(in.dtype, in.A, in.lda);  // four copies of x
+    const bool shifted = codes && !aligned_rows(in.dtype, in.A, in.lda);  // two copies of x
     const int64_t max_kc = shifted ? kBatXStride : kBatLds / xs;
     if (in.split < 0 || in.group < 0 || in.rows_per_tile < 0) {
         snprintf(why, whylen, "negative configuration value");

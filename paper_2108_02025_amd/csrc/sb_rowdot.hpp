@@ -141,13 +141,13 @@ template <> struct Codes<false> {
 // rows must share the same 16-byte alignment.  A lane's additions happen in
 // the same order for any U and R, so the result does not depend on them.
 // EDGE_NT as for row_dot: the codes peeled at the row ends read with the
-// non-temporal hint.  SHIFTED: LDS holds 4 copies of x, copy h shifted left
+// non-temporal hint.  XC > 1: LDS holds XC copies of x, copy h shifted left
 // by h elements and xstride elements apart, and a row peeled by h codes
-// reads the x of its vectors from copy h % 4 as aligned 16-byte vectors
-// (in the single copy, rows with h % 4 != 0 read x one element at a time,
-// lanes P elements apart: a bank conflict of every lane pair 32/P apart).
-template <class C, int G, int U, int R, bool NTL, bool BATCH_TAIL = true, bool EDGE_NT = false,
-          bool SHIFTED = false>
+// reads the x of its vectors from copy h % XC as aligned XC-element vectors
+// (4: 16 bytes, 2: 8 bytes).  With one copy (XC = 1) rows with h % 4 != 0
+// read x one element at a time, lanes P elements apart: a bank conflict of
+// every lane pair 32/P apart.
+template <class C, int G, int U, int R, bool NTL, bool BATCH_TAIL = true, bool EDGE_NT = false, int XC = 1>
 __device__ __forceinline__ void tile_dot(const typename C::code_t* Q0, int64_t ldq, int64_t klen,
                                          const float* xs, int l, float (&t)[R], int64_t xstride = 0)
 {
@@ -163,9 +163,10 @@ __device__ __forceinline__ void tile_dot(const typename C::code_t* Q0, int64_t l
         for (int r = 0; r < R; ++r) acc[r][0] += C::one(ld_stream<NTL && EDGE_NT>(Q0 + r * ldq + e)) * xs[e];
     }
     const int64_t nv = (klen - head) / P;
-    const int64_t hs = SHIFTED ? (head & 3) : 0;
+    static_assert(XC == 1 || XC == 2 || XC == 4, "x copies");
+    const int64_t hs = XC > 1 ? (head & (XC - 1)) : 0;
     const float* xb = xs + hs * xstride + head - hs;
-    const bool xal = SHIFTED || ((head * 4) & 15) == 0;
+    const bool xal = XC > 1 || ((head * 4) & 15) == 0;
     const v4u* Qv[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) Qv[r] = reinterpret_cast<const v4u*>(Q0 + r * ldq + head);
@@ -190,7 +191,14 @@ __device__ __forceinline__ void tile_dot(const typename C::code_t* Q0, int64_t l
                 float xr[P];
 #pragma unroll
                 for (int q = 0; q < P; q += 4) {
-                    if constexpr (XAL) {
+                    if constexpr (XAL && XC == 2) {
+                        const v2f xa = *reinterpret_cast<const v2f*>(xe + q);
+                        const v2f xc = *reinterpret_cast<const v2f*>(xe + q + 2);
+                        xr[q] = xa[0];
+                        xr[q + 1] = xa[1];
+                        xr[q + 2] = xc[0];
+                        xr[q + 3] = xc[1];
+                    } else if constexpr (XAL) {
                         const v4f xv = *reinterpret_cast<const v4f*>(xe + q);
                         xr[q] = xv[0];
                         xr[q + 1] = xv[1];

@@ -245,13 +245,14 @@ def test_batched_resolve_encode_on_host(L):
     assert L.sb_gemv_batched_resolve(arr, 3, out) == 0
     assert out[0].split == 1 and out[1].split == 3
     assert (out[2].group, out[2].rows_per_tile, out[2].split) == (8, 32, 1)
-    # codes whose rows are not 16-byte aligned read x from four shifted
-    # copies: chunks of at most 4096 columns, a given split raised to that
-    odd = (sb.sb_gemv_desc * 2)(_desc(sb, 2, 100, 8191, A_, C_, scales=X_, split=1),
-                                _desc(sb, 2, 100, 8192, A_ + (1 << 30), C_ + (1 << 20), scales=X_ + 4096, split=1))
-    odd_out = (sb.sb_gemv_desc * 2)()
-    assert L.sb_gemv_batched_resolve(odd, 2, odd_out) == 0
-    assert odd_out[0].split == 2 and odd_out[1].split == 1
+    # codes whose rows are not 16-byte aligned read x from two shifted
+    # copies: chunks of at most 8192 columns, a given split raised to that
+    odd = (sb.sb_gemv_desc * 3)(_desc(sb, 2, 100, 8191, A_, C_, scales=X_, split=1),
+                                _desc(sb, 2, 100, 12289, A_ + (1 << 30), C_ + (1 << 20), scales=X_ + 4096, split=1),
+                                _desc(sb, 2, 100, 12288, A_ + (2 << 30), C_ + (2 << 20), scales=X_ + 8192, split=1))
+    odd_out = (sb.sb_gemv_desc * 3)()
+    assert L.sb_gemv_batched_resolve(odd, 3, odd_out) == 0
+    assert [odd_out[k].split for k in range(3)] == [1, 2, 1]
     for k in range(3):
         assert out[k].group in (4, 8, 16, 32, 64) and out[k].rows_per_tile % (4 * 64 // out[k].group) == 0
     img = ctypes.c_size_t(0)
