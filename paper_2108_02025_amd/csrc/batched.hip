@@ -62,7 +62,7 @@ constexpr int kBatWaves = kBatNT / kWave;
 // x chunk bytes per tile: two workgroups per compute unit, each with 64 KiB
 // (68 KiB with the column-axpy buffer) of the 160 KiB of LDS
 constexpr int64_t kBatLds = 64 * 1024;
-// Code rows that are not 16-byte aligned: two copies of x, copy h shifted
+// Code and binary32 rows that are not 16-byte aligned: two copies of x, copy h shifted
 // left by h elements, kBatXStride elements apart, read as 8-byte pairs, so
 // chunks of at most kBatXStride columns (the automatic or given split is
 // raised to keep them so).
@@ -189,6 +189,7 @@ __device__ __forceinline__ void bat_rows(const BatProblem& p, int64_t s, int64_t
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int g = lane / G, l = lane % G;
     constexpr bool CODES = DT == SB_BF16 || DT == SB_FP8_E4M3;
+    constexpr bool PHASED = CODES || (DT == SB_F32 && !AL);  // x read from copies
     // Code rows not 16-byte aligned: the rows of one pass of a wave are
     // `period` rows apart (period: the rows after which the phase of a row
     // start repeats), so that its groups share the copy of x they read and
@@ -196,15 +197,15 @@ __device__ __forceinline__ void bat_rows(const BatProblem& p, int64_t s, int64_t
     // c = q % period, b = q / period: every row of the tile once.  A row's
     // arithmetic does not depend on the order.
     int lp = 0;  // log2 of the period (a power of two, at most 16)
-    if constexpr (CODES) {
-        const int rb = (int)((p.lda * (DT == SB_BF16 ? 2 : 1)) & 15);
+    if constexpr (PHASED) {
+        const int rb = (int)((p.lda * (DT == SB_BF16 ? 2 : DT == SB_F32 ? 4 : 1)) & 15);
         lp = rb ? 4 - __builtin_ctz(rb) : 0;
     }
     const int64_t period = (int64_t)1 << lp;
     const int64_t nrows = r1 - r0;
     for (int64_t q = w;; q += kBatWaves) {
         int64_t row;
-        if constexpr (CODES) {
+        if constexpr (PHASED) {
             const int64_t c = q & (period - 1), b = q >> lp;
             const int64_t base = c + period * b * GW;
             if (base >= nrows) break;
@@ -217,7 +218,10 @@ __device__ __forceinline__ void bat_rows(const BatProblem& p, int64_t s, int64_t
         if constexpr (DT == SB_F64 || DT == SB_F32) {
             typedef typename std::conditional<DT == SB_F64, double, float>::type T;
             const T* Ar = static_cast<const T*>(p.A) + row * p.lda + k0;
-            T t = row_dot<T, G, kBatUnrollPlain, AL, true, SB_BAT_BATCH_TAIL>(Ar, klen, reinterpret_cast<const T*>(xs_raw), l);
+            // binary32 rows not aligned: x from copy head % 2 as 8-byte pairs
+            constexpr bool PAIRS = DT == SB_F32 && !AL;
+            T t = row_dot<T, G, kBatUnrollPlain, AL, true, SB_BAT_BATCH_TAIL, false, false, PAIRS>(
+                Ar, klen, reinterpret_cast<const T*>(xs_raw), l, kBatXStride);
             t = group_sum<G>(t);
             if (l == 0) {
                 if (p.S > 1) static_cast<T*>(p.partial)[s * p.m + row] = t;
@@ -377,7 +381,7 @@ __global__ __launch_bounds__(kBatNT, 2) void gemv_batched_kernel(const unsigned 
                     const int xs_size = p.dtype == SB_F64 ? 8 : 4;
                     const unsigned char* xg = static_cast<const unsigned char*>(p.x) + k0 * xs_size;
                     const int64_t nbytes = klen * xs_size;
-                    if ((p.dtype == SB_BF16 || p.dtype == SB_FP8_E4M3) && !p.aligned) {
+                    if ((p.dtype == SB_BF16 || p.dtype == SB_FP8_E4M3 || p.dtype == SB_F32) && !p.aligned) {
                         float* xf = reinterpret_cast<float*>(xs);
                         stage_to_lds<kBatNT, 16>(reinterpret_cast<const float*>(xg), klen, [&](int64_t e, float v) {
                             xf[e] = v;
@@ -464,7 +468,7 @@ static bool resolve_rows(const sb_gemv_desc& in, sb_gemv_desc& out, int64_t* KC,
     const int es = esize(in.dtype), xs = xsize(in.dtype);
     const int64_t vec = 16 / es;  // elements per 16-byte load
     const bool codes = in.dtype == SB_BF16 || in.dtype == SB_FP8_E4M3;
-    const bool shifted = codes && !aligned_rows(in.dtype, in.A, in.lda);  // two copies of x
+    const bool shifted = (codes || in.dtype == SB_F32) && !aligned_rows(in.dtype, in.A, in.lda);  // two copies of x
     const int64_t max_kc = shifted ? kBatXStride : kBatLds / xs;
     if (in.split < 0 || in.group < 0 || in.rows_per_tile < 0) {
         snprintf(why, whylen, "negative configuration value");

@@ -27,10 +27,13 @@ namespace sb {
 // they allocate no cache lines (a cached read of them misses to HBM when
 // other data has filled the caches since the last call: binary32 65537 x
 // 4093 GEMV-N after a 2 GiB write 189 -> 175 us; with A's row ends still
-// cached from the previous call the hint costs 2-3 us).  The additions
-// happen in the same order in every case.
+// cached from the previous call the hint costs 2-3 us).  PAIRS (binary32
+// rows not aligned): LDS holds 2 copies of x, copy h shifted left by h
+// elements and xstride apart, and a row peeled by h elements reads its x
+// from copy h % 2 as aligned 8-byte pairs.  The additions happen in the
+// same order in every case.
 template <typename T, int G, int U, bool ALIGNED, bool NTL, bool BATCH_TAIL = true, bool SHIFTED = false,
-          bool EDGE_NT = false>
+          bool EDGE_NT = false, bool PAIRS = false>
 __device__ __forceinline__ T row_dot(const T* Ar, int64_t klen, const T* xs, int l, int64_t xstride = 0)
 {
     typedef typename Vec<T>::type V;
@@ -45,7 +48,8 @@ __device__ __forceinline__ T row_dot(const T* Ar, int64_t klen, const T* xs, int
 
     const int64_t nv = (klen - head) / W;
     const V* Av = reinterpret_cast<const V*>(Ar + head);
-    const T* xb = SHIFTED ? xs + head * xstride : xs + head;
+    static_assert(!PAIRS || (std::is_same<T, float>::value && !SHIFTED), "pairs: binary32, one copy mode");
+    const T* xb = SHIFTED ? xs + head * xstride : PAIRS ? xs + (head & 1) * xstride + (head & ~(int64_t)1) : xs + head;
     int64_t v = l;
     // Full batches: with BATCH_TAIL as many as every lane of the group has
     // (the same count for the whole wave), the rest in one predicated batch.
@@ -59,6 +63,13 @@ __device__ __forceinline__ T row_dot(const T* Ar, int64_t klen, const T* xs, int
             const int64_t e = (v + u * G) * W;
             if (ALIGNED || SHIFTED) {
                 acc += av[u] * *reinterpret_cast<const V*>(xb + e);
+            } else if constexpr (PAIRS) {
+                const v2f xa = *reinterpret_cast<const v2f*>(xb + e);
+                const v2f xc = *reinterpret_cast<const v2f*>(xb + e + 2);
+                acc[0] += av[u][0] * xa[0];
+                acc[1] += av[u][1] * xa[1];
+                acc[2] += av[u][2] * xc[0];
+                acc[3] += av[u][3] * xc[1];
             } else {
 #pragma unroll
                 for (int q = 0; q < W; ++q) acc[q] += av[u][q] * xb[e + q];
