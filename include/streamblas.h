@@ -314,9 +314,10 @@ sb_status sb_dot2_f32(sb_handle* handle, int64_t n, const float* x, const float*
  *          Column axpys: stored rows per chunk (0: from split, or about
  *          256 KiB of A per tile); the chunking sets the summation order.
  *   split  row dots: column chunks, each chunk's x must fit 64 KiB of LDS
- *          (0: automatic; for SB_BF16 / SB_FP8_E4M3 rows that are not all
- *          16-byte aligned, chunks of at most 8192 columns, and a smaller
- *          split is raised to that: x is staged as two shifted copies).
+ *          (0: automatic; for SB_F32, SB_BF16 and SB_FP8_E4M3 rows that
+ *          are not all 16-byte aligned, chunks of at most 8192 columns, and
+ *          a smaller split is raised to that: x is staged as two shifted
+ *          copies).
  *          Column axpys: row chunks (0: from rows_per_tile; if both are
  *          given they must agree).
  * Outputs of different problems must not overlap.  Problems with m = 0 or
