@@ -179,7 +179,7 @@ static_assert(sizeof(sb_gemv_desc) == 80, "descriptor layout (mirrored by the Py
 // Rows [r0, r1) of one tile, per-row results to c or to the split partials.
 // Inlined into the kernel, whose bound of two workgroups per compute unit
 // leaves room for every (dtype, group, alignment) variant without spills
-// (204 VGPRs): as separate non-inlined functions their call frames cost 160
+// (248 VGPRs): as separate non-inlined functions their call frames cost 160
 // bytes of scratch per lane, and within 128 VGPRs the inlined variants spill.
 template <int DT, int G, bool AL>
 __device__ __forceinline__ void bat_rows(const BatProblem& p, int64_t s, int64_t r0, int64_t r1, int64_t k0,
@@ -190,9 +190,10 @@ __device__ __forceinline__ void bat_rows(const BatProblem& p, int64_t s, int64_t
     const int g = lane / G, l = lane % G;
     constexpr bool CODES = DT == SB_BF16 || DT == SB_FP8_E4M3;
     constexpr bool PHASED = CODES || (DT == SB_F32 && !AL);  // x read from copies
-    // Code rows not 16-byte aligned: the rows of one pass of a wave are
-    // `period` rows apart (period: the rows after which the phase of a row
-    // start repeats), so that its groups share the copy of x they read and
+    // Rows that read x from the copies (codes; binary32 rows not 16-byte
+    // aligned): the rows of one pass of a wave are `period` rows apart
+    // (period: the rows after which the phase of a row start repeats; 1 for
+    // aligned rows), so that its groups share the copy of x they read and
     // read the same addresses.  Pass slot q covers rows c + period (b GW + g),
     // c = q % period, b = q / period: every row of the tile once.  A row's
     // arithmetic does not depend on the order.
