@@ -94,8 +94,11 @@ struct GemvNArgs {
 // the x chunk, copy h shifted left by h elements, KC elements apart, and a
 // row whose first 16-byte boundary is h elements in reads copy h as
 // aligned vectors (otherwise it reads x one element at a time: four LDS
-// reads instead of one per binary32 vector).  Same arithmetic either way.
-template <typename T, int G, int NT, bool ALIGNED, int U = kUnrollN, bool SHIFT = false>
+// reads instead of one per binary32 vector).  PAIRS (binary32 rows not
+// aligned, x too large for four copies but not for two): copies 0 and 1,
+// and a row peeled by h reads copy h % 2 as 8-byte pairs.  Same arithmetic
+// either way.
+template <typename T, int G, int NT, bool ALIGNED, int U = kUnrollN, bool SHIFT = false, bool PAIRS = false>
 __global__ __launch_bounds__(NT) void gemv_n_kernel(GemvNArgs<T> a)
 {
     constexpr int NW = NT / kWave, GW = kWave / G;
@@ -114,6 +117,11 @@ __global__ __launch_bounds__(NT) void gemv_n_kernel(GemvNArgs<T> a)
             for (int h = 0; h < W; ++h)
                 if (t >= h) xs[h * a.KC + t - h] = v;
         });
+    } else if constexpr (PAIRS) {
+        stage_to_lds<NT>(a.x + k0, klen, [&](int64_t t, T v) {
+            xs[t] = v;
+            if (t >= 1) xs[a.KC + t - 1] = v;
+        });
     } else {
         stage_to_lds<NT>(a.x + k0, klen, [&](int64_t t, T v) { xs[t] = v; });
     }
@@ -125,7 +133,7 @@ __global__ __launch_bounds__(NT) void gemv_n_kernel(GemvNArgs<T> a)
     const int64_t r1 = min(a.rows, r0 + a.RB);
 
     for (int64_t row = r0 + w * GW + g; row < r1; row += NW * GW) {
-        T t = row_dot<T, G, U, ALIGNED, kGemvNT, true, SHIFT, true>(a.A + row * a.ld + k0, klen, xs, l, a.KC);
+        T t = row_dot<T, G, U, ALIGNED, kGemvNT, true, SHIFT, true, PAIRS>(a.A + row * a.ld + k0, klen, xs, l, a.KC);
         t = group_sum<G>(t);
         if (l == 0) {
             if (a.partial) a.partial[s * a.rows + row] = t;
@@ -563,6 +571,11 @@ GemvNPlan plan_gemv_n(int esize, int64_t rows, int64_t cols, bool unaligned)
     if (unaligned && p.nsplit == 1 && W * round_up(p.KC * esize, 16) <= kShiftedXBytes) {
         p.xcopies = W;
         shape_gemv_n(p, esize, rows);
+    } else if (unaligned && esize == 4 && p.nsplit == 1 && 2 * round_up(p.KC * esize, 16) <= kMaxStagedX) {
+        // binary32: two copies read as 8-byte pairs where four do not fit
+        p.xcopies = 2;
+        p.pairs = true;
+        shape_gemv_n(p, esize, rows);
     }
     p.ws = p.nsplit > 1 ? (size_t)(p.nsplit * rows * esize) : 0;
     return p;
@@ -605,37 +618,37 @@ GemvTPlan plan_gemv_t(int esize, int64_t rows, int64_t cols, int64_t small_split
 
 // ------------------------------------------------------------- launchers ---
 
-template <typename T, int G, int NT, bool AL, int U = kUnrollN, bool SH = false>
+template <typename T, int G, int NT, bool AL, int U = kUnrollN, bool SH = false, bool PR = false>
 static void launch_n(const GemvNArgs<T>& a, dim3 grid, size_t lds, hipStream_t st)
 {
     static const bool attr_set = [] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemv_n_kernel<T, G, NT, AL, U, SH>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemv_n_kernel<T, G, NT, AL, U, SH, PR>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsPerCU);
         return true;
     }();
     (void)attr_set;
-    hipLaunchKernelGGL((gemv_n_kernel<T, G, NT, AL, U, SH>), grid, dim3(NT), lds, st, a);
+    hipLaunchKernelGGL((gemv_n_kernel<T, G, NT, AL, U, SH, PR>), grid, dim3(NT), lds, st, a);
 }
 
-template <typename T, int NT, bool AL, bool SH>
+template <typename T, int NT, bool AL, bool SH, bool PR>
 static bool dispatch_n_g(int G, const GemvNArgs<T>& a, dim3 grid, size_t lds, hipStream_t st)
 {
     switch (G) {
-    case 4: launch_n<T, 4, NT, AL, kUnrollN, SH>(a, grid, lds, st); return true;
-    case 8: launch_n<T, 8, NT, AL, kUnrollN, SH>(a, grid, lds, st); return true;
-    case 16: launch_n<T, 16, NT, AL, kUnrollN, SH>(a, grid, lds, st); return true;
-    case 32: launch_n<T, 32, NT, AL, kUnrollN, SH>(a, grid, lds, st); return true;
-    case 64: launch_n<T, 64, NT, AL, kUnrollN, SH>(a, grid, lds, st); return true;
+    case 4: launch_n<T, 4, NT, AL, kUnrollN, SH, PR>(a, grid, lds, st); return true;
+    case 8: launch_n<T, 8, NT, AL, kUnrollN, SH, PR>(a, grid, lds, st); return true;
+    case 16: launch_n<T, 16, NT, AL, kUnrollN, SH, PR>(a, grid, lds, st); return true;
+    case 32: launch_n<T, 32, NT, AL, kUnrollN, SH, PR>(a, grid, lds, st); return true;
+    case 64: launch_n<T, 64, NT, AL, kUnrollN, SH, PR>(a, grid, lds, st); return true;
     }
     return false;
 }
 
-template <typename T, bool AL, bool SH = false>
+template <typename T, bool AL, bool SH = false, bool PR = false>
 static bool dispatch_n(int NT, int G, const GemvNArgs<T>& a, dim3 grid, size_t lds, hipStream_t st)
 {
     switch (NT) {  // the shapes shape_gemv_n picks (SB_GEMV_N_NT_HUGE goes through launch_n)
-    case 256: return dispatch_n_g<T, 256, AL, SH>(G, a, grid, lds, st);
-    case 512: return dispatch_n_g<T, 512, AL, SH>(G, a, grid, lds, st);
+    case 256: return dispatch_n_g<T, 256, AL, SH, PR>(G, a, grid, lds, st);
+    case 512: return dispatch_n_g<T, 512, AL, SH, PR>(G, a, grid, lds, st);
     }
     return false;
 }
@@ -666,7 +679,17 @@ static sb_status gemv_n_typed(sb_handle* h, int64_t rows, int64_t cols, const T*
     GemvNArgs<T> a{rows, cols, ld, A, x, c, p.nsplit > 1 ? static_cast<T*>(claim_ws(h)) : nullptr, p.KC, p.RB};
     const dim3 grid((unsigned)ceil_div(rows, p.RB), (unsigned)p.nsplit);
     bool ok = true;
-    if (p.lds > 80 * 1024 && p.NT == SB_GEMV_N_NT_HUGE && p.G == 64) {
+    if (p.pairs) {
+        // binary32 rows not aligned, x read as 8-byte pairs from two copies
+        if constexpr (std::is_same<T, float>::value) {
+            if (p.lds > 80 * 1024 && p.NT == SB_GEMV_N_NT_HUGE && p.G == 64)
+                launch_n<T, 64, SB_GEMV_N_NT_HUGE, false, kUnrollNHuge, false, true>(a, grid, p.lds, h->stream);
+            else
+                ok = dispatch_n<T, false, false, true>(p.NT, p.G, a, grid, p.lds, h->stream);
+        } else {
+            ok = false;
+        }
+    } else if (p.lds > 80 * 1024 && p.NT == SB_GEMV_N_NT_HUGE && p.G == 64) {
         // whole rows with x above 80 KiB: more loads in flight per lane
         if (al) launch_n<T, 64, SB_GEMV_N_NT_HUGE, true, kUnrollNHuge>(a, grid, p.lds, h->stream);
         else launch_n<T, 64, SB_GEMV_N_NT_HUGE, false, kUnrollNHuge>(a, grid, p.lds, h->stream);

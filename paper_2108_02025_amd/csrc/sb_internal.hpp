@@ -50,6 +50,7 @@ struct GemvNPlan {
     size_t lds;     // dynamic LDS bytes
     size_t ws;      // workspace bytes (split partial sums)
     int xcopies;    // copies of x in LDS: 1, or 16/esize shifted ones for rows not 16-byte aligned
+    bool pairs;     // binary32 rows not aligned: two copies read as 8-byte pairs (xcopies 2)
 };
 GemvNPlan plan_gemv_n(int esize, int64_t rows, int64_t cols, bool unaligned = false);
 

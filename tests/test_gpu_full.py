@@ -69,6 +69,16 @@ def test_gemv_t_wide_side_by_side(sb, dt, m):
     assert_within(got, ref, bnd, f"{m}x{n} {dt} T")
 
 
+@pytest.mark.parametrize("n", [5121, 8191, 16383])
+def test_gemv_n_f32_unaligned_pairs(sb, n):
+    """Binary32 GEMV-N on packed odd-width rows whose x is too large for four
+    shifted copies but fits two (x read as 8-byte pairs from copy h % 2), and
+    a padded leading dimension that leaves every row start misaligned."""
+    for lda in (None, n + 2):
+        got, ref, bnd = gemv_case(sb, 257, n, 0, 331 + n, "normal", np.float32, lda=lda)
+        assert_within(got, ref, bnd, f"257x{n} lda={lda}")
+
+
 @pytest.mark.parametrize("m,n,seed", SKEWED)
 def test_gemv_skewed_integer_f32(sb, m, n, seed):
     """binary32 integer data in [-7, 7]: partial sums stay below 2^24, so the
